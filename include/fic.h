@@ -1,0 +1,182 @@
+/*
+ * fic.h -- C ABI of the MI355X (gfx950) fractal image encoder.
+ *
+ * The method (Salarian & Miar Naimi, "Modified Fast Fractal Image
+ * Compression Algorithm in spatial domain"): an N x N gray image is cut into
+ * B x B range blocks; each range is matched against a pool of 2B x 2B domain
+ * blocks taken at integer step L, decimated 2 x 2 and seen under 8
+ * rotations/mirrors (Sec. 2); the pool keeps only high-entropy domains
+ * (Sec. 3, Eq 5-6); the contrast s is drawn from a predefined set instead of
+ * Eq 2 (Sec. 2, Sec. 3.2) and the stored offset is the range mean (Sec. 3.3);
+ * a range whose error misses the level threshold splits into four and the
+ * search repeats one quadtree level down (Sec. 2, Fig 1).
+ *
+ * Conventions for every entry point:
+ *  - Image, pool, range and code buffers are DEVICE pointers owned by the
+ *    caller; the library never frees them.  Scalars marked "device" are
+ *    single int32 values in device memory, so consecutive levels chain on the
+ *    stream without a host round trip.
+ *  - stream is a hipStream_t (NULL = the legacy default stream).  All work is
+ *    enqueued on it; no call waits for the device unless stated.
+ *  - A fic_ctx owns scratch memory and is bound to one device and one stream
+ *    at a time; it is not thread safe.
+ *  - Every call returns an int status (FIC_OK or a negative FIC_E_*) and
+ *    validates all sizes on the host before it enqueues anything; on error
+ *    nothing is written.  fic_strerror() names a status.
+ *  - Coordinates are packed xy = (y << 16) | x of a block's top-left pixel.
+ *  - Level order (BFS): level 0 lists every B x B range in raster order;
+ *    level l+1 lists the quarters of every range level l split, in parent
+ *    order, each as top-left, top-right, bottom-left, bottom-right.
+ *
+ * Exact arithmetic (no floating point decides any output):
+ *  n = B^2; r = range pixels; D4 = 2x2 sums of the domain; s = num/den;
+ *  A  = n*sum(D4^2) - (sum D4)^2,    Cr = n*sum(r^2) - (sum r)^2,
+ *  Bx = n*sum(r * T_t(D4)) - sum(r)*sum(D4),
+ *  val = num^2*A - 8*num*den*Bx + 16*den^2*Cr  (= 16 den^2 n E, Eq 1 with
+ *  the Eq 3 offset).  The search returns the lexicographically lowest
+ *  (domain, isometry, s index) of minimal val.
+ */
+#ifndef FIC_H
+#define FIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FIC_OK = 0,
+    FIC_E_INVALID = -1,   /* bad argument (see fic_validate_params) */
+    FIC_E_NOMEM = -2,     /* scratch allocation failed or exceeds the ctx limit */
+    FIC_E_HIP = -3,       /* a HIP runtime call failed (no device, launch error) */
+    FIC_E_CAPACITY = -4,  /* a caller buffer is smaller than the worst case */
+    FIC_E_ARCH = -5       /* the device is not gfx950 */
+};
+
+enum { FIC_ENGINE_MFMA = 0, FIC_ENGINE_FP32 = 1 };
+enum { FIC_MAX_LEVELS = 4, FIC_MAX_S = 32 };
+
+typedef struct fic_ctx fic_ctx;
+typedef void *fic_stream;            /* hipStream_t */
+
+typedef struct { int32_t num, den; } fic_ratio;
+
+/* An 8-bit gray image in device memory, row pitch in bytes. */
+typedef struct { const uint8_t *pix; int32_t width, height, pitch; } fic_image;
+
+/* Encoder parameters (Sec. 2-3).  Level l uses B_l = block0 >> l. */
+typedef struct {
+    int32_t levels;                  /* 1..4 quadtree steps (2-bit step field, Sec. 3.3) */
+    int32_t block0;                  /* B at level 0, power of two, B_last >= 2, block0 <= 32 */
+    int32_t step[FIC_MAX_LEVELS];    /* domain step L per level, >= 1 (Sec. 2) */
+    fic_ratio pool_pct;              /* drop the ceil(p*Nd) lowest-entropy candidates, 0 <= p < 1 */
+    int32_t pool_max;                /* 0 = no cap; else keep at most DN highest-entropy (Sec. 3.2.1) */
+    int32_t s_count[FIC_MAX_LEVELS]; /* contrast set per level: s_k = s_num[l][k] / s_den[l] */
+    int32_t s_den[FIC_MAX_LEVELS];   /* 1..1024 */
+    int32_t s_num[FIC_MAX_LEVELS][FIC_MAX_S]; /* strictly ascending, 0 <= num <= den */
+    fic_ratio split_rms[FIC_MAX_LEVELS]; /* split iff RMS error > num/den; den 1..16; unused at the last level */
+    int32_t engine;                  /* FIC_ENGINE_MFMA (default) or FIC_ENGINE_FP32 */
+} fic_params;
+
+/* Domain pool of one level (Sec. 3.3: the domain address is the list index).
+ * Entries are in raster order of xy.  key = integer entropy key G (larger =
+ * lower entropy), sum4 = sum of the 4B^2 raw pixels, a = A above. */
+typedef struct {
+    int32_t capacity;                /* entries the arrays can hold */
+    int32_t *count;                  /* device: entries written */
+    uint32_t *xy;
+    int64_t *key;
+    uint32_t *sum4;
+    int64_t *a;
+} fic_pool;
+
+/* Codes of one level, one entry per range of that level (BFS order).
+ * err = val_q = 16 den^2 n E_q, the error with the stored 8-bit offset. */
+typedef struct {
+    int32_t capacity;
+    int32_t *count;                  /* device: ranges of this level */
+    uint32_t *xy;                    /* range top-left */
+    uint8_t *split;                  /* 1 = split into four at the next level */
+    uint32_t *domain;                /* index into the level's pool */
+    uint8_t *iso;                    /* t = 4m + r: r clockwise quarter turns, then mirror if m */
+    uint8_t *s_idx;                  /* index into the level's contrast set */
+    uint8_t *offset;                 /* round-half-up of the range mean (Sec. 3.3) */
+    int64_t *err;
+} fic_level_codes;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Binds device `device`; fails with FIC_E_ARCH unless it is gfx950 and with
+ * FIC_E_HIP when no device is present. */
+int fic_ctx_create(fic_ctx **ctx, int device);
+void fic_ctx_destroy(fic_ctx *ctx);
+/* Caps the scratch the ctx may hold (bytes, 0 = unlimited); a call that
+ * needs more fails with FIC_E_NOMEM before enqueuing anything. */
+int fic_ctx_set_scratch_limit(fic_ctx *ctx, int64_t bytes);
+const char *fic_strerror(int status);
+
+/* ---- host-only helpers (no device needed) ----------------------------- */
+
+/* FIC_OK if params are usable for a width x height image:
+ * levels in 1..4; block0 a power of two <= 32 with block0 >> (levels-1) >= 2;
+ * width, height multiples of block0 and >= 2*block0, both <= 65535;
+ * step >= 1; 0 <= pool_pct < 1 with den >= 1; pool_max >= 0;
+ * per level 1 <= s_count <= 32, 1 <= s_den <= 1024, nums strictly ascending
+ * in [0, s_den]; split_rms num >= 0, den in 1..16; engine known. */
+int fic_validate_params(const fic_params *p, int32_t width, int32_t height);
+
+/* Worst-case pool entries and ranges per level (candidates, and all ranges
+ * split) for a width x height image; arrays of FIC_MAX_LEVELS entries. */
+int fic_query_capacity(const fic_params *p, int32_t width, int32_t height,
+                       int64_t *pool_cap, int64_t *range_cap);
+
+/* Copies the first n (<= 4097) entries of the entropy key table
+ * T[q] = q * sum over prime powers p^e || q of e * round(ln p * 2^32), so the
+ * key of a block is G = sum over gray levels of T[count]. */
+int fic_entropy_table(int64_t *out, int32_t n);
+
+/* ---- encoder and decoder ---------------------------------------------- */
+
+/* Sec. 3, Eq 5-6 and Sec. 3.2.1: the domain pool for range size B at step L.
+ * Candidates are all 2B x 2B blocks at multiples of L, raster order.  With
+ * c = ceil(pct*Nd) > 0, the c-th largest key is the threshold t and the pool
+ * keeps keys < t (entropy strictly greater); if none, it keeps the keys equal
+ * to the minimum.  pool_max > 0 then keeps the pool_max smallest (key, index)
+ * pairs.  out->capacity must be >= Nd. */
+int fic_build_domain_pool(fic_ctx *ctx, const fic_image *img, int32_t B, int32_t L,
+                          fic_ratio pct, int32_t pool_max, fic_pool *out, fic_stream stream);
+
+/* One quadtree step (Sec. 2): searches the *n_ranges (device) ranges
+ * ranges_xy against every pool domain, 8 isometries and s_count contrasts,
+ * writes one code per range to out (out->xy copies ranges_xy), and appends the
+ * four children of every split range to children_xy with their number in
+ * *n_children (device).  Split iff !is_last and RMS(E_q) > split_rms.
+ * range_capacity bounds *n_ranges; out->capacity >= range_capacity;
+ * children_xy may be NULL when is_last, else it holds 4*range_capacity. */
+int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool,
+                     const uint32_t *ranges_xy, const int32_t *n_ranges, int32_t range_capacity,
+                     int32_t B, const int32_t *s_num, int32_t s_count, int32_t s_den,
+                     fic_ratio split_rms, int32_t is_last, int32_t engine,
+                     fic_level_codes *out, uint32_t *children_xy, int32_t *n_children,
+                     fic_stream stream);
+
+/* Whole encoder for n_images images with one parameter set: pools and codes
+ * are arrays of n_images*levels entries, image-major.  codes[i*levels+l].xy
+ * and .count hold level l's ranges; capacities as fic_query_capacity. */
+int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_params *p,
+               fic_pool *pools, fic_level_codes *codes, fic_stream stream);
+
+/* Decoder (Sec. 1-2): X0 = every accepted range filled with its offset; each
+ * iteration rebuilds every accepted range from the previous image,
+ * pixel = clamp(O + floor(s*(T_t(D4)/4 - mean(D4)/4) + 1/2), 0, 255).
+ * pools/codes as written by fic_encode for one image; out is width x height,
+ * pitch width (device). */
+int fic_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes,
+               int32_t width, int32_t height, int32_t iterations, uint8_t *out, fic_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIC_H */

@@ -1,0 +1,156 @@
+// Internal declarations of the gfx950 fractal encoder library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fic.h"
+
+namespace fic {
+
+// ---------------------------------------------------------------- constants
+constexpr int kWave = 64;
+constexpr int kMaxLevels = FIC_MAX_LEVELS;
+constexpr int kMaxS = FIC_MAX_S;
+constexpr int kTableSize = 4097;       // entropy table entries, q = 0..4096
+constexpr int kScanBlock = 1024;       // items per block in stable compaction
+constexpr int kDomTile = 16;           // domains per MFMA column tile
+
+// ---------------------------------------------------------------- small PODs
+// Contrast set of one level, passed by value to kernels.
+struct SSet {
+    int32_t count, den;
+    int32_t num[kMaxS];
+};
+
+// Per-range values prepared for the search kernels.
+// The prune test compares the isometry-max of C' = sum (view-128)(dom-128)
+// with  tn*sqrtA[p] - bn*Sd4[p] - an  (see search_common.h).
+struct RInfo {
+    int64_t cr;      // n*sum(r^2) - (sum r)^2
+    int32_t sr;      // sum r
+    float bn;        // (128 n - Sr) / n
+    float an;        // (512 n Sr - 65536 n^2) / n + margin
+    float pad;
+};
+
+// One search partial: the best code of a range within one domain chunk.
+struct Partial {
+    int64_t val;
+    int32_t p;       // -1 when the chunk held no domain
+    int32_t k;
+};
+
+// Radix-select state kept in device memory.
+struct SelState {
+    unsigned long long key_prefix;
+    uint32_t idx_prefix;
+    int32_t remaining;
+    int32_t all;            // 1 = fewer candidates than requested: keep every one
+    int32_t pad[3];
+    uint32_t hist[256];
+};
+
+// Thresholds deciding pool membership, produced on the device.
+struct PoolSel {
+    SelState pct;           // c-th largest key (drop threshold)
+    SelState cap;           // pool_max-th smallest (key, index)
+    unsigned long long gmin;
+};
+
+// ---------------------------------------------------------------- isometries
+// out[y][x] = in[sy][sx] for isometry t = 4m + r of a B x B block:
+// r clockwise quarter turns, then a left-right mirror when m = 1.
+__host__ __device__ inline void iso_src(int t, int B, int y, int x, int &sy, int &sx) {
+    const int e = B - 1;
+    switch (t) {
+        case 0: sy = y;     sx = x;     break;
+        case 1: sy = e - x; sx = y;     break;
+        case 2: sy = e - y; sx = e - x; break;
+        case 3: sy = x;     sx = e - y; break;
+        case 4: sy = y;     sx = e - x; break;
+        case 5: sy = x;     sx = y;     break;
+        case 6: sy = e - y; sx = x;     break;
+        default: sy = e - x; sx = e - y; break;
+    }
+}
+
+// Inverse isometry: quarter turns 1 and 3 swap, every other one is an involution.
+__host__ __device__ inline int iso_inv(int t) { return t == 1 ? 3 : (t == 3 ? 1 : t); }
+
+// ---------------------------------------------------------------- scratch
+// Scratch slots owned by a context; each grows on demand.
+enum Slot {
+    S_KEYS, S_SEL, S_BLOCKSUM, S_BLOCKOFF, S_RINFO, S_AFRAG, S_BFRAG, S_DINFO, S_PARTIAL,
+    S_VF32, S_DF32, S_DEC0, S_DEC1, S_RANGES0, S_RANGES1, S_COUNTS, S_NUM_SLOTS
+};
+
+struct Buf { void *ptr; size_t bytes; };
+
+}  // namespace fic
+
+struct fic_ctx {
+    int device;
+    int64_t limit;               // 0 = unlimited
+    fic::Buf slot[fic::S_NUM_SLOTS];
+    int64_t *table;              // device entropy table
+};
+
+namespace fic {
+
+int reserve(fic_ctx *ctx, const size_t *bytes);   // bytes[S_NUM_SLOTS], 0 = untouched
+inline void *sp(fic_ctx *ctx, Slot s) { return ctx->slot[s].ptr; }
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipError_t of the launch; geometry arguments are host values
+// (capacities), live counts are read by the kernels from device memory.
+
+// pool
+hipError_t launch_sel_init(PoolSel *sel, int64_t c, int pool_max, hipStream_t st);
+hipError_t launch_pool_keys(const uint8_t *img, int pitch, int nx, int nd, int L, int dsz, const int64_t *table,
+                            int64_t *keys, PoolSel *sel, hipStream_t st);
+hipError_t launch_pool_select(const int64_t *keys, int nd, int64_t c, int pool_max, PoolSel *sel, hipStream_t st);
+hipError_t launch_pool_compact(const int64_t *keys, int nd, int nx, int L, int64_t c, int pool_max,
+                               const PoolSel *sel, int *blocksum, int *blockoff, fic_pool *pool,
+                               hipStream_t st);
+hipError_t launch_pool_moments(const uint8_t *img, int pitch, int B, int cap, fic_pool *pool, hipStream_t st);
+
+// levels
+hipError_t launch_level0(int nx, int ny, int B, uint32_t *xy, int32_t *count, hipStream_t st);
+hipError_t launch_range_info(const uint8_t *img, int pitch, int B, const uint32_t *xy, const int32_t *n,
+                             int cap, RInfo *ri, hipStream_t st);
+hipError_t launch_finalize(const uint8_t *img, int pitch, int B, const uint32_t *xy, const int32_t *n, int cap,
+                           const fic_pool *pool, const Partial *part, int nchunk, SSet ss, fic_ratio rms,
+                           int is_last, fic_level_codes *out, hipStream_t st);
+hipError_t launch_children(const fic_level_codes *codes, int cap, int B, int *blocksum, int *blockoff,
+                           uint32_t *children, int32_t *n_children, hipStream_t st);
+
+// MFMA engine
+bool mfma_supported(int B);
+void mfma_geometry(int B, int range_cap, int pool_cap, int *ranges_per_wg, int *nchunk, int *tiles_per_chunk);
+int mfma_quads_padded(int B, int range_cap);
+hipError_t launch_mfma_prep(const uint8_t *img, int pitch, int B, const uint32_t *rxy, const int32_t *nr,
+                            int range_cap, const fic_pool *pool, int pool_cap, void *afrag, void *bfrag,
+                            float2 *dinfo, hipStream_t st);
+hipError_t launch_mfma_search(int B, const void *afrag, const void *bfrag, const float2 *dinfo,
+                              const RInfo *ri, const int32_t *nr, int range_cap, const fic_pool *pool,
+                              int pool_cap, SSet ss, Partial *part, hipStream_t st);
+
+// FP32 engine
+void fp32_geometry(int B, int range_cap, int pool_cap, int *nchunk, int *tiles_per_chunk);
+int fp32_rpad(int range_cap);
+int fp32_ppad(int pool_cap);
+hipError_t launch_fp32_prep(const uint8_t *img, int pitch, int B, const uint32_t *rxy, const int32_t *nr,
+                            int range_cap, const fic_pool *pool, int pool_cap, float *vf, float *df,
+                            float2 *dinfo, hipStream_t st);
+hipError_t launch_fp32_search(int B, const float *vf, const float *df, const float2 *dinfo, const RInfo *ri,
+                              const int32_t *nr, int range_cap, const fic_pool *pool, int pool_cap, SSet ss,
+                              Partial *part, hipStream_t st);
+
+// decoder
+hipError_t launch_decode_init(int B, const fic_level_codes *codes, int cap, uint8_t *img, int pitch,
+                              hipStream_t st);
+hipError_t launch_decode_iter(int B, const fic_level_codes *codes, int cap, const fic_pool *pool, SSet ss,
+                              const uint8_t *cur, uint8_t *nxt, int pitch, hipStream_t st);
+
+}  // namespace fic

@@ -1,0 +1,215 @@
+// Plain per-pixel FP32 search engine: the baseline the MFMA engine is
+// measured against, and the engine for range sizes the MFMA tiling does not
+// cover (B = 2, B = 32).
+//
+// Per (range, isometry, domain) it sums (view_j - 128)(D4_j - 512) over the
+// B^2 decimated cells in FP32 -- the same integer C' as the MFMA engine.
+// Every product is an integer of magnitude <= 2^16 and every partial sum of
+// up to 256 cells stays below 2^24, so FP32 is exact; for B = 32 the sums are
+// flushed to int32 every 256 cells.  LDS-tiled: 8 ranges x 128 domains per
+// 256-thread block, each thread 8 isometries x 4 domains in registers.
+//
+// Layouts: views vf[(j * Rpad + r) * 8 + t], domains df[j * Ppad + p], with j
+// the decimated cell (row-major) and Rpad, Ppad padded to the tile sizes.
+#include "fic_internal.h"
+#include "search_common.h"
+
+namespace fic {
+
+constexpr int kF32Ranges = 8;
+constexpr int kF32Doms = 128;
+
+void fp32_geometry(int B, int range_cap, int pool_cap, int *nchunk, int *tiles_per_chunk) {
+    (void)B;
+    const int ntiles = (pool_cap + kF32Doms - 1) / kF32Doms;
+    const int nrg = (range_cap + kF32Ranges - 1) / kF32Ranges;
+    int nc = (4096 + nrg - 1) / nrg;
+    nc = max(1, min(nc, max(1, ntiles / 4)));
+    nc = min(nc, 4096);
+    *nchunk = nc;
+    *tiles_per_chunk = (ntiles + nc - 1) / nc;
+}
+
+int fp32_rpad(int range_cap) { return (range_cap + kF32Ranges - 1) / kF32Ranges * kF32Ranges; }
+int fp32_ppad(int pool_cap) { return (pool_cap + kF32Doms - 1) / kF32Doms * kF32Doms; }
+
+__global__ __launch_bounds__(256) void k_fp32_views(const uint8_t *__restrict__ img, int pitch, int B,
+                                                    const uint32_t *__restrict__ rxy, const int32_t *nr, int cap,
+                                                    int Rpad, float *__restrict__ vf) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int n = B * B;
+    if (e >= n * Rpad) return;
+    const int j = e / Rpad, r = e - j * Rpad;
+    const int cy = j / B, cx = j - cy * B;
+    const bool valid = r < min(*nr, cap);
+    int x0 = 0, y0 = 0;
+    if (valid) {
+        const uint32_t v = rxy[r];
+        x0 = v & 0xffff;
+        y0 = v >> 16;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        float val = 0.f;
+        if (valid) {
+            int sy, sx;
+            iso_src(iso_inv(t), B, cy, cx, sy, sx);
+            val = (float)((int)img[(size_t)(y0 + sy) * pitch + x0 + sx] - 128);
+        }
+        vf[(size_t)e * 8 + t] = val;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fp32_doms(const uint8_t *__restrict__ img, int pitch, int B,
+                                                   const uint32_t *__restrict__ pxy, const int32_t *np, int cap,
+                                                   int Ppad, const uint32_t *__restrict__ sum4,
+                                                   const int64_t *__restrict__ pa, float *__restrict__ df,
+                                                   float2 *__restrict__ dinfo) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int n = B * B;
+    if (e >= n * Ppad) return;
+    const int j = e / Ppad, p = e - j * Ppad;
+    const bool valid = p < min(*np, cap);
+    float val = 0.f;
+    if (valid) {
+        const uint32_t v = pxy[p];
+        const int cy = j / B, cx = j - cy * B;
+        const uint8_t *q = img + (size_t)((v >> 16) + 2 * cy) * pitch + (v & 0xffff) + 2 * cx;
+        val = (float)(q[0] + q[1] + q[pitch] + q[pitch + 1] - 512);
+    }
+    df[e] = val;
+    if (j == 0) dinfo[p] = valid ? make_float2((float)sum4[p], sqrt_down((double)pa[p])) : make_float2(0.f, 0.f);
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_fp32_search(const float *__restrict__ vf, const float *__restrict__ df,
+                                                     const float2 *__restrict__ dinfo, const RInfo *__restrict__ ri,
+                                                     const int32_t *nr, int range_cap, int Rpad, const int32_t *np,
+                                                     int pool_cap, int Ppad, const uint32_t *__restrict__ sum4,
+                                                     const int64_t *__restrict__ pa, SSet ss, int tiles_per_chunk,
+                                                     int nchunk, Partial *__restrict__ part) {
+    constexpr int n = B * B;
+    constexpr int KC = n < 16 ? n : 16;
+    constexpr int NKC = n / KC;
+    __shared__ __align__(16) float Vs[KC][kF32Ranges * 8];
+    __shared__ __align__(16) float Ds[KC][kF32Doms];
+    const int tid = threadIdx.x, tr = tid >> 5, td = tid & 31;
+    const int R = min(*nr, range_cap), P = min(*np, pool_cap);
+    const int rg = blockIdx.x;
+    if (rg * kF32Ranges >= R) return;  // uniform over the block
+    const int r = rg * kF32Ranges + tr;
+    const bool rvalid = r < R;
+    const int chunk = blockIdx.y;
+    const int ntiles = (P + kF32Doms - 1) / kF32Doms;
+    const int t0 = chunk * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
+    const RInfo x = ri[rvalid ? r : rg * kF32Ranges];
+    const float bn = x.bn, an = x.an;
+    float tn = -1e30f;
+    int64_t best = INT64_MAX;
+    int bp = INT32_MAX, bk = 0;
+
+    for (int tile = t0; tile < t1; ++tile) {
+        float acc[8][4];
+        int iacc[8][4];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[t][j] = 0.f;
+                iacc[t][j] = 0;
+            }
+        for (int kc = 0; kc < NKC; ++kc) {
+            __syncthreads();
+            for (int e = tid; e < KC * 64; e += 256) {
+                const int kk = e >> 6, o = e & 63;
+                Vs[kk][o] = vf[((size_t)(kc * KC + kk) * Rpad + rg * kF32Ranges) * 8 + o];
+            }
+            for (int e = tid; e < KC * kF32Doms; e += 256) {
+                const int kk = e >> 7, dd = e & 127;
+                Ds[kk][dd] = df[(size_t)(kc * KC + kk) * Ppad + tile * kF32Doms + dd];
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int kk = 0; kk < KC; ++kk) {
+                const float4 va = *(const float4 *)&Vs[kk][tr * 8];
+                const float4 vb = *(const float4 *)&Vs[kk][tr * 8 + 4];
+                const float4 d = *(const float4 *)&Ds[kk][td * 4];
+                const float v[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+                const float dd[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[t][j] = fmaf(v[t], dd[j], acc[t][j]);
+            }
+            if (n > 256 && ((kc + 1) % 16 == 0 || kc == NKC - 1)) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        iacc[t][j] += (int)acc[t][j];
+                        acc[t][j] = 0.f;
+                    }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int c[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) c[t] = n > 256 ? iacc[t][j] : (int)acc[t][j];
+            const int m = max8(c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7]);
+            const int p = tile * kF32Doms + td * 4 + j;
+            const float2 di = dinfo[p];
+            const float rhs = fmaf(tn, di.y, fmaf(-bn, di.x, -an));
+            if (p < P && rvalid && (float)m > rhs) confirm_pair(m, p, r, n, ri, sum4, pa, ss, best, bp, bk, tn);
+        }
+    }
+    group_min<32>(best, bp, bk);
+    if (td == 0 && rvalid) {
+        Partial o;
+        o.val = best;
+        o.p = bp == INT32_MAX ? -1 : bp;
+        o.k = bk;
+        part[(size_t)r * nchunk + chunk] = o;
+    }
+}
+
+hipError_t launch_fp32_prep(const uint8_t *img, int pitch, int B, const uint32_t *rxy, const int32_t *nr,
+                            int range_cap, const fic_pool *pool, int pool_cap, float *vf, float *df, float2 *dinfo,
+                            hipStream_t st) {
+    const int n = B * B, Rpad = fp32_rpad(range_cap), Ppad = fp32_ppad(pool_cap);
+    const long nv = (long)n * Rpad, nd = (long)n * Ppad;
+    if (nv > 0) k_fp32_views<<<(unsigned)((nv + 255) / 256), 256, 0, st>>>(img, pitch, B, rxy, nr, range_cap, Rpad, vf);
+    if (nd > 0)
+        k_fp32_doms<<<(unsigned)((nd + 255) / 256), 256, 0, st>>>(img, pitch, B, pool->xy, pool->count, pool_cap,
+                                                                  Ppad, pool->sum4, pool->a, df, dinfo);
+    return hipGetLastError();
+}
+
+template <int B>
+static void fp32_launch_t(dim3 grid, hipStream_t st, const float *vf, const float *df, const float2 *dinfo,
+                          const RInfo *ri, const int32_t *nr, int range_cap, const fic_pool *pool, int pool_cap,
+                          SSet ss, int tpc, int nchunk, Partial *part) {
+    k_fp32_search<B><<<grid, 256, 0, st>>>(vf, df, dinfo, ri, nr, range_cap, fp32_rpad(range_cap), pool->count,
+                                           pool_cap, fp32_ppad(pool_cap), pool->sum4, pool->a, ss, tpc, nchunk,
+                                           part);
+}
+
+hipError_t launch_fp32_search(int B, const float *vf, const float *df, const float2 *dinfo, const RInfo *ri,
+                              const int32_t *nr, int range_cap, const fic_pool *pool, int pool_cap, SSet ss,
+                              Partial *part, hipStream_t st) {
+    int nchunk, tpc;
+    fp32_geometry(B, range_cap, pool_cap, &nchunk, &tpc);
+    const dim3 grid((range_cap + kF32Ranges - 1) / kF32Ranges, nchunk);
+    if (grid.x == 0) return hipSuccess;
+    switch (B) {
+        case 2: fp32_launch_t<2>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
+        case 4: fp32_launch_t<4>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
+        case 8: fp32_launch_t<8>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
+        case 16: fp32_launch_t<16>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
+        case 32: fp32_launch_t<32>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fic

@@ -1,0 +1,310 @@
+"""Python binding of libfic.so (the gfx950 fractal encoder C ABI).
+
+Argument marshalling only: every step of the encoder and decoder runs in
+the library's HIP kernels.  PyTorch provides device memory and the stream.
+The entry points keep the C names: build_domain_pool, encode_level, encode,
+decode (see include/fic.h for the contract of each).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfic.so")
+
+FIC_OK, FIC_E_INVALID, FIC_E_NOMEM, FIC_E_HIP, FIC_E_CAPACITY, FIC_E_ARCH = 0, -1, -2, -3, -4, -5
+ENGINE_MFMA, ENGINE_FP32 = 0, 1
+MAX_LEVELS, MAX_S = 4, 32
+
+i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+
+
+class FicError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (where, strerror(status), status))
+
+
+class Ratio(ctypes.Structure):
+    _fields_ = [("num", i32), ("den", i32)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("pix", vp), ("width", i32), ("height", i32), ("pitch", i32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("levels", i32), ("block0", i32), ("step", i32 * MAX_LEVELS), ("pool_pct", Ratio),
+                ("pool_max", i32), ("s_count", i32 * MAX_LEVELS), ("s_den", i32 * MAX_LEVELS),
+                ("s_num", (i32 * MAX_S) * MAX_LEVELS), ("split_rms", Ratio * MAX_LEVELS), ("engine", i32)]
+
+
+class PoolC(ctypes.Structure):
+    _fields_ = [("capacity", i32), ("count", vp), ("xy", vp), ("key", vp), ("sum4", vp), ("a", vp)]
+
+
+class CodesC(ctypes.Structure):
+    _fields_ = [("capacity", i32), ("count", vp), ("xy", vp), ("split", vp), ("domain", vp), ("iso", vp),
+                ("s_idx", vp), ("offset", vp), ("err", vp)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The HIP library; raises when it has not been built (no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfic.so is not built (run __graft_entry__.build()); the encoder has no "
+                              "other implementation")
+        L = ctypes.CDLL(LIB_PATH)
+        L.fic_strerror.restype = ctypes.c_char_p
+        L.fic_strerror.argtypes = [i32]
+        L.fic_ctx_create.argtypes = [ctypes.POINTER(vp), i32]
+        L.fic_ctx_destroy.argtypes = [vp]
+        L.fic_ctx_destroy.restype = None
+        L.fic_ctx_set_scratch_limit.argtypes = [vp, i64]
+        L.fic_validate_params.argtypes = [ctypes.POINTER(Params), i32, i32]
+        L.fic_query_capacity.argtypes = [ctypes.POINTER(Params), i32, i32, vp, vp]
+        L.fic_entropy_table.argtypes = [vp, i32]
+        L.fic_build_domain_pool.argtypes = [vp, ctypes.POINTER(Image), i32, i32, Ratio, i32, ctypes.POINTER(PoolC),
+                                            vp]
+        L.fic_encode_level.argtypes = [vp, ctypes.POINTER(Image), ctypes.POINTER(PoolC), vp, vp, i32, i32, vp, i32,
+                                       i32, Ratio, i32, i32, ctypes.POINTER(CodesC), vp, vp, vp]
+        L.fic_encode.argtypes = [vp, ctypes.POINTER(Image), i32, ctypes.POINTER(Params), ctypes.POINTER(PoolC),
+                                 ctypes.POINTER(CodesC), vp]
+        L.fic_decode.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(PoolC), ctypes.POINTER(CodesC), i32, i32,
+                                 i32, vp, vp]
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("fic_ctx_create", "fic_ctx_destroy", "fic_ctx_set_scratch_limit", "fic_strerror",
+            "fic_validate_params", "fic_query_capacity", "fic_entropy_table", "fic_build_domain_pool",
+            "fic_encode_level", "fic_encode", "fic_decode")
+
+
+def strerror(status: int) -> str:
+    return lib().fic_strerror(status).decode()
+
+
+def _check(status: int, where: str):
+    if status != FIC_OK:
+        raise FicError(status, where)
+
+
+# ---------------------------------------------------------------- parameters
+def make_params(levels, block0=None, pct=(3, 10), pool_max=0, s_num=tuple(range(17)), s_den=16,
+                split_rms=(8, 1), engine=ENGINE_MFMA) -> Params:
+    """levels: list of (B, L).  s_num / s_den / split_rms: one value for all
+    levels or one per level."""
+    p = Params()
+    nl = len(levels)
+    p.levels = nl
+    p.block0 = block0 if block0 is not None else levels[0][0]
+    per_level_s = isinstance(s_num[0], (list, tuple, np.ndarray))
+    for l, (B, L) in enumerate(levels):
+        if B != p.block0 >> l:
+            raise ValueError("level sizes must halve: %r" % (levels,))
+        p.step[l] = L
+        sn = s_num[l] if per_level_s else s_num
+        sd = s_den[l] if isinstance(s_den, (list, tuple)) else s_den
+        rm = split_rms[l] if isinstance(split_rms[0], (list, tuple)) else split_rms
+        p.s_count[l] = len(sn)
+        p.s_den[l] = sd
+        for k, v in enumerate(sn):
+            p.s_num[l][k] = int(v)
+        p.split_rms[l] = Ratio(int(rm[0]), int(rm[1]))
+    p.pool_pct = Ratio(int(pct[0]), int(pct[1]))
+    p.pool_max = pool_max
+    p.engine = engine
+    return p
+
+
+def validate_params(p: Params, width: int, height: int) -> int:
+    return lib().fic_validate_params(ctypes.byref(p), width, height)
+
+
+def query_capacity(p: Params, width: int, height: int):
+    pc = np.zeros(MAX_LEVELS, np.int64)
+    rc = np.zeros(MAX_LEVELS, np.int64)
+    _check(lib().fic_query_capacity(ctypes.byref(p), width, height, pc.ctypes.data, rc.ctypes.data),
+           "fic_query_capacity")
+    return pc[:p.levels].tolist(), rc[:p.levels].tolist()
+
+
+def entropy_table() -> np.ndarray:
+    out = np.zeros(4097, np.int64)
+    _check(lib().fic_entropy_table(out.ctypes.data, 4097), "fic_entropy_table")
+    return out
+
+
+# ---------------------------------------------------------------- device buffers
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return vp(_torch().cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Pool:
+    count: object
+    xy: object
+    key: object
+    sum4: object
+    a: object
+
+    @staticmethod
+    def alloc(cap: int, device) -> "Pool":
+        t = _torch()
+        return Pool(t.zeros(1, dtype=t.int32, device=device), t.empty(cap, dtype=t.int32, device=device),
+                    t.empty(cap, dtype=t.int64, device=device), t.empty(cap, dtype=t.int32, device=device),
+                    t.empty(cap, dtype=t.int64, device=device))
+
+    def c(self) -> PoolC:
+        return PoolC(self.xy.numel(), self.count.data_ptr(), self.xy.data_ptr(), self.key.data_ptr(),
+                     self.sum4.data_ptr(), self.a.data_ptr())
+
+    def numpy(self) -> dict:
+        n = int(self.count.item())
+        return {"xy": self.xy[:n].cpu().numpy().view(np.uint32), "key": self.key[:n].cpu().numpy(),
+                "sum4": self.sum4[:n].cpu().numpy().view(np.uint32), "a": self.a[:n].cpu().numpy()}
+
+
+@dataclass
+class Codes:
+    count: object
+    xy: object
+    split: object
+    domain: object
+    iso: object
+    s_idx: object
+    offset: object
+    err: object
+
+    @staticmethod
+    def alloc(cap: int, device) -> "Codes":
+        t = _torch()
+        e = lambda dt: t.empty(max(cap, 1), dtype=dt, device=device)
+        return Codes(t.zeros(1, dtype=t.int32, device=device), e(t.int32), e(t.uint8), e(t.int32), e(t.uint8),
+                     e(t.uint8), e(t.uint8), e(t.int64))
+
+    def c(self) -> CodesC:
+        return CodesC(self.xy.numel(), self.count.data_ptr(), self.xy.data_ptr(), self.split.data_ptr(),
+                      self.domain.data_ptr(), self.iso.data_ptr(), self.s_idx.data_ptr(), self.offset.data_ptr(),
+                      self.err.data_ptr())
+
+    def numpy(self) -> dict:
+        n = int(self.count.item())
+        return {"xy": self.xy[:n].cpu().numpy().view(np.uint32), "split": self.split[:n].cpu().numpy(),
+                "domain": self.domain[:n].cpu().numpy().view(np.uint32), "iso": self.iso[:n].cpu().numpy(),
+                "s_idx": self.s_idx[:n].cpu().numpy(), "offset": self.offset[:n].cpu().numpy(),
+                "err": self.err[:n].cpu().numpy()}
+
+
+def _image(img) -> Image:
+    if img.dtype != _torch().uint8 or img.dim() != 2 or not img.is_cuda:
+        raise ValueError("image must be a 2-D uint8 CUDA tensor")
+    if img.stride(1) != 1:
+        raise ValueError("image rows must be contiguous")
+    return Image(img.data_ptr(), img.shape[1], img.shape[0], img.stride(0))
+
+
+class Context:
+    """Owns a fic_ctx (scratch memory) on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = vp()
+        _check(lib().fic_ctx_create(ctypes.byref(h), device), "fic_ctx_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().fic_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_scratch_limit(self, nbytes: int):
+        _check(lib().fic_ctx_set_scratch_limit(self.h, nbytes), "fic_ctx_set_scratch_limit")
+
+    # -------------------------------------------------------------- entry points
+    def build_domain_pool(self, img, B: int, L: int, pct=(3, 10), pool_max: int = 0, pool: Pool | None = None) -> Pool:
+        H, W = img.shape
+        nd = ((W - 2 * B) // L + 1) * ((H - 2 * B) // L + 1)
+        cap = min(nd, pool_max) if pool_max > 0 else nd
+        pool = pool or Pool.alloc(cap, img.device)
+        pc = pool.c()
+        _check(lib().fic_build_domain_pool(self.h, ctypes.byref(_image(img)), B, L, Ratio(*pct), pool_max,
+                                           ctypes.byref(pc), _stream()), "fic_build_domain_pool")
+        return pool
+
+    def encode_level(self, img, pool: Pool, ranges_xy, n_ranges, range_cap: int, B: int, s_num, s_den: int,
+                     split_rms=(8, 1), is_last: bool = False, engine: int = ENGINE_MFMA):
+        """ranges_xy: int32 CUDA tensor (packed y<<16|x); n_ranges: 1-element int32
+        CUDA tensor.  Returns (codes, children_xy, n_children)."""
+        t = _torch()
+        dev = img.device
+        codes = Codes.alloc(range_cap, dev)
+        children = None if is_last else t.empty(max(4 * range_cap, 1), dtype=t.int32, device=dev)
+        nch = None if is_last else t.zeros(1, dtype=t.int32, device=dev)
+        sn = np.ascontiguousarray(s_num, np.int32)
+        cc = codes.c()
+        pc = pool.c()
+        _check(lib().fic_encode_level(self.h, ctypes.byref(_image(img)), ctypes.byref(pc), ranges_xy.data_ptr(),
+                                      n_ranges.data_ptr(), range_cap, B, sn.ctypes.data, len(sn), s_den,
+                                      Ratio(*split_rms), int(is_last), engine, ctypes.byref(cc),
+                                      None if is_last else children.data_ptr(),
+                                      None if is_last else nch.data_ptr(), _stream()), "fic_encode_level")
+        return codes, children, nch
+
+    def alloc_encode(self, shapes, p: Params, device):
+        """Pools and codes for images of the given (width, height) shapes."""
+        out = []
+        for (W, H) in shapes:
+            pc, rc = query_capacity(p, W, H)
+            out.append(([Pool.alloc(int(c), device) for c in pc], [Codes.alloc(int(c), device) for c in rc]))
+        return out
+
+    def encode(self, images, p: Params, bufs=None):
+        """images: list of 2-D uint8 CUDA tensors.  Returns, per image, the
+        lists (pools, codes) of device buffers, one entry per level."""
+        if bufs is None:
+            bufs = self.alloc_encode([(im.shape[1], im.shape[0]) for im in images], p, images[0].device)
+        n = len(images)
+        imgs = (Image * n)(*[_image(im) for im in images])
+        pools = (PoolC * (n * p.levels))(*[pl.c() for (pls, _) in bufs for pl in pls])
+        codes = (CodesC * (n * p.levels))(*[cd.c() for (_, cds) in bufs for cd in cds])
+        _check(lib().fic_encode(self.h, imgs, n, ctypes.byref(p), pools, codes, _stream()), "fic_encode")
+        return bufs
+
+    def decode(self, p: Params, pools, codes, width: int, height: int, iterations: int, out=None):
+        t = _torch()
+        out = out if out is not None else t.empty((height, width), dtype=t.uint8, device=codes[0].xy.device)
+        pc = (PoolC * p.levels)(*[pl.c() for pl in pools])
+        cc = (CodesC * p.levels)(*[cd.c() for cd in codes])
+        _check(lib().fic_decode(self.h, ctypes.byref(p), pc, cc, width, height, iterations, out.data_ptr(),
+                                _stream()), "fic_decode")
+        return out
+
+
+def levels_numpy(pools, codes, p: Params):
+    """Host copies of one image's encoder output, trimmed to the live counts."""
+    out = []
+    for l in range(p.levels):
+        out.append({"B": p.block0 >> l, "pool": pools[l].numpy(), "codes": codes[l].numpy(),
+                    "s_num": np.array(p.s_num[l][:p.s_count[l]], np.int32), "s_den": p.s_den[l]})
+    return out

@@ -1,0 +1,212 @@
+"""Parity of the HIP encoder and decoder with the oracle, element by element:
+pools (xy, key, sum4, A), codes (range xy, split, domain, isometry, s index,
+offset, val_q), the child lists and the decoded image, for both search
+engines.  Inputs are seeded synthetic images (paper_1502_00324_amd.synth)."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1502_00324_amd import fic
+from paper_1502_00324_amd.configs import WORKLOADS, K16
+from paper_1502_00324_amd.synth import make_image
+
+pytestmark = pytest.mark.gpu
+WORKERS = max(1, min(16, os.cpu_count() or 1))
+ENGINES = [fic.ENGINE_MFMA, fic.ENGINE_FP32]
+ENGINE_IDS = ["mfma", "fp32"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build()
+    c = fic.Context(0)
+    yield c
+    c.close()
+
+
+def params(levels, pct, pool_max, s_num, s_den, rms, engine):
+    return fic.make_params(levels, pct=pct, pool_max=pool_max, s_num=s_num, s_den=s_den, split_rms=rms,
+                           engine=engine)
+
+
+def gpu_run(ctx, img, p, iters=None):
+    H, W = img.shape
+    t = torch.from_numpy(img).cuda()
+    pools, codes = ctx.encode([t], p)[0]
+    dec = ctx.decode(p, pools, codes, W, H, iters) if iters is not None else None
+    torch.cuda.synchronize()
+    return fic.levels_numpy(pools, codes, p), (dec.cpu().numpy() if dec is not None else None)
+
+
+def oracle_run(img, levels, pct, pool_max, s_num, s_den, rms):
+    return oracle.encode(img, levels, pct=pct, pool_max=pool_max, s_num=s_num, s_den=s_den, split_rms=rms,
+                         workers=WORKERS)
+
+
+def assert_levels_equal(got, ref, tag=""):
+    assert len(got) == len(ref)
+    for l, (g, r) in enumerate(zip(got, ref)):
+        for f in ("xy", "key", "sum4", "a"):
+            np.testing.assert_array_equal(g["pool"][f], r["pool"][f], err_msg="%s level %d pool %s" % (tag, l, f))
+        np.testing.assert_array_equal(g["codes"]["xy"], r["ranges"], err_msg="%s level %d ranges" % (tag, l))
+        for f in ("split", "domain", "iso", "s_idx", "offset", "err"):
+            np.testing.assert_array_equal(g["codes"][f], r["codes"][f], err_msg="%s level %d %s" % (tag, l, f))
+
+
+CASES = [
+    # name, seed, W, H, n_rect, levels, pct, pool_max, s_num, s_den, split_rms
+    ("c1_64", 0, 64, 64, 10, [(8, 4), (4, 4)], (3, 10), 0, K16, 16, (8, 1)),
+    ("ragged_160x96", 1, 160, 96, 6, [(8, 4), (4, 4)], (3, 10), 0, K16, 16, (8, 1)),
+    ("three_levels_L2", 2, 128, 64, 8, [(16, 2), (8, 2), (4, 2)], (3, 10), 0, K16, 16, (6, 1)),
+    ("b4_L1_to_b2", 3, 64, 48, 4, [(4, 1), (2, 1)], (1, 2), 0, K16, 16, (8, 1)),
+    ("paper_schedule_dn32", 4, 128, 128, 12, [(16, 4), (8, 4), (4, 4), (2, 4)], (0, 1), 32,
+     ((1,), (2, 4), (3, 8), (5, 9)), 10, (8, 1)),
+    ("all_split", 5, 64, 64, 2, [(8, 2), (4, 2)], (3, 10), 0, K16, 16, (0, 1)),
+    ("none_split", 6, 64, 64, 2, [(8, 2), (4, 2)], (3, 10), 0, K16, 16, (255, 1)),
+    ("b16_single_level", 7, 96, 96, 5, [(16, 2)], (3, 10), 0, K16, 16, (8, 1)),
+    ("pct0_full_pool", 8, 64, 64, 5, [(8, 2), (4, 2)], (0, 1), 0, K16, 16, (5, 1)),
+    ("odd_s_set", 9, 64, 64, 5, [(8, 4), (4, 4)], (3, 10), 0, (0, 3, 7, 10), 10, (7, 2)),
+    ("b32_to_b16", 10, 128, 128, 10, [(32, 4), (16, 4)], (1, 2), 0, K16, 16, (8, 1)),
+    ("pool_max_ties", 11, 96, 64, 30, [(8, 2), (4, 2)], (1, 10), 100, K16, 16, (6, 1)),
+]
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_encode_decode_parity(ctx, case, engine):
+    name, seed, W, H, nrect, levels, pct, dn, s_num, s_den, rms = case
+    print("case", name, "engine", engine, flush=True)
+    img = make_image(seed, W, H, nrect)
+    got, dec = gpu_run(ctx, img, params(levels, pct, dn, s_num, s_den, rms, engine), iters=6)
+    ref = oracle_run(img, levels, pct, dn, s_num, s_den, rms)
+    assert_levels_equal(got, ref, name)
+    ref_dec = oracle.decode(W, H, ref, 6)
+    np.testing.assert_array_equal(dec, ref_dec)
+    assert oracle.psnr(img, dec) == oracle.psnr(img, ref_dec)
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+def test_constant_and_block_constant_images(ctx, engine):
+    rng = np.random.default_rng(99)
+    for img in (np.full((64, 64), 77, np.uint8),
+                np.kron(rng.integers(0, 256, (8, 8)), np.ones((8, 8), np.int64)).astype(np.uint8)):
+        p = params([(8, 4), (4, 4)], (3, 10), 0, K16, 16, (8, 1), engine)
+        got, dec = gpu_run(ctx, img, p, iters=3)
+        c = got[0]["codes"]
+        assert (c["domain"] == 0).all() and (c["iso"] == 0).all() and (c["s_idx"] == 0).all()
+        assert (c["err"] == 0).all() and (c["split"] == 0).all() and len(got[1]["codes"]["xy"]) == 0
+        np.testing.assert_array_equal(dec, img)
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+def test_config2_512_full_parity(ctx, engine):
+    wl = WORKLOADS["c2_512"]
+    seed, W, H, nrect = wl.images[0]
+    img = make_image(seed, W, H, nrect)
+    p = params(wl.levels, wl.pct, wl.pool_max, wl.s_num, wl.s_den, wl.split_rms, engine)
+    got, dec = gpu_run(ctx, img, p, iters=8)
+    ref = oracle_run(img, wl.levels, wl.pct, wl.pool_max, list(wl.s_num), wl.s_den, wl.split_rms)
+    assert_levels_equal(got, ref, "c2")
+    np.testing.assert_array_equal(dec, oracle.decode(W, H, ref, 8))
+
+
+def test_config3_1024_sampled_parity(ctx):
+    """Full-size c3 (L = 1, ~0.7 M domains per level): both pools in full, and
+    the codes of 24 seeded level-0 ranges with their whole quadtree subtrees."""
+    wl = WORKLOADS["c3_1024"]
+    seed, W, H, nrect = wl.images[0]
+    img = make_image(seed, W, H, nrect)
+    p = params(wl.levels, wl.pct, wl.pool_max, wl.s_num, wl.s_den, wl.split_rms, fic.ENGINE_MFMA)
+    got, _ = gpu_run(ctx, img, p)
+    s_num = list(wl.s_num)
+    pools = []
+    for l, (B, L) in enumerate(wl.levels):
+        ref_pool = oracle.build_pool(img, B, L, wl.pct, wl.pool_max)
+        for f in ("xy", "key", "sum4", "a"):
+            np.testing.assert_array_equal(got[l]["pool"][f], ref_pool[f], err_msg="c3 level %d pool %s" % (l, f))
+        pools.append(ref_pool)
+    rng = np.random.default_rng(2024)
+    B0 = wl.levels[0][0]
+    all0 = oracle.level0_ranges(W, H, B0)
+    np.testing.assert_array_equal(got[0]["codes"]["xy"], all0)
+    pick = np.sort(rng.choice(len(all0), 24, replace=False))
+    ranges = all0[pick]
+    for l, (B, L) in enumerate(wl.levels):
+        last = l == len(wl.levels) - 1
+        ref = oracle.encode_level(img, pools[l]["xy"], ranges, B, s_num, wl.s_den, wl.split_rms, last,
+                                  workers=WORKERS)
+        pos = {int(v): i for i, v in enumerate(got[l]["codes"]["xy"])}
+        idx = np.array([pos[int(v)] for v in ranges], np.int64)
+        for f in ("split", "domain", "iso", "s_idx", "offset", "err"):
+            np.testing.assert_array_equal(got[l]["codes"][f][idx], ref[f], err_msg="c3 level %d %s" % (l, f))
+        if not last:
+            ranges = oracle.children(ranges, ref["split"], B)
+            if len(ranges) == 0:
+                break
+
+
+def test_stepwise_entry_points_match_oracle(ctx):
+    """fic_build_domain_pool + fic_encode_level driven one level at a time."""
+    img = make_image(12, 96, 64, 8)
+    levels = [(8, 2), (4, 2)]
+    ref = oracle_run(img, levels, (3, 10), 0, K16, 16, (6, 1))
+    t = torch.from_numpy(img).cuda()
+    xy = torch.from_numpy(oracle.level0_ranges(96, 64, 8).view(np.int32)).cuda()
+    n = torch.tensor([len(xy)], dtype=torch.int32, device="cuda")
+    cap = len(xy)
+    for l, (B, L) in enumerate(levels):
+        pool = ctx.build_domain_pool(t, B, L, (3, 10), 0)
+        last = l == len(levels) - 1
+        codes, children, nch = ctx.encode_level(t, pool, xy, n, cap, B, K16, 16, (6, 1), last, fic.ENGINE_MFMA)
+        torch.cuda.synchronize()
+        g = codes.numpy()
+        for f in ("split", "domain", "iso", "s_idx", "offset", "err"):
+            np.testing.assert_array_equal(g[f], ref[l]["codes"][f], err_msg="level %d %s" % (l, f))
+        np.testing.assert_array_equal(pool.numpy()["xy"], ref[l]["pool"]["xy"])
+        if not last:
+            xy, n, cap = children, nch, 4 * cap
+
+
+def test_determinism_and_batch_independence(ctx):
+    imgs = [make_image(s, w, h, 6) for s, w, h in [(20, 64, 64), (21, 128, 64), (22, 96, 96)]]
+    p = params([(16, 2), (8, 2), (4, 2)], (3, 10), 0, K16, 16, (6, 1), fic.ENGINE_MFMA)
+    batch = ctx.encode([torch.from_numpy(im).cuda() for im in imgs], p)
+    torch.cuda.synchronize()
+    for im, (pools, codes) in zip(imgs, batch):
+        alone, _ = gpu_run(ctx, im, p)
+        again, _ = gpu_run(ctx, im, p)
+        together = fic.levels_numpy(pools, codes, p)
+        for a, b, c in zip(alone, again, together):
+            for f in ("split", "domain", "iso", "s_idx", "offset", "err", "xy"):
+                np.testing.assert_array_equal(a["codes"][f], b["codes"][f])
+                np.testing.assert_array_equal(a["codes"][f], c["codes"][f])
+
+
+def test_failure_paths_return_status_without_launch(ctx):
+    img = torch.from_numpy(make_image(30, 64, 64, 3)).cuda()
+    p = params([(8, 4), (4, 4)], (3, 10), 0, K16, 16, (8, 1), fic.ENGINE_MFMA)
+    (pools, codes), = ctx.alloc_encode([(64, 64)], p, img.device)
+    small = fic.Pool.alloc(5, img.device)
+    with pytest.raises(fic.FicError) as e:
+        ctx.encode([img], p, bufs=[([small, pools[1]], codes)])
+    assert e.value.status == fic.FIC_E_CAPACITY
+    bad = params([(8, 4), (4, 4)], (3, 10), 0, K16, 16, (8, 1), fic.ENGINE_MFMA)
+    bad.s_num[0][3] = 1   # not ascending
+    with pytest.raises(fic.FicError) as e:
+        ctx.encode([img], bad)
+    assert e.value.status == fic.FIC_E_INVALID
+    limited = fic.Context(0)
+    limited.set_scratch_limit(1024)
+    with pytest.raises(fic.FicError) as e:
+        limited.encode([img], p)
+    assert e.value.status == fic.FIC_E_NOMEM
+    limited.close()
+    # the shared context still works after the refused calls
+    got, _ = gpu_run(ctx, make_image(0, 64, 64, 10), p)
+    assert len(got[0]["codes"]["xy"]) == 64
