@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of the fractal encoder's range-to-domain search on one MI355X.
+
+One step = one whole encode of the workload's images (every quadtree level:
+pool build, operand preparation, search, per-range codes, child lists) with
+the int8-MFMA engine, inputs resident in HBM.  The metric is range x domain x
+isometry comparisons per second: sum over levels of ranges x pool domains x 8
+per step, divided by the step time.  Printed as one JSON line, with the plain
+FP32 engine timed beside it, the roofline of the dominant kernel (the search
+at the level that takes longest, timed with HIP events on its own stream) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+INT8_PEAK_TOPS = 5000.0          # MI355X dense int8 MFMA, published
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_search_mfma.json")
+KERNEL_SOURCES = ["paper_1502_00324_amd/csrc/k_search_mfma.hip", "paper_1502_00324_amd/csrc/search_common.h",
+                  "paper_1502_00324_amd/csrc/fic_internal.h"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def level_counts(bufs, p):
+    """(B, ranges, pool) per level and image, read back after a run."""
+    out = []
+    for pools, codes in bufs:
+        out.append([(p.block0 >> l, int(codes[l].count.item()), int(pools[l].count.item())) for l in range(p.levels)])
+    return out
+
+
+def run_steps(ctx, imgs, p, bufs, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.encode(imgs, p, bufs)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / max(steps, 1)
+
+
+def cpu_baseline(wl, images, counts, budget_s):
+    """The oracle, single-threaded, on a bounded sample: full pool builds and
+    a seeded sample of ranges per level, scaled to the whole workload."""
+    import numpy as np
+
+    import oracle
+    oracle.build()
+    seed, W, H, nrect = wl.images[0]
+    img = images[0]
+    rng = np.random.default_rng(7)
+    total_triples, t_total, sampled = 0, 0.0, []
+    per_level_budget = budget_s / max(1, len(wl.levels))
+    for l, (B, L) in enumerate(wl.levels):
+        t0 = time.perf_counter()
+        pool = oracle.build_pool(img, B, L, wl.pct, wl.pool_max)
+        t_pool = time.perf_counter() - t0
+        s_num = list(wl.s_num[l]) if isinstance(wl.s_num[0], (tuple, list)) else list(wl.s_num)
+        all_r = oracle.level0_ranges(W, H, B)
+        done, t_search = 0, 0.0
+        while t_search < per_level_budget - t_pool and done < len(all_r):
+            pick = all_r[rng.integers(0, len(all_r), 2)]
+            t1 = time.perf_counter()
+            oracle.encode_level(img, pool["xy"], pick, B, s_num, wl.s_den if isinstance(wl.s_den, int)
+                                else wl.s_den[l], wl.split_rms, l == len(wl.levels) - 1, workers=1)
+            t_search += time.perf_counter() - t1
+            done += len(pick)
+        _, R, P = counts[0][l]
+        per_range = t_search / done
+        t_total += t_pool + per_range * R
+        total_triples += R * P * 8
+        sampled.append("level %d (B=%d): full pool (%.2f s) + %d ranges x %d domains (%.2f s)" %
+                       (l, B, t_pool, done, len(pool["xy"]), t_search))
+    return {"value": total_triples / t_total, "unit": "comparisons/s", "cores": 1, "kind": "oracle",
+            "sample": "; ".join(sampled) + "; time scaled to every range of the GPU run's levels",
+            "extrapolated_encode_s": round(t_total, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3_1024")
+    ap.add_argument("--fp32-steps", type=int, default=2, help="timed steps of the plain FP32 engine (0 skips)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample budget (0 skips)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 1 GiB device copy (HBM counter calibration for profiling runs)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this encoder build measures one GPU only; --gpus %d is not supported" % args.gpus)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1502_00324_amd import fic
+    from paper_1502_00324_amd.configs import WORKLOADS
+    from paper_1502_00324_amd.synth import make_image
+
+    wl = WORKLOADS[args.workload]
+    images = [make_image(s, w, h, n) for (s, w, h, n) in wl.images]
+    dev = torch.device("cuda:0")
+    imgs = [torch.from_numpy(im).to(dev) for im in images]
+    ctx = fic.Context(0)
+    mk = lambda engine: fic.make_params(wl.levels, pct=wl.pct, pool_max=wl.pool_max, s_num=wl.s_num,
+                                        s_den=wl.s_den, split_rms=wl.split_rms, engine=engine)
+    p = mk(fic.ENGINE_MFMA)
+    bufs = ctx.alloc_encode([(im.shape[1], im.shape[0]) for im in images], p, dev)
+    for _ in range(args.warmup):
+        ctx.encode(imgs, p, bufs)
+    torch.cuda.synchronize()
+
+    ctx.set_timing(True)
+    sec = run_steps(ctx, imgs, p, bufs, args.steps, torch)
+    stages = ctx.read_timing()
+    ctx.set_timing(False)
+    counts = level_counts(bufs, p)
+    triples_by_B = {}
+    for per_img in counts:
+        for (B, R, P) in per_img:
+            triples_by_B[B] = triples_by_B.get(B, 0) + R * P * 8
+    triples = sum(triples_by_B.values())
+    value = triples / sec
+
+    # dominant kernel: the search launch with the largest summed time
+    search = {B: v for (name, B), v in stages.items() if name == "search"}
+    dom_B = max(search, key=lambda b: search[b][0])
+    ms_tot, launches = search[dom_B]
+    avg_ms = ms_tot / launches
+    launches_per_step = launches / max(args.steps, 1)
+    alg_ops = triples_by_B[dom_B] * 2 * dom_B * dom_B / launches_per_step   # decimated MACs x 2 per launch
+    achieved = alg_ops / (avg_ms * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == kernel_source_hash() and tr.get("workload") == wl.name:
+            traffic = tr.get("per_launch_bytes", {}).get(str(dom_B))
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": traffic,
+                "kernel": "k_mfma_search (B=%d)" % dom_B, "avg_launch_ms": round(avg_ms, 4),
+                "ops_per_launch": alg_ops,
+                "ops_note": "algorithmic int8 ops = 2 B^2 per comparison (decimated inner product); the MFMA form "
+                            "issues 8 B^2 (4B^2 int8 MACs), i.e. %.2f TOPS issued" % (4 * achieved)}
+
+    fp32 = None
+    if args.fp32_steps > 0:
+        pf = mk(fic.ENGINE_FP32)
+        bf = ctx.alloc_encode([(im.shape[1], im.shape[0]) for im in images], pf, dev)
+        ctx.encode(imgs, pf, bf)
+        ctx.set_timing(True)
+        sec_f = run_steps(ctx, imgs, pf, bf, args.fp32_steps, torch)
+        st_f = ctx.read_timing()
+        ctx.set_timing(False)
+        same = all(
+            bool((a[1][l].domain[:int(a[1][l].count.item())] == b[1][l].domain[:int(b[1][l].count.item())]).all())
+            for a, b in zip(bufs, bf) for l in range(p.levels))
+        fsearch = {B: v[0] / max(args.fp32_steps, 1) for (name, B), v in st_f.items() if name == "search"}
+        msearch = {B: v[0] / max(args.steps, 1) for B, v in search.items()}
+        fp32 = {"value": triples / sec_f, "ms_per_step": round(sec_f * 1e3, 3), "speedup_mfma": round(sec_f / sec, 2),
+                "search_ms_per_step": {str(B): round(v, 3) for B, v in fsearch.items()},
+                "search_speedup_mfma": {str(B): round(fsearch[B] / msearch[B], 2) for B in fsearch if B in msearch},
+                "codes_identical": same}
+
+    if args.copy_calib:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(wl, images, counts, args.cpu_seconds)
+
+    per_stage = {"%s_B%d" % (n, B): round(v[0] / max(args.steps, 1), 4) for (n, B), v in sorted(stages.items())}
+    out = {
+        "metric": "range x domain x isometry comparisons/s (whole encode, all quadtree levels)",
+        "value": value, "unit": "comparisons/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 3), "encode_ms_per_image": round(sec * 1e3 / len(images), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic (seeded 1/f^2 noise + rectangles)",
+        "config": {"workload": wl.name + ": " + wl.notes, "images": len(images),
+                   "levels": [{"B": B, "L": L} for (B, L) in wl.levels],
+                   "pool": "drop ceil(%d/%d * Nd) lowest-entropy candidates" % wl.pct,
+                   "s_set": "k/16, k=0..16" if wl.s_den == 16 else str(wl.s_num), "split_rms": wl.split_rms[0],
+                   "engine": "int8 MFMA", "parallelism": "single GPU"},
+        "comparisons_per_step": triples,
+        "levels": [{"B": B, "ranges": R, "pool": P, "comparisons": R * P * 8} for (B, R, P) in counts[0]]
+        if len(counts) == 1 else None,
+        "stage_ms_per_step": per_stage,
+        "roofline": roofline, "fp32_baseline": fp32, "cpu_baseline": cpu,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

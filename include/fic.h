@@ -116,6 +116,21 @@ void fic_ctx_destroy(fic_ctx *ctx);
 int fic_ctx_set_scratch_limit(fic_ctx *ctx, int64_t bytes);
 const char *fic_strerror(int status);
 
+/* Stage timing with HIP events recorded on the caller's stream around each
+ * stage a call enqueues (measurement aid; off by default).  Stages: pool build,
+ * search operand preparation (range moments and operand layouts), the search
+ * kernel, the per-range finalisation (argmin merge, isometry, split, child
+ * list), and one decoder iteration.  Slots are indexed by log2(B). */
+enum { FIC_T_POOL = 0, FIC_T_PREP = 1, FIC_T_SEARCH = 2, FIC_T_FINAL = 3, FIC_T_DECODE = 4, FIC_T_KINDS = 5 };
+typedef struct {
+    double ms[FIC_T_KINDS][6];       /* summed event time per stage and log2(B) */
+    int32_t launches[FIC_T_KINDS][6];
+} fic_timing;
+/* enable != 0 starts recording (discarding earlier records); 0 stops. */
+int fic_ctx_set_timing(fic_ctx *ctx, int enable);
+/* Waits for the recorded events, writes their sums to *out and clears them. */
+int fic_ctx_read_timing(fic_ctx *ctx, fic_timing *out);
+
 /* ---- host-only helpers (no device needed) ----------------------------- */
 
 /* FIC_OK if params are usable for a width x height image:

@@ -14,7 +14,10 @@ SOURCES = ["fic_host.hip", "k_pool.hip", "k_level.hip", "k_search_mfma.hip", "k_
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          # packed FP32 instructions are kept out of every kernel
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA results land in VGPRs, not AGPRs: the epilogue reads every
+         # accumulator, and AGPR results would need one copy each
+         "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _compile(src: str) -> str:

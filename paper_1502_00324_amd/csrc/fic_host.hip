@@ -3,7 +3,23 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 #include "fic_internal.h"
+
+namespace fic {
+
+struct Timer {
+    struct Rec {
+        int kind, slot;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> spare;
+    int open = -1;
+};
+
+}  // namespace fic
 
 using namespace fic;
 
@@ -186,6 +202,7 @@ int do_pool(fic_ctx *ctx, const fic_image *img, int B, int L, fic_ratio pct, int
     const int64_t c = ((int64_t)pct.num * nd + pct.den - 1) / pct.den;
     PoolSel *sel = (PoolSel *)sp(ctx, S_SEL);
     int64_t *keys = (int64_t *)sp(ctx, S_KEYS);
+    mark(ctx, FIC_T_POOL, B, st);
     FIC_TRY(launch_sel_init(sel, c, pool_max, st));
     FIC_TRY(launch_pool_keys(img->pix, img->pitch, nx, (int)nd, L, 2 * B, ctx->table, keys, sel, st));
     FIC_TRY(launch_pool_select(keys, (int)nd, c, pool_max, sel, st));
@@ -193,6 +210,7 @@ int do_pool(fic_ctx *ctx, const fic_image *img, int B, int L, fic_ratio pct, int
                                 (int *)sp(ctx, S_BLOCKOFF), out, st));
     const int cap = (int)(pool_max > 0 && pool_max < nd ? pool_max : nd);
     FIC_TRY(launch_pool_moments(img->pix, img->pitch, B, cap, out, st));
+    mark(ctx, -1, 0, st);
     return FIC_OK;
 }
 
@@ -204,26 +222,31 @@ int do_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, const uin
     Partial *part = (Partial *)sp(ctx, S_PARTIAL);
     float2 *dinfo = (float2 *)sp(ctx, S_DINFO);
     int nchunk, tpc;
+    mark(ctx, FIC_T_PREP, B, st);
     FIC_TRY(launch_range_info(img->pix, img->pitch, B, rxy, nr, range_cap, ri, st));
     if (mfma) {
         int rpw;
         mfma_geometry(B, range_cap, pool_cap, &rpw, &nchunk, &tpc);
         FIC_TRY(launch_mfma_prep(img->pix, img->pitch, B, rxy, nr, range_cap, pool, pool_cap, sp(ctx, S_AFRAG),
                                  sp(ctx, S_BFRAG), dinfo, st));
+        mark(ctx, FIC_T_SEARCH, B, st);
         FIC_TRY(launch_mfma_search(B, sp(ctx, S_AFRAG), sp(ctx, S_BFRAG), dinfo, ri, nr, range_cap, pool, pool_cap,
                                    ss, part, st));
     } else {
         fp32_geometry(B, range_cap, pool_cap, &nchunk, &tpc);
         FIC_TRY(launch_fp32_prep(img->pix, img->pitch, B, rxy, nr, range_cap, pool, pool_cap,
                                  (float *)sp(ctx, S_VF32), (float *)sp(ctx, S_DF32), dinfo, st));
+        mark(ctx, FIC_T_SEARCH, B, st);
         FIC_TRY(launch_fp32_search(B, (const float *)sp(ctx, S_VF32), (const float *)sp(ctx, S_DF32), dinfo, ri, nr,
                                    range_cap, pool, pool_cap, ss, part, st));
     }
+    mark(ctx, FIC_T_FINAL, B, st);
     FIC_TRY(launch_finalize(img->pix, img->pitch, B, rxy, nr, range_cap, pool, part, nchunk, ss, rms, is_last, out,
                             st));
     if (!is_last)
         FIC_TRY(launch_children(out, range_cap, B, (int *)sp(ctx, S_BLOCKSUM), (int *)sp(ctx, S_BLOCKOFF), children,
                                 n_children, st));
+    mark(ctx, -1, 0, st);
     return FIC_OK;
 }
 
@@ -267,6 +290,58 @@ int reserve(fic_ctx *ctx, const size_t *bytes) {
         ctx->slot[i].bytes = want;
     }
     return FIC_OK;
+}
+
+static int log2i(int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v && l < 5) ++l;
+    return l;
+}
+
+static hipEvent_t take_event(Timer *t) {
+    if (!t->spare.empty()) {
+        hipEvent_t e = t->spare.back();
+        t->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void mark(fic_ctx *ctx, int kind, int B, hipStream_t st) {
+    Timer *t = ctx->timer;
+    if (!t) return;
+    if (t->open >= 0) {
+        (void)hipEventRecord(t->recs[t->open].b, st);
+        t->open = -1;
+    }
+    if (kind < 0 || t->recs.size() >= (1u << 16)) return;
+    Timer::Rec r;
+    r.kind = kind;
+    r.slot = log2i(B);
+    r.a = take_event(t);
+    r.b = take_event(t);
+    if (!r.a || !r.b) return;
+    (void)hipEventRecord(r.a, st);
+    t->recs.push_back(r);
+    t->open = (int)t->recs.size() - 1;
+}
+
+static void recycle(Timer *t) {
+    for (auto &r : t->recs) {
+        t->spare.push_back(r.a);
+        t->spare.push_back(r.b);
+    }
+    t->recs.clear();
+    t->open = -1;
+}
+
+static void destroy_timer(Timer *t) {
+    if (!t) return;
+    recycle(t);
+    for (hipEvent_t e : t->spare) (void)hipEventDestroy(e);
+    delete t;
 }
 
 }  // namespace fic
@@ -355,6 +430,7 @@ void fic_ctx_destroy(fic_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    destroy_timer(ctx->timer);
     for (int i = 0; i < S_NUM_SLOTS; ++i)
         if (ctx->slot[i].ptr) (void)hipFree(ctx->slot[i].ptr);
     if (ctx->table) (void)hipFree(ctx->table);
@@ -364,6 +440,39 @@ void fic_ctx_destroy(fic_ctx *ctx) {
 int fic_ctx_set_scratch_limit(fic_ctx *ctx, int64_t bytes) {
     if (!ctx || bytes < 0) return FIC_E_INVALID;
     ctx->limit = bytes;
+    return FIC_OK;
+}
+
+int fic_ctx_set_timing(fic_ctx *ctx, int enable) {
+    if (!ctx) return FIC_E_INVALID;
+    int st = enter(ctx);
+    if (st != FIC_OK) return st;
+    if (enable) {
+        if (!ctx->timer) ctx->timer = new Timer;
+        else recycle(ctx->timer);
+    } else {
+        (void)hipDeviceSynchronize();
+        destroy_timer(ctx->timer);
+        ctx->timer = nullptr;
+    }
+    return FIC_OK;
+}
+
+int fic_ctx_read_timing(fic_ctx *ctx, fic_timing *out) {
+    if (!ctx || !out) return FIC_E_INVALID;
+    memset(out, 0, sizeof(*out));
+    Timer *t = ctx->timer;
+    if (!t) return FIC_OK;
+    int st = enter(ctx);
+    if (st != FIC_OK) return st;
+    for (auto &r : t->recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return FIC_E_HIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return FIC_E_HIP;
+        out->ms[r.kind][r.slot] += ms;
+        out->launches[r.kind][r.slot] += 1;
+    }
+    recycle(t);
     return FIC_OK;
 }
 
@@ -480,10 +589,12 @@ int fic_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const f
     for (int it = 0; it < iterations; ++it) {
         const uint8_t *cur = (it % 2 == 0) ? buf0 : buf1;
         uint8_t *nxt = (it % 2 == 0) ? buf1 : buf0;
+        mark(ctx, FIC_T_DECODE, 1, s);
         for (int l = 0; l < p->levels; ++l)
             FIC_TRY(launch_decode_iter(p->block0 >> l, &codes[l], codes[l].capacity, &pools[l],
                                        make_sset(p->s_num[l], p->s_count[l], p->s_den[l]), cur, nxt, width, s));
     }
+    mark(ctx, -1, 0, s);
     return FIC_OK;
 }
 

@@ -89,16 +89,25 @@ struct Buf { void *ptr; size_t bytes; };
 
 }  // namespace fic
 
+namespace fic {
+struct Timer;  // event records of the optional stage timing
+}
+
 struct fic_ctx {
     int device;
     int64_t limit;               // 0 = unlimited
     fic::Buf slot[fic::S_NUM_SLOTS];
     int64_t *table;              // device entropy table
+    fic::Timer *timer;           // non-null while stage timing is on
 };
 
 namespace fic {
 
 int reserve(fic_ctx *ctx, const size_t *bytes);   // bytes[S_NUM_SLOTS], 0 = untouched
+
+// Stage timing: mark(ctx, kind, B, st) opens a stage (closing the previous
+// open one); mark(ctx, -1, 0, st) closes it.  No-ops unless timing is on.
+void mark(fic_ctx *ctx, int kind, int B, hipStream_t st);
 inline void *sp(fic_ctx *ctx, Slot s) { return ctx->slot[s].ptr; }
 
 // ---------------------------------------------------------------- launchers

@@ -6,44 +6,79 @@
 namespace fic {
 
 // ---------------------------------------------------------------- keys
-// One wave per candidate, a private 256-bin LDS histogram per wave.
 // G = sum over gray levels of T[count]; a larger G means a lower entropy.
-__global__ __launch_bounds__(256) void k_pool_keys(const uint8_t *__restrict__ img, int pitch, int nx, int nd, int L,
-                                                   int dsz, const int64_t *__restrict__ T,
-                                                   int64_t *__restrict__ keys, unsigned long long *gmin) {
-    __shared__ uint32_t hist[4][256];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int cand = blockIdx.x * 4 + w;
-    uint32_t *h = hist[w];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) h[lane + 64 * i] = 0;
+// One wave per strip: lane l owns candidate column cx = 64*bx + l and slides
+// its window down over S candidate rows.  Each lane keeps a private 256-bin
+// histogram in LDS (layout [bin][lane], no atomics) and updates G
+// incrementally: adding a pixel whose bin held c adds T[c+1] - T[c].
+constexpr int kStripRows = 16;
+
+__global__ __launch_bounds__(64) void k_pool_keys(const uint8_t *__restrict__ img, int pitch, int nx, int ny, int L,
+                                                  int dsz, const int64_t *__restrict__ T,
+                                                  int64_t *__restrict__ keys, unsigned long long *gmin) {
+    __shared__ uint16_t hist[256][64];
+    __shared__ int64_t dtab[1025];
+    const int lane = threadIdx.x;
+    const int M = dsz * dsz;
+    const bool lds_tab = M <= 1024;
+    if (lds_tab)
+        for (int c = lane; c < M; c += 64) dtab[c] = T[c + 1] - T[c];
+    for (int v = 0; v < 256; ++v) hist[v][lane] = 0;
     __syncthreads();
-    const bool valid = cand < nd;
-    if (valid) {
-        const int cy = cand / nx, cx = cand - cy * nx;
-        const uint8_t *base = img + (size_t)(cy * L) * pitch + (size_t)cx * L;
-        const int m = dsz * dsz;
-        if (dsz >= 64) {
-            for (int dy = 0; dy < dsz; ++dy)
-                for (int dx = lane; dx < dsz; dx += 64) atomicAdd(&h[base[(size_t)dy * pitch + dx]], 1u);
-        } else {
-            for (int i = lane; i < m; i += 64) {
-                const int dy = i / dsz, dx = i - dy * dsz;
-                atomicAdd(&h[base[(size_t)dy * pitch + dx]], 1u);
+    const int cx = blockIdx.x * 64 + lane;
+    const int cy0 = blockIdx.y * kStripRows;
+    const int cy1 = min(ny, cy0 + kStripRows);
+    // inactive lanes stay for the wave reduction below
+    const bool active = cx < nx && cy0 < ny;
+    const uint8_t *col = img + (size_t)(active ? cx : 0) * L;
+    uint16_t *h = &hist[0][lane];
+    auto dlt = [&](int c) -> int64_t { return lds_tab ? dtab[c] : T[c + 1] - T[c]; };
+    int64_t g = 0, gm = INT64_MAX;
+    auto add_row = [&](int y) {
+        const uint8_t *row = col + (size_t)y * pitch;
+        for (int i = 0; i < dsz; ++i) {
+            const int v = row[i];
+            const int c = h[v * 64];
+            g += dlt(c);
+            h[v * 64] = (uint16_t)(c + 1);
+        }
+    };
+    auto remove_row = [&](int y) {
+        const uint8_t *row = col + (size_t)y * pitch;
+        for (int i = 0; i < dsz; ++i) {
+            const int v = row[i];
+            const int c = h[v * 64];
+            g -= dlt(c - 1);
+            h[v * 64] = (uint16_t)(c - 1);
+        }
+    };
+    if (active) {
+        int ytop = cy0 * L;
+        for (int r = 0; r < dsz; ++r) add_row(ytop + r);
+        keys[(size_t)cy0 * nx + cx] = g;
+        gm = g;
+        for (int cy = cy0 + 1; cy < cy1; ++cy) {
+            const int ynew = cy * L;
+            if (L < dsz) {
+                for (int r = 0; r < L; ++r) {
+                    remove_row(ytop + r);
+                    add_row(ytop + dsz + r);
+                }
+            } else {
+                for (int r = 0; r < dsz; ++r) remove_row(ytop + r);
+                for (int r = 0; r < dsz; ++r) add_row(ynew + r);
             }
+            ytop = ynew;
+            keys[(size_t)cy * nx + cx] = g;
+            gm = min(gm, g);
         }
     }
-    __syncthreads();
-    if (valid) {
-        int64_t g = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) g += T[h[lane + 64 * i]];
-        g = wave_sum_i64(g);
-        if (lane == 0) {
-            keys[cand] = g;
-            atomicMin(gmin, (unsigned long long)g);
-        }
+    // wave minimum, then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(gm, off, 64);
+        gm = min(gm, o);
     }
+    if (lane == 0) atomicMin(gmin, (unsigned long long)gm);
 }
 
 // ---------------------------------------------------------------- radix select
@@ -186,13 +221,12 @@ __global__ __launch_bounds__(256) void k_pool_moments(const uint8_t *__restrict_
 }
 
 // ---------------------------------------------------------------- launchers
+// k_sel_init must run first on the stream: it resets gmin.
 hipError_t launch_pool_keys(const uint8_t *img, int pitch, int nx, int nd, int L, int dsz, const int64_t *table,
                             int64_t *keys, PoolSel *sel, hipStream_t st) {
-    // the selection state and gmin are initialised by launch_pool_select's caller order:
-    // k_sel_init runs first (see fic_build_domain_pool)
-    const int blocks = (nd + 3) / 4;
-    if (blocks > 0)
-        k_pool_keys<<<blocks, 256, 0, st>>>(img, pitch, nx, nd, L, dsz, table, keys, &sel->gmin);
+    const int ny = nx > 0 ? nd / nx : 0;
+    const dim3 grid((nx + 63) / 64, (ny + kStripRows - 1) / kStripRows);
+    if (nd > 0) k_pool_keys<<<grid, 64, 0, st>>>(img, pitch, nx, ny, L, dsz, table, keys, &sel->gmin);
     return hipGetLastError();
 }
 

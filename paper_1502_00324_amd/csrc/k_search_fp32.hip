@@ -93,7 +93,10 @@ __global__ __launch_bounds__(256) void k_fp32_search(const float *__restrict__ v
     constexpr int NKC = n / KC;
     __shared__ __align__(16) float Vs[KC][kF32Ranges * 8];
     __shared__ __align__(16) float Ds[KC][kF32Doms];
+    __shared__ SLds sl;
     const int tid = threadIdx.x, tr = tid >> 5, td = tid & 31;
+    load_sset(sl, ss);
+    __syncthreads();
     const int R = min(*nr, range_cap), P = min(*np, pool_cap);
     const int rg = blockIdx.x;
     if (rg * kF32Ranges >= R) return;  // uniform over the block
@@ -151,6 +154,7 @@ __global__ __launch_bounds__(256) void k_fp32_search(const float *__restrict__ v
                     }
             }
         }
+        bool any = false;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             int c[8];
@@ -160,7 +164,13 @@ __global__ __launch_bounds__(256) void k_fp32_search(const float *__restrict__ v
             const int p = tile * kF32Doms + td * 4 + j;
             const float2 di = dinfo[p];
             const float rhs = fmaf(tn, di.y, fmaf(-bn, di.x, -an));
-            if (p < P && rvalid && (float)m > rhs) confirm_pair(m, p, r, n, ri, sum4, pa, ss, best, bp, bk, tn);
+            const bool pass = (p < P) & rvalid & ((float)m > rhs);
+            if (pass) confirm_pair(m, p, r, n, ri, sum4, pa, sl, best, bp, bk);
+            any |= pass;
+        }
+        if (__ballot(any)) {  // share the best of the 32 threads holding this range
+            const int64_t gb = group_min_val<32>(best);
+            tn = rvalid ? tn_from(gb, x.cr, sl.den, n) : -1e30f;
         }
     }
     group_min<32>(best, bp, bk);

@@ -17,6 +17,9 @@
 //   K index k = 64 s + 16 (L/16) + byte -> raw pixel (k / 2B, k % 2B).
 // With rows arranged this way the two halves give each lane all 8 isometries
 // of one (range, domain) pair, so the isometry max stays in registers.
+#include <stdio.h>
+#include <stdlib.h>
+
 #include "fic_internal.h"
 #include "search_common.h"
 
@@ -26,7 +29,27 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 bool mfma_supported(int B) { return B == 4 || B == 8 || B == 16; }
 
-static int mfma_rq(int B) { return B == 4 ? 4 : (B == 8 ? 2 : 1); }
+// Tile shape: range quads per wave (RQ) and domain tiles per LDS stage (DT).
+// Each range size has a measured default; FIC_MFMA_SHAPE="rq,dt" selects
+// another compiled shape (used to tune).
+struct Shape { int B, rq, dt; };
+static const Shape kShapes[] = {
+    {4, 2, 16}, {4, 1, 16}, {4, 4, 16},
+    {8, 2, 8}, {8, 2, 4}, {8, 1, 8}, {8, 3, 8},
+    {16, 1, 1}, {16, 1, 2},
+};
+static Shape mfma_shape(int B) {
+    const char *e = getenv("FIC_MFMA_SHAPE");
+    int rq = 0, dt = 0;
+    if (e && sscanf(e, "%d,%d", &rq, &dt) == 2)
+        for (const Shape &s : kShapes)
+            if (s.B == B && s.rq == rq && s.dt == dt) return s;
+    for (const Shape &s : kShapes)
+        if (s.B == B) return s;  // the first entry per size is the default
+    return Shape{B, 1, 1};
+}
+static int mfma_rq(int B) { return mfma_shape(B).rq; }
+static int mfma_dt(int B) { return mfma_shape(B).dt; }
 
 // Quads of 4 ranges covered by the search grid (every wave reads RQ whole quads).
 int mfma_quads_padded(int B, int range_cap) {
@@ -34,13 +57,19 @@ int mfma_quads_padded(int B, int range_cap) {
     return (range_cap + rpw - 1) / rpw * (rpw / 4);
 }
 
+// Work split: nrg range groups (16 RQ ranges per workgroup) x nchunk domain
+// chunks.  nchunk is a multiple of 8 whenever the pool allows, so that the
+// workgroups of one XCD (dispatched round-robin, id % 8) share their chunks.
 void mfma_geometry(int B, int range_cap, int pool_cap, int *ranges_per_wg, int *nchunk, int *tiles_per_chunk) {
-    const int rpw = 4 * 4 * mfma_rq(B);
+    const int rpw = 16 * mfma_rq(B);
     const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
     const int nrg = (range_cap + rpw - 1) / rpw;
-    int nc = (8192 + nrg - 1) / nrg;
-    nc = max(1, min(nc, max(1, ntiles / 8)));
-    nc = min(nc, 4096);
+    const int min_tiles = 8 * mfma_dt(B);          // at least 8 LDS stages per chunk
+    int nc = (4096 + nrg - 1) / nrg;
+    nc = (nc + 7) / 8 * 8;
+    nc = min(nc, max(1, ntiles / min_tiles));
+    if (nc >= 8) nc = nc / 8 * 8;
+    nc = max(1, min(nc, 4096));
     *ranges_per_wg = rpw;
     *nchunk = nc;
     *tiles_per_chunk = (ntiles + nc - 1) / nc;
@@ -110,21 +139,41 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(const uint8_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------- search
-// One wave owns RQ quads (4 RQ ranges) and streams one chunk of domain tiles.
-template <int KS, int RQ>
-__global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afrag, const v4i *__restrict__ bfrag,
+// A workgroup of 4 waves owns 16 RQ ranges (each wave RQ quads) and one chunk
+// of domain tiles.  Domain fragments go global -> registers -> LDS in stages
+// of DT tiles, double-buffered: the loads for stage s+1 are issued before the
+// MFMAs of stage s and written to the other LDS buffer after them.
+template <int KS, int RQ, int DT>
+__global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afrag, const uint4 *__restrict__ bfrag,
                                                      const float2 *__restrict__ dinfo, const RInfo *__restrict__ ri,
                                                      const int32_t *nr, int range_cap, const int32_t *np,
                                                      int pool_cap, const uint32_t *__restrict__ sum4,
-                                                     const int64_t *__restrict__ pa, SSet ss, int n,
-                                                     int tiles_per_chunk, int nchunk, Partial *__restrict__ part) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                                                     const int64_t *__restrict__ pa, SSet ss, int n, int nrg,
+                                                     int nchunk, int tiles_per_chunk, Partial *__restrict__ part) {
+    constexpr int STAGE = DT * KS * 64;          // uint4 per stage
+    constexpr int PER_T = STAGE / 256;
+    static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
+    __shared__ uint4 bl[2][STAGE];
+    __shared__ float2 dl[2][DT * kDomTile];
+    __shared__ SLds sl;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    load_sset(sl, ss);
+    int rg, chunk;
+    if (nchunk % 8 == 0) {  // XCD-aware: workgroup w runs on XCD w % 8
+        const int w = blockIdx.x, xcd = w & 7, k = w >> 3;
+        chunk = xcd + 8 * (k / nrg);
+        rg = k % nrg;
+    } else {
+        rg = blockIdx.x % nrg;
+        chunk = blockIdx.x / nrg;
+    }
     const int R = min(*nr, range_cap), P = min(*np, pool_cap);
-    const int q0 = (blockIdx.x * 4 + wave) * RQ;
-    if (q0 * 4 >= R) return;  // whole wave; the kernel has no block barrier
-    const int chunk = blockIdx.y;
+    if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
     const int ntiles = (P + kDomTile - 1) / kDomTile;
     const int t0 = chunk * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
+    const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
+    const int q0 = (rg * 4 + wave) * RQ;
+    const bool wave_on = q0 * 4 < R;
     const int g = lane >> 4;
 
     v4i A[RQ][2][KS];
@@ -148,28 +197,98 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
         bk[qi] = 0;
     }
 
-    for (int tile = t0; tile < t1; ++tile) {
+    // Drain the one-time loads above now: vmcnt is in-order, so a wait for
+    // them inside the tile loop would also wait for the stage prefetch.
+    __builtin_amdgcn_s_waitcnt(0);
+
+    uint4 pre[PER_T];
+    float2 dpre = make_float2(0.f, 0.f);
+    auto gload = [&](int stg) {
+        const int tbase = t0 + stg * DT;
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) {
+            const int e = tid + 256 * i;
+            pre[i] = tbase + e / (KS * 64) < t1 ? bfrag[(size_t)tbase * KS * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        if (tid < DT * kDomTile && tbase + tid / kDomTile < t1) dpre = dinfo[(size_t)tbase * kDomTile + tid];
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
+        if (tid < DT * kDomTile) dl[buf][tid] = dpre;
+    };
+    if (nstage > 0) {
+        gload(0);
+        swrite(0);
+    }
+    __syncthreads();
+    // lane l holds domain 16 t + (l % 16) of tile t: valid while t < lim (the
+    // chunk end and the pool end); tiles past t1 in the last stage are zeros
+    const int lim = min(t1, (P - (lane & 15) + kDomTile - 1) / kDomTile);
+    auto mfma_tile = [&](v4i (&acc)[RQ][2], int buf, int dt) {
         v4i Bf[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) Bf[s] = bfrag[((size_t)tile * KS + s) * 64 + lane];
-        const int p = tile * kDomTile + (lane & 15);
-        const float2 di = dinfo[p];
-        const bool pv = p < P;
-#pragma unroll
-        for (int qi = 0; qi < RQ; ++qi) {
-            v4i cx = {0, 0, 0, 0}, cy = {0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                cx = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][0][s], Bf[s], cx, 0, 0, 0);
-                cy = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][1][s], Bf[s], cy, 0, 0, 0);
-            }
-            const int m = max8(cx.x, cx.y, cx.z, cx.w, cy.x, cy.y, cy.z, cy.w);
-            const float rhs = fmaf(tn[qi], di.y, fmaf(-bn[qi], di.x, -an[qi]));
-            if (pv && rr[qi] >= 0 && (float)m > rhs)
-                confirm_pair(m, p, rr[qi], n, ri, sum4, pa, ss, best[qi], bp[qi], bk[qi], tn[qi]);
+        for (int s = 0; s < KS; ++s) {
+            const uint4 u = bl[buf][(dt * KS + s) * 64 + lane];
+            Bf[s] = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
         }
+#pragma unroll
+        for (int qi = 0; qi < RQ; ++qi) acc[qi][0] = acc[qi][1] = v4i{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int qi = 0; qi < RQ; ++qi) {
+                acc[qi][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][0][s], Bf[s], acc[qi][0], 0, 0, 0);
+                acc[qi][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][1][s], Bf[s], acc[qi][1], 0, 0, 0);
+            }
+    };
+    for (int stg = 0; stg < nstage; ++stg) {
+        const int buf = stg & 1;
+        if (stg + 1 < nstage) gload(stg + 1);
+        if (wave_on) {
+            const int tbase = t0 + stg * DT;
+            // software pipeline: the MFMAs of tile dt+1 are issued before the
+            // prune test of tile dt, in the same basic block
+            v4i acc[2][RQ][2];
+            mfma_tile(acc[0], buf, 0);
+#pragma unroll
+            for (int dt = 0; dt < DT; ++dt) {
+                const int cur = dt & 1;
+                if (dt + 1 < DT) mfma_tile(acc[cur ^ 1], buf, dt + 1);
+                const float2 di = dl[buf][dt * kDomTile + (lane & 15)];
+                const bool pv = tbase + dt < lim;
+                bool pass[RQ];
+                bool any = false;
+                int mx[RQ];
+#pragma unroll
+                for (int qi = 0; qi < RQ; ++qi) {
+                    const v4i cx = acc[cur][qi][0], cy = acc[cur][qi][1];
+                    mx[qi] = max8(cx.x, cx.y, cx.z, cx.w, cy.x, cy.y, cy.z, cy.w);
+                    const float rhs = fmaf(tn[qi], di.y, fmaf(-bn[qi], di.x, -an[qi]));
+                    pass[qi] = pv & (rr[qi] >= 0) & ((float)mx[qi] > rhs);
+                    any |= pass[qi];
+                }
+                if (__builtin_amdgcn_ballot_w64(any)) {  // rare: exact evaluation, then share the best
+                    const int p = (tbase + dt) * kDomTile + (lane & 15);
+#pragma unroll
+                    for (int qi = 0; qi < RQ; ++qi) {
+                        if (pass[qi]) confirm_pair(mx[qi], p, rr[qi], n, ri, sum4, pa, sl, best[qi], bp[qi], bk[qi]);
+                        if (__builtin_amdgcn_ballot_w64(pass[qi])) {
+                            // the 16 lanes holding this range share their best: the
+                            // threshold may use it because a pair is only rejected
+                            // when it cannot even tie it
+                            const int64_t gb = group_min_val<16>(best[qi]);
+                            tn[qi] = rr[qi] >= 0 ? tn_from(gb, ri[rr[qi]].cr, sl.den, n) : -1e30f;
+                        }
+                    }
+                }
+            }
+        }
+        if (stg + 1 < nstage) swrite(buf ^ 1);
+        __syncthreads();
     }
 
+    if (!wave_on) return;
 #pragma unroll
     for (int qi = 0; qi < RQ; ++qi) {
         int64_t v = best[qi];
@@ -203,13 +322,14 @@ hipError_t launch_mfma_prep(const uint8_t *img, int pitch, int B, const uint32_t
     return hipGetLastError();
 }
 
-template <int KS, int RQ>
-static void launch_search_t(dim3 grid, hipStream_t st, const void *afrag, const void *bfrag, const float2 *dinfo,
-                            const RInfo *ri, const int32_t *nr, int range_cap, const fic_pool *pool, int pool_cap,
-                            SSet ss, int n, int tpc, int nchunk, Partial *part) {
-    k_mfma_search<KS, RQ><<<grid, 256, 0, st>>>((const v4i *)afrag, (const v4i *)bfrag, dinfo, ri, nr, range_cap,
-                                                pool->count, pool_cap, pool->sum4, pool->a, ss, n, tpc, nchunk,
-                                                part);
+template <int KS, int RQ, int DT>
+static hipError_t launch_search_t(int nrg, int nchunk, int tpc, hipStream_t st, const void *afrag, const void *bfrag,
+                            const float2 *dinfo, const RInfo *ri, const int32_t *nr, int range_cap,
+                            const fic_pool *pool, int pool_cap, SSet ss, int n, Partial *part) {
+    k_mfma_search<KS, RQ, DT><<<nrg * nchunk, 256, 0, st>>>((const v4i *)afrag, (const uint4 *)bfrag, dinfo, ri, nr,
+                                                            range_cap, pool->count, pool_cap, pool->sum4, pool->a,
+                                                            ss, n, nrg, nchunk, tpc, part);
+    return hipGetLastError();
 }
 
 hipError_t launch_mfma_search(int B, const void *afrag, const void *bfrag, const float2 *dinfo, const RInfo *ri,
@@ -217,19 +337,29 @@ hipError_t launch_mfma_search(int B, const void *afrag, const void *bfrag, const
                               Partial *part, hipStream_t st) {
     int rpw, nchunk, tpc;
     mfma_geometry(B, range_cap, pool_cap, &rpw, &nchunk, &tpc);
-    const dim3 grid((range_cap + rpw - 1) / rpw, nchunk);
-    if (grid.x == 0) return hipSuccess;
+    const int nrg = (range_cap + rpw - 1) / rpw;
+    if (nrg == 0) return hipSuccess;
     const int n = B * B;
-    switch (B) {
-        case 4: launch_search_t<1, 4>(grid, st, afrag, bfrag, dinfo, ri, nr, range_cap, pool, pool_cap, ss, n, tpc,
-                                      nchunk, part); break;
-        case 8: launch_search_t<4, 2>(grid, st, afrag, bfrag, dinfo, ri, nr, range_cap, pool, pool_cap, ss, n, tpc,
-                                      nchunk, part); break;
-        case 16: launch_search_t<16, 1>(grid, st, afrag, bfrag, dinfo, ri, nr, range_cap, pool, pool_cap, ss, n,
-                                        tpc, nchunk, part); break;
-        default: return hipErrorInvalidValue;
+    const Shape sh = mfma_shape(B);
+#define FIC_SEARCH(KS, RQ, DT)                                                                                  \
+    if (sh.rq == RQ && sh.dt == DT)                                                                             \
+        return launch_search_t<KS, RQ, DT>(nrg, nchunk, tpc, st, afrag, bfrag, dinfo, ri, nr, range_cap, pool,  \
+                                           pool_cap, ss, n, part)
+    if (B == 4) {
+        FIC_SEARCH(1, 2, 16);
+        FIC_SEARCH(1, 1, 16);
+        FIC_SEARCH(1, 4, 16);
+    } else if (B == 8) {
+        FIC_SEARCH(4, 2, 8);
+        FIC_SEARCH(4, 2, 4);
+        FIC_SEARCH(4, 1, 8);
+        FIC_SEARCH(4, 3, 8);
+    } else if (B == 16) {
+        FIC_SEARCH(16, 1, 1);
+        FIC_SEARCH(16, 1, 2);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
+#undef FIC_SEARCH
 }
 
 }  // namespace fic

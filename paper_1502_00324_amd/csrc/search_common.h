@@ -13,6 +13,8 @@
 // is 16 den^2 (Cr - Bx^2/A), so a pair can reach val <= best only if
 //   Bx > sqrt(A) * sqrt(c),  c = Cr - best/(16 den^2)  (c >= 0),
 // i.e.  C'max > tn*sqrtA - bn*Sd4 - an  with tn = sqrt(c)/n rounded down,
+// where best is the smallest val found so far by any lane holding the range
+// (a pair is rejected only when it cannot even tie that value),
 // bn = (128n - Sr)/n, an = 512 Sr - 65536 n + margin.  When c < 0 every pair
 // passes (tn = -1e30).  The margin (n/4 + 4) exceeds the float rounding of the
 // test (< n/16), so no pair that could win is ever rejected.  Passing pairs
@@ -27,8 +29,10 @@ __device__ inline bool lex_less_vp(int64_t va, int pa, int64_t vb, int pb) {
     return va < vb || (va == vb && pa < pb);
 }
 
+// Written as three 3-input maxima and one 2-input one (v_max3_i32 x3, v_max_i32).
 __device__ __forceinline__ int max8(int a0, int a1, int a2, int a3, int b0, int b1, int b2, int b3) {
-    return max(max(max(a0, a1), max(a2, a3)), max(max(b0, b1), max(b2, b3)));
+    const int m1 = max(max(a0, a1), a2), m2 = max(max(a3, b0), b1), m3 = max(b2, b3);
+    return max(max(m1, m2), m3);
 }
 
 __device__ inline float sqrt_down(double v) {
@@ -38,12 +42,26 @@ __device__ inline float sqrt_down(double v) {
     return f;
 }
 
+// Contrast numerators in LDS, so lanes may index them independently.
+struct SLds {
+    int32_t num[kMaxS];
+    int32_t count, den;
+};
+
+__device__ inline void load_sset(SLds &dst, const SSet &ss) {
+    if (threadIdx.x < kMaxS) dst.num[threadIdx.x] = ss.num[threadIdx.x];
+    if (threadIdx.x == 0) {
+        dst.count = ss.count;
+        dst.den = ss.den;
+    }
+}
+
 // Exact evaluation of one (range, domain) pair given C'max.  Updates the
 // lane's running best with a strict comparison: along a lane the domain index
 // only grows, so equal values keep the earlier domain.
 __device__ __forceinline__ void confirm_pair(int cmax, int p, int r, int n, const RInfo *__restrict__ ri,
-                                          const uint32_t *__restrict__ sum4, const int64_t *__restrict__ pa,
-                                          const SSet &ss, int64_t &best, int &bp, int &bk, float &tn) {
+                                             const uint32_t *__restrict__ sum4, const int64_t *__restrict__ pa,
+                                             const SLds &ss, int64_t &best, int &bp, int &bk) {
     const RInfo x = ri[r];
     const int64_t sd4 = sum4[p], A = pa[p];
     const int64_t sr = x.sr;
@@ -51,26 +69,44 @@ __device__ __forceinline__ void confirm_pair(int cmax, int p, int r, int n, cons
     const int64_t bx = (int64_t)n * x4 - sr * sd4;
     const int64_t den = ss.den;
     const int64_t lhs = 8 * den * bx;
-    // midpoint rule: s_{j+1} beats s_j iff 8 den Bx > A (num_j + num_{j+1});
-    // the predicate is monotone in j, so k* is the last j+1 where it holds
-    int k = 0;
-    int64_t nk = ss.num[0];
-    for (int j = 0; j + 1 < ss.count; ++j) {
-        const int64_t a = ss.num[j], b = ss.num[j + 1];
-        if (lhs > A * (a + b)) {
-            k = j + 1;
-            nk = b;
-        }
+    // midpoint rule: s_{j+1} beats s_j iff 8 den Bx > A (num_j + num_{j+1}); the
+    // predicate is monotone (true, then false) in j, so k* = the first false j
+    int lo = 0, hi = ss.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (lhs > A * (int64_t)(ss.num[mid] + ss.num[mid + 1])) lo = mid + 1;
+        else hi = mid;
     }
+    const int64_t nk = ss.num[lo];
     const int64_t val = nk * nk * A - 8 * nk * den * bx + 16 * den * den * x.cr;
     if (val < best) {
         best = val;
         bp = p;
-        bk = k;
-        const int64_t scale = 16 * den * den;
-        const int64_t num = scale * x.cr - val;
-        tn = num < 0 ? -1e30f : sqrt_down((double)num / (double)scale * (1.0 - 1.0 / 1048576.0)) / (float)n;
+        bk = lo;
     }
+}
+
+// Prune threshold tn = sqrt(Cr - best/(16 den^2)) / n, rounded down: every
+// float step below rounds by at most 2^-24 relative, and the 1 - 2^-20
+// factor covers them all.  No improvement yet (or c < 0): every pair passes.
+// A best of 0 cannot be beaten (val >= 0) and later domains lose ties, so the
+// range is done: NaN makes every later comparison false.  This matters for
+// flat ranges, where every pair ties at 0 and would pass a non-strict test.
+__device__ __forceinline__ float tn_from(int64_t best, int64_t cr, int den, int n) {
+    const int64_t scale = 16 * (int64_t)den * den;
+    if (best == 0) return __builtin_nanf("");
+    if (best == INT64_MAX) return -1e30f;
+    const int64_t num = scale * cr - best;
+    if (num < 0) return -1e30f;
+    const float c = (float)num * (1.0f / (float)scale);
+    return sqrtf(c) * (1.0f - 1.0f / 1048576.0f) / (float)n;
+}
+
+template <int WIDTH>
+__device__ inline int64_t group_min_val(int64_t v) {
+#pragma unroll
+    for (int off = WIDTH / 2; off > 0; off >>= 1) v = min(v, (int64_t)__shfl_xor(v, off, 64));
+    return v;
 }
 
 // Merge (val, domain, k) over 16-lane groups (xor offsets < 16) or 32-lane

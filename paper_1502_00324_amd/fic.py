@@ -43,6 +43,14 @@ class Params(ctypes.Structure):
                 ("s_num", (i32 * MAX_S) * MAX_LEVELS), ("split_rms", Ratio * MAX_LEVELS), ("engine", i32)]
 
 
+T_POOL, T_PREP, T_SEARCH, T_FINAL, T_DECODE, T_KINDS = 0, 1, 2, 3, 4, 5
+T_NAMES = ("pool", "prep", "search", "final", "decode")
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("ms", (ctypes.c_double * 6) * T_KINDS), ("launches", (i32 * 6) * T_KINDS)]
+
+
 class PoolC(ctypes.Structure):
     _fields_ = [("capacity", i32), ("count", vp), ("xy", vp), ("key", vp), ("sum4", vp), ("a", vp)]
 
@@ -69,6 +77,8 @@ def lib() -> ctypes.CDLL:
         L.fic_ctx_destroy.argtypes = [vp]
         L.fic_ctx_destroy.restype = None
         L.fic_ctx_set_scratch_limit.argtypes = [vp, i64]
+        L.fic_ctx_set_timing.argtypes = [vp, i32]
+        L.fic_ctx_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
         L.fic_validate_params.argtypes = [ctypes.POINTER(Params), i32, i32]
         L.fic_query_capacity.argtypes = [ctypes.POINTER(Params), i32, i32, vp, vp]
         L.fic_entropy_table.argtypes = [vp, i32]
@@ -84,7 +94,8 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
-EXPORTED = ("fic_ctx_create", "fic_ctx_destroy", "fic_ctx_set_scratch_limit", "fic_strerror",
+EXPORTED = ("fic_ctx_create", "fic_ctx_destroy", "fic_ctx_set_scratch_limit", "fic_ctx_set_timing",
+            "fic_ctx_read_timing", "fic_strerror",
             "fic_validate_params", "fic_query_capacity", "fic_entropy_table", "fic_build_domain_pool",
             "fic_encode_level", "fic_encode", "fic_decode")
 
@@ -240,6 +251,20 @@ class Context:
 
     def set_scratch_limit(self, nbytes: int):
         _check(lib().fic_ctx_set_scratch_limit(self.h, nbytes), "fic_ctx_set_scratch_limit")
+
+    def set_timing(self, enable: bool):
+        _check(lib().fic_ctx_set_timing(self.h, int(enable)), "fic_ctx_set_timing")
+
+    def read_timing(self) -> dict:
+        """{(stage, B): (ms, launches)} summed over the recorded calls."""
+        t = Timing()
+        _check(lib().fic_ctx_read_timing(self.h, ctypes.byref(t)), "fic_ctx_read_timing")
+        out = {}
+        for k in range(T_KINDS):
+            for s in range(6):
+                if t.launches[k][s]:
+                    out[(T_NAMES[k], 1 << s)] = (t.ms[k][s], t.launches[k][s])
+        return out
 
     # -------------------------------------------------------------- entry points
     def build_domain_pool(self, img, B: int, L: int, pct=(3, 10), pool_max: int = 0, pool: Pool | None = None) -> Pool:
