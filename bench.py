@@ -177,9 +177,10 @@ def main():
                 "codes_identical": same}
 
     if args.copy_calib:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        # an elementwise kernel (not a DMA copy), so the counters see 1 GiB read + 1 GiB written
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 3, out=b)
         torch.cuda.synchronize()
 
     cpu = None

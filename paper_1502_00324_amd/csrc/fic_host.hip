@@ -176,8 +176,7 @@ void level_bytes(int B, int range_cap, int pool_cap, bool mfma, size_t *b) {
     b[S_RINFO] = sizeof(RInfo) * (size_t)(range_cap + 1);
     int nchunk, tpc;
     if (mfma) {
-        int rpw;
-        mfma_geometry(B, range_cap, pool_cap, &rpw, &nchunk, &tpc);
+        nchunk = mfma_geometry(B, range_cap, pool_cap).nslot;
         const size_t KS = (size_t)B * B / 16;
         const size_t ntiles = (size_t)(pool_cap + kDomTile - 1) / kDomTile;
         b[S_AFRAG] = (size_t)mfma_quads_padded(B, range_cap) * 2 * KS * 1024;
@@ -225,8 +224,7 @@ int do_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, const uin
     mark(ctx, FIC_T_PREP, B, st);
     FIC_TRY(launch_range_info(img->pix, img->pitch, B, rxy, nr, range_cap, ri, st));
     if (mfma) {
-        int rpw;
-        mfma_geometry(B, range_cap, pool_cap, &rpw, &nchunk, &tpc);
+        nchunk = mfma_geometry(B, range_cap, pool_cap).nslot;
         FIC_TRY(launch_mfma_prep(img->pix, img->pitch, B, rxy, nr, range_cap, pool, pool_cap, sp(ctx, S_AFRAG),
                                  sp(ctx, S_BFRAG), dinfo, st));
         mark(ctx, FIC_T_SEARCH, B, st);

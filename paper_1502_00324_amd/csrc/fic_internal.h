@@ -136,7 +136,17 @@ hipError_t launch_children(const fic_level_codes *codes, int cap, int B, int *bl
 
 // MFMA engine
 bool mfma_supported(int B);
-void mfma_geometry(int B, int range_cap, int pool_cap, int *ranges_per_wg, int *nchunk, int *tiles_per_chunk);
+struct MfmaGeom {
+    int rpw;      // ranges per workgroup
+    int nrg;      // range groups
+    int tpc;      // domain tiles per chunk
+    int nchunk;   // chunks over the pool capacity
+    int xcd;      // 1 = XCD-aware mapping (nchunk % 8 == 0)
+    int G;        // chunks walked by one workgroup
+    int nslot;    // partial results per range
+    int nwg;      // workgroups
+};
+MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap);
 int mfma_quads_padded(int B, int range_cap);
 hipError_t launch_mfma_prep(const uint8_t *img, int pitch, int B, const uint32_t *rxy, const int32_t *nr,
                             int range_cap, const fic_pool *pool, int pool_cap, void *afrag, void *bfrag,

@@ -57,22 +57,48 @@ int mfma_quads_padded(int B, int range_cap) {
     return (range_cap + rpw - 1) / rpw * (rpw / 4);
 }
 
-// Work split: nrg range groups (16 RQ ranges per workgroup) x nchunk domain
-// chunks.  nchunk is a multiple of 8 whenever the pool allows, so that the
-// workgroups of one XCD (dispatched round-robin, id % 8) share their chunks.
-void mfma_geometry(int B, int range_cap, int pool_cap, int *ranges_per_wg, int *nchunk, int *tiles_per_chunk) {
-    const int rpw = 16 * mfma_rq(B);
+// Work split.  A workgroup owns rpw = 16 RQ ranges (a range group) and
+// streams domain tiles in chunks of about 1.5 MB of fragments, small enough
+// to stay resident in one XCD's 4 MB L2 while every range group running on
+// that XCD reads it.  With 8 or more chunks the mapping is XCD-aware:
+// workgroups are dispatched round-robin (id % 8 = XCD), XCD x owns chunks
+// x, x+8, x+16, ..., and consecutive workgroups of an XCD take consecutive
+// range groups of the same chunks.  A workgroup walks G chunks of its XCD
+// with one running best over them (about a quarter of the XCD's chunks, and
+// enough to keep the partial results, one per range and slot, under 256 MB).
+MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap) {
+    MfmaGeom g;
+    const int rq = mfma_rq(B), dt = mfma_dt(B), KS = B * B / 16;
+    g.rpw = 16 * rq;
+    g.nrg = (range_cap + g.rpw - 1) / g.rpw;
     const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
-    const int nrg = (range_cap + rpw - 1) / rpw;
-    const int min_tiles = 8 * mfma_dt(B);          // at least 8 LDS stages per chunk
-    int nc = (4096 + nrg - 1) / nrg;
-    nc = (nc + 7) / 8 * 8;
-    nc = min(nc, max(1, ntiles / min_tiles));
-    if (nc >= 8) nc = nc / 8 * 8;
-    nc = max(1, min(nc, 4096));
-    *ranges_per_wg = rpw;
-    *nchunk = nc;
-    *tiles_per_chunk = (ntiles + nc - 1) / nc;
+    g.tpc = max(8 * dt, 1536 / KS);
+    g.nchunk = (ntiles + g.tpc - 1) / g.tpc;
+    if (g.nchunk < 8) {
+        // small pool: split finer only to give the GPU enough workgroups
+        int nc = max(g.nchunk, min((ntiles + 8 * dt - 1) / (8 * dt), (2048 + g.nrg - 1) / max(1, g.nrg)));
+        nc = max(1, min(nc, 8));
+        if (nc >= 8) nc = 8;
+        g.nchunk = nc;
+    } else {
+        g.nchunk = (g.nchunk + 7) / 8 * 8;
+    }
+    g.tpc = max(1, (ntiles + g.nchunk - 1) / g.nchunk);
+    g.xcd = g.nchunk % 8 == 0 ? 1 : 0;
+    if (g.xcd) {
+        // a workgroup walks about a quarter of its XCD's chunks, so each range
+        // group reads its operands ~4 times per XCD rather than once per chunk
+        const int per_xcd = g.nchunk / 8;
+        const long max_slots = max(8L, (256L << 20) / 16 / max(1, range_cap));
+        const int groups_max = (int)max(1L, max_slots / 8);
+        g.G = max((per_xcd + groups_max - 1) / groups_max, (per_xcd + 3) / 4);
+        g.nslot = 8 * ((per_xcd + g.G - 1) / g.G);
+    } else {
+        g.G = 1;
+        g.nslot = g.nchunk;
+    }
+    g.nwg = g.nrg * g.nslot;
+    return g;
 }
 
 // ---------------------------------------------------------------- operands
@@ -148,8 +174,8 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
                                                      const float2 *__restrict__ dinfo, const RInfo *__restrict__ ri,
                                                      const int32_t *nr, int range_cap, const int32_t *np,
                                                      int pool_cap, const uint32_t *__restrict__ sum4,
-                                                     const int64_t *__restrict__ pa, SSet ss, int n, int nrg,
-                                                     int nchunk, int tiles_per_chunk, Partial *__restrict__ part) {
+                                                     const int64_t *__restrict__ pa, SSet ss, int n, MfmaGeom geo,
+                                                     Partial *__restrict__ part) {
     constexpr int STAGE = DT * KS * 64;          // uint4 per stage
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
@@ -158,20 +184,23 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
     __shared__ SLds sl;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
-    int rg, chunk;
-    if (nchunk % 8 == 0) {  // XCD-aware: workgroup w runs on XCD w % 8
-        const int w = blockIdx.x, xcd = w & 7, k = w >> 3;
-        chunk = xcd + 8 * (k / nrg);
-        rg = k % nrg;
+    int rg, cfirst, cstep, ncs, slot;
+    if (geo.xcd) {  // XCD-aware: workgroup w runs on XCD w % 8
+        const int w = blockIdx.x, xcd = w & 7, k = w >> 3, grp = k / geo.nrg;
+        rg = k % geo.nrg;
+        cfirst = xcd + 8 * grp * geo.G;
+        cstep = 8;
+        ncs = geo.G;
+        slot = xcd + 8 * grp;
     } else {
-        rg = blockIdx.x % nrg;
-        chunk = blockIdx.x / nrg;
+        rg = blockIdx.x % geo.nrg;
+        cfirst = slot = blockIdx.x / geo.nrg;
+        cstep = 1;
+        ncs = 1;
     }
     const int R = min(*nr, range_cap), P = min(*np, pool_cap);
     if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
     const int ntiles = (P + kDomTile - 1) / kDomTile;
-    const int t0 = chunk * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
-    const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
     const int q0 = (rg * 4 + wave) * RQ;
     const bool wave_on = q0 * 4 < R;
     const int g = lane >> 4;
@@ -203,6 +232,7 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
 
     uint4 pre[PER_T];
     float2 dpre = make_float2(0.f, 0.f);
+    int t0 = 0, t1 = 0;  // tile range of the chunk being streamed
     auto gload = [&](int stg) {
         const int tbase = t0 + stg * DT;
 #pragma unroll
@@ -217,14 +247,9 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
         for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
         if (tid < DT * kDomTile) dl[buf][tid] = dpre;
     };
-    if (nstage > 0) {
-        gload(0);
-        swrite(0);
-    }
-    __syncthreads();
     // lane l holds domain 16 t + (l % 16) of tile t: valid while t < lim (the
     // chunk end and the pool end); tiles past t1 in the last stage are zeros
-    const int lim = min(t1, (P - (lane & 15) + kDomTile - 1) / kDomTile);
+    const int plim = (P - (lane & 15) + kDomTile - 1) / kDomTile;
     auto mfma_tile = [&](v4i (&acc)[RQ][2], int buf, int dt) {
         v4i Bf[KS];
 #pragma unroll
@@ -242,6 +267,17 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
                 acc[qi][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][1][s], Bf[s], acc[qi][1], 0, 0, 0);
             }
     };
+  for (int cj = 0; cj < ncs; ++cj) {
+    const int chunk = cfirst + cj * cstep;
+    t0 = chunk * geo.tpc;
+    t1 = min(ntiles, t0 + geo.tpc);
+    const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
+    const int lim = min(t1, plim);
+    if (nstage > 0) {
+        gload(0);
+        swrite(0);
+    }
+    __syncthreads();
     for (int stg = 0; stg < nstage; ++stg) {
         const int buf = stg & 1;
         if (stg + 1 < nstage) gload(stg + 1);
@@ -287,6 +323,7 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
         if (stg + 1 < nstage) swrite(buf ^ 1);
         __syncthreads();
     }
+  }
 
     if (!wave_on) return;
 #pragma unroll
@@ -299,7 +336,7 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
             o.val = v;
             o.p = p == INT32_MAX ? -1 : p;
             o.k = k;
-            part[(size_t)rr[qi] * nchunk + chunk] = o;
+            part[(size_t)rr[qi] * geo.nslot + slot] = o;
         }
     }
 }
@@ -323,28 +360,26 @@ hipError_t launch_mfma_prep(const uint8_t *img, int pitch, int B, const uint32_t
 }
 
 template <int KS, int RQ, int DT>
-static hipError_t launch_search_t(int nrg, int nchunk, int tpc, hipStream_t st, const void *afrag, const void *bfrag,
-                            const float2 *dinfo, const RInfo *ri, const int32_t *nr, int range_cap,
-                            const fic_pool *pool, int pool_cap, SSet ss, int n, Partial *part) {
-    k_mfma_search<KS, RQ, DT><<<nrg * nchunk, 256, 0, st>>>((const v4i *)afrag, (const uint4 *)bfrag, dinfo, ri, nr,
-                                                            range_cap, pool->count, pool_cap, pool->sum4, pool->a,
-                                                            ss, n, nrg, nchunk, tpc, part);
+static hipError_t launch_search_t(const MfmaGeom &g, hipStream_t st, const void *afrag, const void *bfrag,
+                                  const float2 *dinfo, const RInfo *ri, const int32_t *nr, int range_cap,
+                                  const fic_pool *pool, int pool_cap, SSet ss, int n, Partial *part) {
+    k_mfma_search<KS, RQ, DT><<<g.nwg, 256, 0, st>>>((const v4i *)afrag, (const uint4 *)bfrag, dinfo, ri, nr,
+                                                     range_cap, pool->count, pool_cap, pool->sum4, pool->a, ss, n,
+                                                     g, part);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma_search(int B, const void *afrag, const void *bfrag, const float2 *dinfo, const RInfo *ri,
                               const int32_t *nr, int range_cap, const fic_pool *pool, int pool_cap, SSet ss,
                               Partial *part, hipStream_t st) {
-    int rpw, nchunk, tpc;
-    mfma_geometry(B, range_cap, pool_cap, &rpw, &nchunk, &tpc);
-    const int nrg = (range_cap + rpw - 1) / rpw;
-    if (nrg == 0) return hipSuccess;
+    const MfmaGeom g = mfma_geometry(B, range_cap, pool_cap);
+    if (g.nrg == 0) return hipSuccess;
     const int n = B * B;
     const Shape sh = mfma_shape(B);
 #define FIC_SEARCH(KS, RQ, DT)                                                                                  \
     if (sh.rq == RQ && sh.dt == DT)                                                                             \
-        return launch_search_t<KS, RQ, DT>(nrg, nchunk, tpc, st, afrag, bfrag, dinfo, ri, nr, range_cap, pool,  \
-                                           pool_cap, ss, n, part)
+        return launch_search_t<KS, RQ, DT>(g, st, afrag, bfrag, dinfo, ri, nr, range_cap, pool, pool_cap, ss, n, \
+                                           part)
     if (B == 4) {
         FIC_SEARCH(1, 2, 16);
         FIC_SEARCH(1, 1, 16);
