@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "fic_internal.h"
@@ -22,6 +23,8 @@ struct Timer {
 }  // namespace fic
 
 using namespace fic;
+using std::max;
+using std::min;
 
 namespace {
 
@@ -157,93 +160,246 @@ int hip_status(hipError_t e) { return e == hipSuccess ? FIC_OK : (e == hipErrorO
         if (e_ != hipSuccess) return hip_status(e_); \
     } while (0)
 
-// ---------------------------------------------------------------- scratch sizing
-void max_into(size_t *dst, const size_t *src) {
-    for (int i = 0; i < S_NUM_SLOTS; ++i)
-        if (src[i] > dst[i]) dst[i] = src[i];
-}
+// ---------------------------------------------------------------- batched level plans
+size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
-void pool_bytes(int64_t nd, size_t *b) {
-    const size_t nb = (size_t)((nd + kScanBlock - 1) / kScanBlock);
-    b[S_KEYS] = sizeof(int64_t) * (size_t)nd;
-    b[S_SEL] = sizeof(PoolSel);
-    b[S_BLOCKSUM] = b[S_BLOCKOFF] = sizeof(int) * (nb + 1);
-}
+int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
-void level_bytes(int B, int range_cap, int pool_cap, bool mfma, size_t *b) {
-    const size_t nb = (size_t)((range_cap + kScanBlock - 1) / kScanBlock);
-    b[S_BLOCKSUM] = b[S_BLOCKOFF] = sizeof(int) * (nb + 1);
-    b[S_RINFO] = sizeof(RInfo) * (size_t)(range_cap + 1);
-    int nchunk, tpc;
-    if (mfma) {
-        nchunk = mfma_geometry(B, range_cap, pool_cap).nslot;
-        const size_t KS = (size_t)B * B / 16;
-        const size_t ntiles = (size_t)(pool_cap + kDomTile - 1) / kDomTile;
-        b[S_AFRAG] = (size_t)mfma_quads_padded(B, range_cap) * 2 * KS * 1024;
-        b[S_BFRAG] = ntiles * KS * 1024;
-        b[S_DINFO] = ntiles * kDomTile * sizeof(float2);
-    } else {
-        fp32_geometry(B, range_cap, pool_cap, &nchunk, &tpc);
-        const size_t n = (size_t)B * B;
-        b[S_VF32] = n * (size_t)fp32_rpad(range_cap) * 8 * sizeof(float);
-        b[S_DF32] = n * (size_t)fp32_ppad(pool_cap) * sizeof(float);
-        b[S_DINFO] = (size_t)fp32_ppad(pool_cap) * sizeof(float2);
+// One image's share of one level: what the caller hands over.
+struct ImgIn {
+    const fic_image *img;
+    int B, L, pct_num, pct_den, pool_max;
+    fic_pool *pool;
+    const uint32_t *rxy;
+    const int32_t *nr;
+    int range_cap;
+    fic_level_codes *codes;     // NULL for a pool-only plan
+    uint32_t *children;
+    int32_t *nchildren;
+};
+
+struct LevelPlan {
+    std::vector<ImgLvl> h;
+    std::vector<int> pre;       // K_NUM x (n + 1)
+    size_t slot_bytes[S_NUM_SLOTS];
+    size_t table_off;           // offset of this plan's tables in S_TABLES
+    BatchHost bh;
+};
+
+// Fills geometry, block counts and scratch offsets (as byte offsets cast to
+// pointers; bind() rebases them once the slots are allocated).
+void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int engine, int level0) {
+    const int n = (int)in.size();
+    pl.h.assign(n, ImgLvl());
+    pl.pre.assign((size_t)K_NUM * (n + 1), 0);
+    memset(pl.slot_bytes, 0, sizeof(pl.slot_bytes));
+    memset(&pl.bh, 0, sizeof(pl.bh));
+    const int B = in[0].B;
+    const int KS = B * B / 16;
+    const bool mfma = do_search && engine == FIC_ENGINE_MFMA && mfma_supported(B);
+    pl.bh.B = B;
+    pl.bh.L = in[0].L;
+    pl.bh.KS = KS;
+    size_t off[S_NUM_SLOTS] = {0};
+    for (int i = 0; i < n; ++i) {
+        const ImgIn &x = in[i];
+        ImgLvl &d = pl.h[i];
+        memset(&d, 0, sizeof(d));
+        d.pix = x.img->pix;
+        d.W = x.img->width;
+        d.H = x.img->height;
+        d.pitch = x.img->pitch;
+        d.B = x.B;
+        d.L = x.L;
+        d.nx = (d.W - 2 * d.B) / d.L + 1;
+        d.ny = (d.H - 2 * d.B) / d.L + 1;
+        d.nd = d.nx * d.ny;
+        d.c = ((long long)x.pct_num * d.nd + x.pct_den - 1) / x.pct_den;
+        d.pool_max = x.pool_max;
+        d.pool_cap = x.pool->capacity;
+        d.range_cap = x.range_cap;
+        d.pcount = x.pool->count;
+        d.pxy = x.pool->xy;
+        d.pkey = x.pool->key;
+        d.psum4 = x.pool->sum4;
+        d.pa = x.pool->a;
+        d.rxy = x.rxy;
+        d.nr = x.nr;
+        if (x.codes) {
+            d.ccount = x.codes->count;
+            d.cxy = x.codes->xy;
+            d.csplit = x.codes->split;
+            d.cdom = x.codes->domain;
+            d.ciso = x.codes->iso;
+            d.csidx = x.codes->s_idx;
+            d.coff = x.codes->offset;
+            d.cerr = x.codes->err;
+        }
+        d.children = x.children;
+        d.nchildren = x.nchildren;
+        d.mfma = mfma ? 1 : 0;
+        pl.bh.any_cap |= x.pool_max > 0;
+        // block counts
+        int blk[K_NUM] = {0};
+        if (level0) blk[K_LEVEL0] = cdiv((long)(d.W / d.B) * (d.H / d.B), 256);
+        blk[K_KEYS] = cdiv(d.nx, 64) * cdiv(d.ny, 16);
+        blk[K_HIST] = max(1, min(256, cdiv(d.nd, 256)));
+        blk[K_PCMP] = cdiv(d.nd, kScanBlock);
+        blk[K_MOM] = cdiv(d.pool_cap, 4);
+        // pool scratch
+        auto take = [&](Slot s, size_t bytes) {
+            const size_t o = off[s];
+            off[s] += al(bytes);
+            return o;
+        };
+        d.keys = (int64_t *)take(S_KEYS, sizeof(int64_t) * (size_t)d.nd);
+        d.sel = (PoolSel *)take(S_SEL, sizeof(PoolSel));
+        d.pblocksum = (int *)take(S_PBLOCK, sizeof(int) * (size_t)(blk[K_PCMP] + 1));
+        d.pblockoff = (int *)take(S_PBLOCK, sizeof(int) * (size_t)(blk[K_PCMP] + 1));
+        if (do_search) {
+            const int n2 = d.B * d.B;
+            blk[K_RANGE] = cdiv(d.range_cap, 4);
+            blk[K_FINAL] = cdiv(d.range_cap, 4);
+            blk[K_CCMP] = cdiv(d.range_cap, kScanBlock);
+            d.ri = (RInfo *)take(S_RINFO, sizeof(RInfo) * (size_t)(d.range_cap + 1));
+            d.cblocksum = (int *)take(S_CBLOCK, sizeof(int) * (size_t)(blk[K_CCMP] + 1));
+            d.cblockoff = (int *)take(S_CBLOCK, sizeof(int) * (size_t)(blk[K_CCMP] + 1));
+            if (mfma) {
+                d.geo = mfma_geometry(d.B, d.range_cap, d.pool_cap);
+                const int nquads = d.geo.nrg * (d.geo.rpw / 4);
+                const int ntiles = cdiv(d.pool_cap, kDomTile);
+                blk[K_AFRAG] = cdiv((long)nquads * 2 * KS * 64, 256);
+                blk[K_BFRAG] = cdiv((long)ntiles * KS * 64, 256);
+                blk[K_SEARCH] = cdiv(d.geo.nwg, 8) * 8;  // image blocks start at multiples of 8
+                d.nslot = d.geo.nslot;
+                d.afrag = (uint4 *)take(S_AFRAG, (size_t)nquads * 2 * KS * 1024);
+                d.bfrag = (uint4 *)take(S_BFRAG, (size_t)ntiles * KS * 1024);
+                d.dinfo = (float2 *)take(S_DINFO, (size_t)ntiles * kDomTile * sizeof(float2));
+                pl.bh.any_mfma = 1;
+            } else {
+                fp32_geometry(d.B, d.range_cap, d.pool_cap, &d.fnchunk, &d.ftpc);
+                d.rpad = fp32_rpad(d.range_cap);
+                d.ppad = fp32_ppad(d.pool_cap);
+                blk[K_VIEWS] = cdiv((long)n2 * d.rpad, 256);
+                blk[K_DOMS] = cdiv((long)n2 * d.ppad, 256);
+                blk[K_SEARCH] = fp32_blocks(d.B, d.range_cap, d.pool_cap);
+                d.nslot = d.fnchunk;
+                d.vf = (float *)take(S_VF32, (size_t)n2 * d.rpad * 8 * sizeof(float));
+                d.df = (float *)take(S_DF32, (size_t)n2 * d.ppad * sizeof(float));
+                d.dinfo = (float2 *)take(S_DINFO, (size_t)d.ppad * sizeof(float2));
+                pl.bh.any_fp32 = 1;
+            }
+            d.part = (Partial *)take(S_PARTIAL, sizeof(Partial) * (size_t)d.range_cap * d.nslot);
+        }
+        for (int k = 0; k < K_NUM; ++k) pl.pre[(size_t)k * (n + 1) + i + 1] = pl.pre[(size_t)k * (n + 1) + i] + blk[k];
     }
-    b[S_PARTIAL] = sizeof(Partial) * (size_t)range_cap * nchunk;
+    for (int k = 0; k < K_NUM; ++k) pl.bh.blocks[k] = pl.pre[(size_t)k * (n + 1) + n];
+    for (int s = 0; s < S_NUM_SLOTS; ++s) pl.slot_bytes[s] = off[s];
+    pl.bh.dev.n = n;
 }
 
-// ---------------------------------------------------------------- launch bodies
-int do_pool(fic_ctx *ctx, const fic_image *img, int B, int L, fic_ratio pct, int pool_max, fic_pool *out,
-            hipStream_t st) {
-    const int W = img->width, H = img->height;
-    const int nx = (W - 2 * B) / L + 1;
-    const int64_t nd = n_candidates(W, H, B, L);
-    const int64_t c = ((int64_t)pct.num * nd + pct.den - 1) / pct.den;
-    PoolSel *sel = (PoolSel *)sp(ctx, S_SEL);
-    int64_t *keys = (int64_t *)sp(ctx, S_KEYS);
-    mark(ctx, FIC_T_POOL, B, st);
-    FIC_TRY(launch_sel_init(sel, c, pool_max, st));
-    FIC_TRY(launch_pool_keys(img->pix, img->pitch, nx, (int)nd, L, 2 * B, ctx->table, keys, sel, st));
-    FIC_TRY(launch_pool_select(keys, (int)nd, c, pool_max, sel, st));
-    FIC_TRY(launch_pool_compact(keys, (int)nd, nx, L, c, pool_max, sel, (int *)sp(ctx, S_BLOCKSUM),
-                                (int *)sp(ctx, S_BLOCKOFF), out, st));
-    const int cap = (int)(pool_max > 0 && pool_max < nd ? pool_max : nd);
-    FIC_TRY(launch_pool_moments(img->pix, img->pitch, B, cap, out, st));
+size_t table_bytes(const LevelPlan &pl) {
+    return al(sizeof(ImgLvl) * pl.h.size()) + al(sizeof(int) * pl.pre.size());
+}
+
+// Rebase the scratch offsets onto the allocated slots and point the device
+// table at its place in S_TABLES.
+template <class T>
+void rebase(fic_ctx *ctx, T *&p, Slot s) {
+    p = (T *)((char *)ctx->slot[s].ptr + (size_t)p);
+}
+
+void bind(fic_ctx *ctx, LevelPlan &pl) {
+    auto rb = [&](auto &p, Slot s) { rebase(ctx, p, s); };
+    for (auto &d : pl.h) {
+        rb(d.keys, S_KEYS);
+        rb(d.sel, S_SEL);
+        rb(d.pblocksum, S_PBLOCK);
+        rb(d.pblockoff, S_PBLOCK);
+        if (d.nslot > 0) {  // planned with a search
+            rb(d.ri, S_RINFO);
+            rb(d.cblocksum, S_CBLOCK);
+            rb(d.cblockoff, S_CBLOCK);
+            rb(d.part, S_PARTIAL);
+            rb(d.dinfo, S_DINFO);
+            if (d.mfma) {
+                rb(d.afrag, S_AFRAG);
+                rb(d.bfrag, S_BFRAG);
+            } else {
+                rb(d.vf, S_VF32);
+                rb(d.df, S_DF32);
+            }
+        } else {
+            d.ri = nullptr;
+        }
+    }
+    char *base = (char *)ctx->slot[S_TABLES].ptr + pl.table_off;
+    pl.bh.dev.d = (const ImgLvl *)base;
+    pl.bh.dev.pre = (const int *)(base + al(sizeof(ImgLvl) * pl.h.size()));
+}
+
+// Copies every plan's tables to S_TABLES with one async copy from pinned
+// memory; the staging buffer is reused once the previous copy has finished.
+int upload(fic_ctx *ctx, std::vector<LevelPlan> &plans, hipStream_t st) {
+    size_t total = 0;
+    for (auto &pl : plans) total += table_bytes(pl);
+    if (ctx->staging_event) {
+        if (hipEventSynchronize(ctx->staging_event) != hipSuccess) return FIC_E_HIP;
+    }
+    if (ctx->staging_bytes < total) {
+        if (ctx->staging) (void)hipHostFree(ctx->staging);
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+        if (hipHostMalloc(&ctx->staging, total) != hipSuccess) return FIC_E_NOMEM;
+        ctx->staging_bytes = total;
+    }
+    if (!ctx->staging_event && hipEventCreateWithFlags(&ctx->staging_event, hipEventDisableTiming) != hipSuccess)
+        return FIC_E_HIP;
+    for (auto &pl : plans) {
+        char *dst = (char *)ctx->staging + pl.table_off;
+        memcpy(dst, pl.h.data(), sizeof(ImgLvl) * pl.h.size());
+        memcpy(dst + al(sizeof(ImgLvl) * pl.h.size()), pl.pre.data(), sizeof(int) * pl.pre.size());
+    }
+    if (hipMemcpyAsync(ctx->slot[S_TABLES].ptr, ctx->staging, total, hipMemcpyHostToDevice, st) != hipSuccess)
+        return FIC_E_HIP;
+    if (hipEventRecord(ctx->staging_event, st) != hipSuccess) return FIC_E_HIP;
+    return FIC_OK;
+}
+
+// Reserve the largest per-slot need over all plans (levels run one after the
+// other on the stream) plus room for every table.
+int reserve_plans(fic_ctx *ctx, std::vector<LevelPlan> &plans, size_t extra_dec0) {
+    size_t need[S_NUM_SLOTS] = {0};
+    size_t tables = 0;
+    for (auto &pl : plans) {
+        for (int s = 0; s < S_NUM_SLOTS; ++s) need[s] = max(need[s], pl.slot_bytes[s]);
+        pl.table_off = tables;
+        tables += table_bytes(pl);
+    }
+    need[S_TABLES] = tables;
+    need[S_DEC0] = max(need[S_DEC0], extra_dec0);
+    return reserve(ctx, need);
+}
+
+int run_pool(fic_ctx *ctx, LevelPlan &pl, hipStream_t st) {
+    mark(ctx, FIC_T_POOL, pl.bh.B, st);
+    FIC_TRY(launch_pool_b(pl.bh, ctx->table, st));
     mark(ctx, -1, 0, st);
     return FIC_OK;
 }
 
-int do_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, const uint32_t *rxy, const int32_t *nr,
-             int range_cap, int B, SSet ss, fic_ratio rms, int is_last, bool mfma, fic_level_codes *out,
-             uint32_t *children, int32_t *n_children, hipStream_t st) {
-    const int pool_cap = pool->capacity;
-    RInfo *ri = (RInfo *)sp(ctx, S_RINFO);
-    Partial *part = (Partial *)sp(ctx, S_PARTIAL);
-    float2 *dinfo = (float2 *)sp(ctx, S_DINFO);
-    int nchunk, tpc;
-    mark(ctx, FIC_T_PREP, B, st);
-    FIC_TRY(launch_range_info(img->pix, img->pitch, B, rxy, nr, range_cap, ri, st));
-    if (mfma) {
-        nchunk = mfma_geometry(B, range_cap, pool_cap).nslot;
-        FIC_TRY(launch_mfma_prep(img->pix, img->pitch, B, rxy, nr, range_cap, pool, pool_cap, sp(ctx, S_AFRAG),
-                                 sp(ctx, S_BFRAG), dinfo, st));
-        mark(ctx, FIC_T_SEARCH, B, st);
-        FIC_TRY(launch_mfma_search(B, sp(ctx, S_AFRAG), sp(ctx, S_BFRAG), dinfo, ri, nr, range_cap, pool, pool_cap,
-                                   ss, part, st));
-    } else {
-        fp32_geometry(B, range_cap, pool_cap, &nchunk, &tpc);
-        FIC_TRY(launch_fp32_prep(img->pix, img->pitch, B, rxy, nr, range_cap, pool, pool_cap,
-                                 (float *)sp(ctx, S_VF32), (float *)sp(ctx, S_DF32), dinfo, st));
-        mark(ctx, FIC_T_SEARCH, B, st);
-        FIC_TRY(launch_fp32_search(B, (const float *)sp(ctx, S_VF32), (const float *)sp(ctx, S_DF32), dinfo, ri, nr,
-                                   range_cap, pool, pool_cap, ss, part, st));
-    }
-    mark(ctx, FIC_T_FINAL, B, st);
-    FIC_TRY(launch_finalize(img->pix, img->pitch, B, rxy, nr, range_cap, pool, part, nchunk, ss, rms, is_last, out,
-                            st));
-    if (!is_last)
-        FIC_TRY(launch_children(out, range_cap, B, (int *)sp(ctx, S_BLOCKSUM), (int *)sp(ctx, S_BLOCKOFF), children,
-                                n_children, st));
+int run_search(fic_ctx *ctx, LevelPlan &pl, hipStream_t st) {
+    const BatchHost &b = pl.bh;
+    mark(ctx, FIC_T_PREP, b.B, st);
+    FIC_TRY(launch_range_info_b(b, st));
+    if (b.any_mfma) FIC_TRY(launch_mfma_prep_b(b, st));
+    else FIC_TRY(launch_fp32_prep_b(b, st));
+    mark(ctx, FIC_T_SEARCH, b.B, st);
+    if (b.any_mfma) FIC_TRY(launch_mfma_search_b(b, st));
+    else FIC_TRY(launch_fp32_search_b(b, st));
+    mark(ctx, FIC_T_FINAL, b.B, st);
+    FIC_TRY(launch_finalize_b(b, st));
+    if (!b.is_last) FIC_TRY(launch_children_b(b, st));
     mark(ctx, -1, 0, st);
     return FIC_OK;
 }
@@ -429,6 +585,8 @@ void fic_ctx_destroy(fic_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     destroy_timer(ctx->timer);
+    if (ctx->staging_event) (void)hipEventDestroy(ctx->staging_event);
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
     for (int i = 0; i < S_NUM_SLOTS; ++i)
         if (ctx->slot[i].ptr) (void)hipFree(ctx->slot[i].ptr);
     if (ctx->table) (void)hipFree(ctx->table);
@@ -484,11 +642,17 @@ int fic_build_domain_pool(fic_ctx *ctx, const fic_image *img, int32_t B, int32_t
     if (out->capacity < need) return FIC_E_CAPACITY;
     int st = enter(ctx);
     if (st != FIC_OK) return st;
-    size_t b[S_NUM_SLOTS] = {0};
-    pool_bytes(nd, b);
-    st = reserve(ctx, b);
+    std::vector<ImgIn> in(1);
+    in[0] = ImgIn{img, B, L, pct.num, pct.den, pool_max, out, nullptr, nullptr, 0, nullptr, nullptr, nullptr};
+    std::vector<LevelPlan> plans(1);
+    plan_level(plans[0], in, false, FIC_ENGINE_MFMA, 0);
+    st = reserve_plans(ctx, plans, 0);
     if (st != FIC_OK) return st;
-    return do_pool(ctx, img, B, L, pct, pool_max, out, (hipStream_t)stream);
+    bind(ctx, plans[0]);
+    hipStream_t s = (hipStream_t)stream;
+    st = upload(ctx, plans, s);
+    if (st != FIC_OK) return st;
+    return run_pool(ctx, plans[0], s);
 }
 
 int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, const uint32_t *ranges_xy,
@@ -503,20 +667,28 @@ int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, c
     if (out->capacity < range_capacity) return FIC_E_CAPACITY;
     int st = enter(ctx);
     if (st != FIC_OK) return st;
-    const bool mfma = engine == FIC_ENGINE_MFMA && mfma_supported(B);
-    size_t b[S_NUM_SLOTS] = {0};
-    level_bytes(B, range_capacity, pool->capacity, mfma, b);
-    st = reserve(ctx, b);
+    // the search needs no pool scratch: the coarsest step keeps the unused key buffer small
+    std::vector<ImgIn> in(1);
+    in[0] = ImgIn{img, B, B, 0, 1, 0, const_cast<fic_pool *>(pool), ranges_xy, n_ranges, range_capacity, out,
+                  children_xy, n_children};
+    std::vector<LevelPlan> plans(1);
+    plan_level(plans[0], in, true, engine, 0);
+    plans[0].bh.ss = make_sset(s_num, s_count, s_den);
+    plans[0].bh.rms = split_rms;
+    plans[0].bh.is_last = is_last ? 1 : 0;
+    st = reserve_plans(ctx, plans, 0);
     if (st != FIC_OK) return st;
-    return do_level(ctx, img, pool, ranges_xy, n_ranges, range_capacity, B, make_sset(s_num, s_count, s_den),
-                    split_rms, is_last ? 1 : 0, mfma, out, children_xy, n_children, (hipStream_t)stream);
+    bind(ctx, plans[0]);
+    hipStream_t s = (hipStream_t)stream;
+    st = upload(ctx, plans, s);
+    if (st != FIC_OK) return st;
+    return run_search(ctx, plans[0], s);
 }
 
 int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_params *p, fic_pool *pools,
                fic_level_codes *codes, fic_stream stream) {
     if (!ctx || !imgs || n_images < 0 || !p || !pools || !codes) return FIC_E_INVALID;
     const int NL = p->levels;
-    size_t need[S_NUM_SLOTS] = {0};
     // validate everything before the first launch
     for (int i = 0; i < n_images; ++i) {
         const fic_image *img = &imgs[i];
@@ -526,41 +698,44 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
         int64_t pcap[kMaxLevels], rcap[kMaxLevels];
         fic_query_capacity(p, img->width, img->height, pcap, rcap);
         for (int l = 0; l < NL; ++l) {
-            const int B = p->block0 >> l;
             fic_pool *pl = &pools[i * NL + l];
             fic_level_codes *cl = &codes[i * NL + l];
             if (!pool_ok(pl) || !codes_ok(cl)) return FIC_E_INVALID;
             if (pl->capacity < pcap[l] || cl->capacity < rcap[l]) return FIC_E_CAPACITY;
-            size_t b[S_NUM_SLOTS] = {0};
-            pool_bytes(n_candidates(img->width, img->height, B, p->step[l]), b);
-            max_into(need, b);
-            memset(b, 0, sizeof(b));
-            level_bytes(B, (int)rcap[l], pl->capacity, p->engine == FIC_ENGINE_MFMA && mfma_supported(B), b);
-            max_into(need, b);
         }
     }
+    if (n_images == 0) return FIC_OK;
     int st = enter(ctx);
     if (st != FIC_OK) return st;
-    st = reserve(ctx, need);
-    if (st != FIC_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    for (int i = 0; i < n_images; ++i) {
-        const fic_image *img = &imgs[i];
-        const int W = img->width, H = img->height;
-        FIC_TRY(launch_level0(W / p->block0, H / p->block0, p->block0, codes[i * NL].xy, codes[i * NL].count, s));
-        for (int l = 0; l < NL; ++l) {
-            const int B = p->block0 >> l;
-            fic_pool *pl = &pools[i * NL + l];
+    std::vector<LevelPlan> plans(NL);
+    for (int l = 0; l < NL; ++l) {
+        const int B = p->block0 >> l;
+        const bool last = l == NL - 1;
+        std::vector<ImgIn> in(n_images);
+        for (int i = 0; i < n_images; ++i) {
+            const fic_image *img = &imgs[i];
             fic_level_codes *cl = &codes[i * NL + l];
-            st = do_pool(ctx, img, B, p->step[l], p->pool_pct, p->pool_max, pl, s);
-            if (st != FIC_OK) return st;
-            const bool last = l == NL - 1;
-            const int rcap = (W / B) * (H / B);
-            st = do_level(ctx, img, pl, cl->xy, cl->count, rcap, B, make_sset(p->s_num[l], p->s_count[l], p->s_den[l]),
-                          p->split_rms[l], last ? 1 : 0, p->engine == FIC_ENGINE_MFMA && mfma_supported(B), cl,
-                          last ? nullptr : codes[i * NL + l + 1].xy, last ? nullptr : codes[i * NL + l + 1].count, s);
-            if (st != FIC_OK) return st;
+            in[i] = ImgIn{img, B, p->step[l], p->pool_pct.num, p->pool_pct.den, p->pool_max, &pools[i * NL + l],
+                          cl->xy, cl->count, (img->width / B) * (img->height / B), cl,
+                          last ? nullptr : codes[i * NL + l + 1].xy, last ? nullptr : codes[i * NL + l + 1].count};
         }
+        plan_level(plans[l], in, true, p->engine, l == 0);
+        plans[l].bh.ss = make_sset(p->s_num[l], p->s_count[l], p->s_den[l]);
+        plans[l].bh.rms = p->split_rms[l];
+        plans[l].bh.is_last = last ? 1 : 0;
+    }
+    st = reserve_plans(ctx, plans, 0);
+    if (st != FIC_OK) return st;
+    for (auto &pl : plans) bind(ctx, pl);
+    hipStream_t s = (hipStream_t)stream;
+    st = upload(ctx, plans, s);
+    if (st != FIC_OK) return st;
+    FIC_TRY(launch_level0_b(plans[0].bh, s));
+    for (int l = 0; l < NL; ++l) {
+        st = run_pool(ctx, plans[l], s);
+        if (st != FIC_OK) return st;
+        st = run_search(ctx, plans[l], s);
+        if (st != FIC_OK) return st;
     }
     return FIC_OK;
 }

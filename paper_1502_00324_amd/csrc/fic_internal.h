@@ -81,8 +81,8 @@ __host__ __device__ inline int iso_inv(int t) { return t == 1 ? 3 : (t == 3 ? 1 
 // ---------------------------------------------------------------- scratch
 // Scratch slots owned by a context; each grows on demand.
 enum Slot {
-    S_KEYS, S_SEL, S_BLOCKSUM, S_BLOCKOFF, S_RINFO, S_AFRAG, S_BFRAG, S_DINFO, S_PARTIAL,
-    S_VF32, S_DF32, S_DEC0, S_DEC1, S_RANGES0, S_RANGES1, S_COUNTS, S_NUM_SLOTS
+    S_KEYS, S_SEL, S_PBLOCK, S_CBLOCK, S_RINFO, S_AFRAG, S_BFRAG, S_DINFO, S_PARTIAL,
+    S_VF32, S_DF32, S_DEC0, S_TABLES, S_NUM_SLOTS
 };
 
 struct Buf { void *ptr; size_t bytes; };
@@ -99,6 +99,9 @@ struct fic_ctx {
     fic::Buf slot[fic::S_NUM_SLOTS];
     int64_t *table;              // device entropy table
     fic::Timer *timer;           // non-null while stage timing is on
+    void *staging;               // pinned host buffer for the level tables
+    size_t staging_bytes;
+    hipEvent_t staging_event;    // last copy out of the staging buffer
 };
 
 namespace fic {
@@ -110,32 +113,7 @@ int reserve(fic_ctx *ctx, const size_t *bytes);   // bytes[S_NUM_SLOTS], 0 = unt
 void mark(fic_ctx *ctx, int kind, int B, hipStream_t st);
 inline void *sp(fic_ctx *ctx, Slot s) { return ctx->slot[s].ptr; }
 
-// ---------------------------------------------------------------- launchers
-// Each returns hipError_t of the launch; geometry arguments are host values
-// (capacities), live counts are read by the kernels from device memory.
-
-// pool
-hipError_t launch_sel_init(PoolSel *sel, int64_t c, int pool_max, hipStream_t st);
-hipError_t launch_pool_keys(const uint8_t *img, int pitch, int nx, int nd, int L, int dsz, const int64_t *table,
-                            int64_t *keys, PoolSel *sel, hipStream_t st);
-hipError_t launch_pool_select(const int64_t *keys, int nd, int64_t c, int pool_max, PoolSel *sel, hipStream_t st);
-hipError_t launch_pool_compact(const int64_t *keys, int nd, int nx, int L, int64_t c, int pool_max,
-                               const PoolSel *sel, int *blocksum, int *blockoff, fic_pool *pool,
-                               hipStream_t st);
-hipError_t launch_pool_moments(const uint8_t *img, int pitch, int B, int cap, fic_pool *pool, hipStream_t st);
-
-// levels
-hipError_t launch_level0(int nx, int ny, int B, uint32_t *xy, int32_t *count, hipStream_t st);
-hipError_t launch_range_info(const uint8_t *img, int pitch, int B, const uint32_t *xy, const int32_t *n,
-                             int cap, RInfo *ri, hipStream_t st);
-hipError_t launch_finalize(const uint8_t *img, int pitch, int B, const uint32_t *xy, const int32_t *n, int cap,
-                           const fic_pool *pool, const Partial *part, int nchunk, SSet ss, fic_ratio rms,
-                           int is_last, fic_level_codes *out, hipStream_t st);
-hipError_t launch_children(const fic_level_codes *codes, int cap, int B, int *blocksum, int *blockoff,
-                           uint32_t *children, int32_t *n_children, hipStream_t st);
-
-// MFMA engine
-bool mfma_supported(int B);
+// ---------------------------------------------------------------- search geometry
 struct MfmaGeom {
     int rpw;      // ranges per workgroup
     int nrg;      // range groups
@@ -147,26 +125,105 @@ struct MfmaGeom {
     int nwg;      // workgroups
 };
 MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap);
-int mfma_quads_padded(int B, int range_cap);
-hipError_t launch_mfma_prep(const uint8_t *img, int pitch, int B, const uint32_t *rxy, const int32_t *nr,
-                            int range_cap, const fic_pool *pool, int pool_cap, void *afrag, void *bfrag,
-                            float2 *dinfo, hipStream_t st);
-hipError_t launch_mfma_search(int B, const void *afrag, const void *bfrag, const float2 *dinfo,
-                              const RInfo *ri, const int32_t *nr, int range_cap, const fic_pool *pool,
-                              int pool_cap, SSet ss, Partial *part, hipStream_t st);
 
+// ---------------------------------------------------------------- batched levels
+// One quadtree level of a batch of images runs as ~25 launches whatever the
+// number of images: every kernel takes the device table of per-image level
+// state below, and a launch of kind k gives image i the workgroups
+// [pre[k][i], pre[k][i+1]) (found by binary search on the prefix table).
+enum Kind {
+    K_LEVEL0, K_KEYS, K_HIST, K_PCMP, K_MOM, K_RANGE, K_AFRAG, K_BFRAG, K_VIEWS, K_DOMS, K_SEARCH, K_FINAL,
+    K_CCMP, K_NUM
+};
+
+struct ImgLvl {
+    // image
+    const uint8_t *pix;
+    int W, H, pitch;
+    // level geometry: candidates nx * ny = nd at step L, c = ceil(p nd)
+    int B, L, nx, ny, nd, pool_max, pool_cap, range_cap;
+    long long c;
+    // pool (caller buffers)
+    int32_t *pcount;
+    uint32_t *pxy;
+    int64_t *pkey;
+    uint32_t *psum4;
+    int64_t *pa;
+    // ranges in, codes and children out (caller buffers)
+    const uint32_t *rxy;
+    const int32_t *nr;
+    int32_t *ccount;
+    uint32_t *cxy;
+    uint8_t *csplit;
+    uint32_t *cdom;
+    uint8_t *ciso, *csidx, *coff;
+    int64_t *cerr;
+    uint32_t *children;
+    int32_t *nchildren;
+    // scratch slices of this image
+    int64_t *keys;
+    PoolSel *sel;
+    int *pblocksum, *pblockoff, *cblocksum, *cblockoff;
+    RInfo *ri;
+    Partial *part;
+    uint4 *afrag, *bfrag;
+    float2 *dinfo;
+    float *vf, *df;
+    // search geometry of the engine in use
+    int mfma;            // 1 = int8 MFMA engine, 0 = FP32 engine
+    MfmaGeom geo;        // MFMA
+    int rpad, ppad, fnchunk, ftpc;  // FP32
+    int nslot;           // partial results per range
+};
+
+struct BatchDev {
+    const ImgLvl *d;     // device table, n entries
+    const int *pre;      // device prefixes, K_NUM x (n + 1)
+    int n;
+};
+
+__device__ inline int find_img(const int *pre, int n, int b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Host view of one batched level: grid sizes per kind and the device table.
+struct BatchHost {
+    BatchDev dev;
+    int blocks[K_NUM];   // total workgroups per kind
+    int B, L, KS, any_cap, any_fp32, any_mfma;
+    SSet ss;
+    fic_ratio rms;
+    int is_last;
+};
+
+// pool
+hipError_t launch_pool_b(const BatchHost &b, const int64_t *table, hipStream_t st);
+// levels
+hipError_t launch_level0_b(const BatchHost &b, hipStream_t st);
+hipError_t launch_range_info_b(const BatchHost &b, hipStream_t st);
+hipError_t launch_finalize_b(const BatchHost &b, hipStream_t st);
+hipError_t launch_children_b(const BatchHost &b, hipStream_t st);
+// MFMA engine
+bool mfma_supported(int B);
+int mfma_quads_padded(int B, int range_cap);
+hipError_t launch_mfma_prep_b(const BatchHost &b, hipStream_t st);
+hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st);
 // FP32 engine
 void fp32_geometry(int B, int range_cap, int pool_cap, int *nchunk, int *tiles_per_chunk);
 int fp32_rpad(int range_cap);
 int fp32_ppad(int pool_cap);
-hipError_t launch_fp32_prep(const uint8_t *img, int pitch, int B, const uint32_t *rxy, const int32_t *nr,
-                            int range_cap, const fic_pool *pool, int pool_cap, float *vf, float *df,
-                            float2 *dinfo, hipStream_t st);
-hipError_t launch_fp32_search(int B, const float *vf, const float *df, const float2 *dinfo, const RInfo *ri,
-                              const int32_t *nr, int range_cap, const fic_pool *pool, int pool_cap, SSet ss,
-                              Partial *part, hipStream_t st);
+int fp32_blocks(int B, int range_cap, int pool_cap);
+hipError_t launch_fp32_prep_b(const BatchHost &b, hipStream_t st);
+hipError_t launch_fp32_search_b(const BatchHost &b, hipStream_t st);
+// block counts per kind for one image (host)
 
-// decoder
+// decoder (one image)
 hipError_t launch_decode_init(int B, const fic_level_codes *codes, int cap, uint8_t *img, int pitch,
                               hipStream_t st);
 hipError_t launch_decode_iter(int B, const fic_level_codes *codes, int cap, const fic_pool *pool, SSet ss,

@@ -1,5 +1,6 @@
-// Domain pool (Sec. 3, Eq 5-6; Sec. 3.2.1): entropy key per candidate, radix
-// selection of the thresholds on the device, stable compaction in raster order.
+// Domain pool (Sec. 3, Eq 5-6; Sec. 3.2.1) for every image of a batch: entropy
+// key per candidate, radix selection of the thresholds on the device, stable
+// compaction in raster order, domain moments.
 #include "fic_internal.h"
 #include "scan_util.h"
 
@@ -7,30 +8,34 @@ namespace fic {
 
 // ---------------------------------------------------------------- keys
 // G = sum over gray levels of T[count]; a larger G means a lower entropy.
-// One wave per strip: lane l owns candidate column cx = 64*bx + l and slides
-// its window down over S candidate rows.  Each lane keeps a private 256-bin
-// histogram in LDS (layout [bin][lane], no atomics) and updates G
+// One wave per strip: lane l owns candidate column cx = 64 gx + l and slides
+// its window down over kStripRows candidate rows.  Each lane keeps a private
+// 256-bin histogram in LDS (layout [bin][lane], no atomics) and updates G
 // incrementally: adding a pixel whose bin held c adds T[c+1] - T[c].
 constexpr int kStripRows = 16;
 
-__global__ __launch_bounds__(64) void k_pool_keys(const uint8_t *__restrict__ img, int pitch, int nx, int ny, int L,
-                                                  int dsz, const int64_t *__restrict__ T,
-                                                  int64_t *__restrict__ keys, unsigned long long *gmin) {
+__global__ __launch_bounds__(64) void k_pool_keys(BatchDev b, const int64_t *__restrict__ T) {
     __shared__ uint16_t hist[256][64];
     __shared__ int64_t dtab[1025];
+    const int *pre = b.pre + K_KEYS * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
+    const int lb = blockIdx.x - pre[im];
+    const int ngx = (d.nx + 63) / 64;
+    const int gx = lb % ngx, gy = lb / ngx;
     const int lane = threadIdx.x;
-    const int M = dsz * dsz;
+    const int dsz = 2 * d.B, M = dsz * dsz, L = d.L, pitch = d.pitch, nx = d.nx;
     const bool lds_tab = M <= 1024;
     if (lds_tab)
         for (int c = lane; c < M; c += 64) dtab[c] = T[c + 1] - T[c];
     for (int v = 0; v < 256; ++v) hist[v][lane] = 0;
     __syncthreads();
-    const int cx = blockIdx.x * 64 + lane;
-    const int cy0 = blockIdx.y * kStripRows;
-    const int cy1 = min(ny, cy0 + kStripRows);
+    const int cx = gx * 64 + lane;
+    const int cy0 = gy * kStripRows;
+    const int cy1 = min(d.ny, cy0 + kStripRows);
     // inactive lanes stay for the wave reduction below
-    const bool active = cx < nx && cy0 < ny;
-    const uint8_t *col = img + (size_t)(active ? cx : 0) * L;
+    const bool active = cx < nx && cy0 < d.ny;
+    const uint8_t *col = d.pix + (size_t)(active ? cx : 0) * L;
     uint16_t *h = &hist[0][lane];
     auto dlt = [&](int c) -> int64_t { return lds_tab ? dtab[c] : T[c + 1] - T[c]; };
     int64_t g = 0, gm = INT64_MAX;
@@ -55,7 +60,7 @@ __global__ __launch_bounds__(64) void k_pool_keys(const uint8_t *__restrict__ im
     if (active) {
         int ytop = cy0 * L;
         for (int r = 0; r < dsz; ++r) add_row(ytop + r);
-        keys[(size_t)cy0 * nx + cx] = g;
+        d.keys[(size_t)cy0 * nx + cx] = g;
         gm = g;
         for (int cy = cy0 + 1; cy < cy1; ++cy) {
             const int ynew = cy * L;
@@ -69,7 +74,7 @@ __global__ __launch_bounds__(64) void k_pool_keys(const uint8_t *__restrict__ im
                 for (int r = 0; r < dsz; ++r) add_row(ynew + r);
             }
             ytop = ynew;
-            keys[(size_t)cy * nx + cx] = g;
+            d.keys[(size_t)cy * nx + cx] = g;
             gm = min(gm, g);
         }
     }
@@ -78,72 +83,82 @@ __global__ __launch_bounds__(64) void k_pool_keys(const uint8_t *__restrict__ im
         const int64_t o = __shfl_xor(gm, off, 64);
         gm = min(gm, o);
     }
-    if (lane == 0) atomicMin(gmin, (unsigned long long)gm);
+    if (lane == 0) atomicMin(&d.sel->gmin, (unsigned long long)gm);
 }
 
 // ---------------------------------------------------------------- radix select
 // Passes 0..5 pick the key 8 bits at a time (keys < 2^48); passes 6..9 pick
-// the candidate index (< 2^32).  largest = 1 finds the k-th largest key, 0 the
-// k-th smallest (key, index) pair.  filter = 1 restricts to candidates kept by
-// the percentile threshold.
+// the candidate index (< 2^32).  The percentile select finds the c-th largest
+// key; the pool-size select the pool_max-th smallest (key, index) pair among
+// the candidates the percentile keeps.
 __device__ inline bool pct_keep(int64_t key, const PoolSel *sel, int64_t c) {
     if (c == 0) return true;
     const unsigned long long t = sel->pct.key_prefix;
     return (unsigned long long)key < t || (t == sel->gmin && (unsigned long long)key == sel->gmin);
 }
 
-__global__ __launch_bounds__(256) void k_sel_init(PoolSel *sel, int64_t c, int pool_max) {
+__global__ __launch_bounds__(256) void k_sel_init(BatchDev b) {
+    const ImgLvl &d = b.d[blockIdx.x];
+    PoolSel *sel = d.sel;
     const int t = threadIdx.x;
     sel->pct.hist[t] = 0;
     sel->cap.hist[t] = 0;
     if (t == 0) {
         sel->pct.key_prefix = 0;
         sel->pct.idx_prefix = 0;
-        sel->pct.remaining = (int32_t)c;
-        sel->pct.all = c == 0 ? 1 : 0;
+        sel->pct.remaining = (int32_t)d.c;
+        sel->pct.all = d.c == 0 ? 1 : 0;
         sel->cap.key_prefix = 0;
         sel->cap.idx_prefix = 0;
-        sel->cap.remaining = pool_max;
-        sel->cap.all = pool_max == 0 ? 1 : 0;
+        sel->cap.remaining = d.pool_max;
+        sel->cap.all = d.pool_max == 0 ? 1 : 0;
         sel->gmin = ~0ull;
     }
 }
 
-__global__ __launch_bounds__(256) void k_sel_hist(const int64_t *__restrict__ keys, int nd, int pass, int filter,
-                                                  int64_t c, PoolSel *sel, SelState *st) {
+// which = 0: percentile select (all candidates); 1: pool-size select (filtered)
+__global__ __launch_bounds__(256) void k_sel_hist(BatchDev b, int pass, int which) {
     __shared__ uint32_t h[256];
+    const int *pre = b.pre + K_HIST * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
+    const int lb = blockIdx.x - pre[im], nb = pre[im + 1] - pre[im];
+    SelState *st = which ? &d.sel->cap : &d.sel->pct;
     h[threadIdx.x] = 0;
     __syncthreads();
     if (st->all) return;  // uniform: every thread reads the same flag
     const unsigned long long kp = st->key_prefix;
     const uint32_t ip = st->idx_prefix;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < nd; i += gridDim.x * 256) {
-        const int64_t key = keys[i];
-        if (filter && !pct_keep(key, sel, c)) continue;
-        uint32_t d;
+    for (int i = lb * 256 + threadIdx.x; i < d.nd; i += nb * 256) {
+        const int64_t key = d.keys[i];
+        if (which && !pct_keep(key, d.sel, d.c)) continue;
+        uint32_t dg;
         if (pass < 6) {
             const int sh = 40 - 8 * pass;
             if (((unsigned long long)key >> (sh + 8)) != (kp >> (sh + 8))) continue;
-            d = (uint32_t)(((unsigned long long)key >> sh) & 255u);
+            dg = (uint32_t)(((unsigned long long)key >> sh) & 255u);
         } else {
             const int sh = 24 - 8 * (pass - 6);
             if ((unsigned long long)key != kp) continue;
             if (sh < 24 && ((uint32_t)i >> (sh + 8)) != (ip >> (sh + 8))) continue;
-            d = ((uint32_t)i >> sh) & 255u;
+            dg = ((uint32_t)i >> sh) & 255u;
         }
-        atomicAdd(&h[d], 1u);
+        atomicAdd(&h[dg], 1u);
     }
     __syncthreads();
     if (h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ __launch_bounds__(256) void k_sel_pick(int pass, int largest, SelState *st) {
+__global__ __launch_bounds__(256) void k_sel_pick(BatchDev b, int pass, int which) {
     __shared__ uint32_t cum[256];
+    const ImgLvl &d = b.d[blockIdx.x];
+    SelState *st = which ? &d.sel->cap : &d.sel->pct;
+    const int largest = which ? 0 : 1;
     const int t = threadIdx.x;
     if (st->all) return;  // uniform
     // position t in the scan order: descending digits when looking for the largest
-    const int d = largest ? 255 - t : t;
-    const uint32_t cnt = st->hist[d];
+    const int dg = largest ? 255 - t : t;
+    const uint32_t cnt = st->hist[dg];
     cum[t] = cnt;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
@@ -155,59 +170,55 @@ __global__ __launch_bounds__(256) void k_sel_pick(int pass, int largest, SelStat
     const uint32_t incl = cum[t], excl = incl - cnt, total = cum[255];
     const int32_t rem = st->remaining;
     __syncthreads();
-    st->hist[d] = 0;
+    st->hist[dg] = 0;
     if (pass == 0 && total < (uint32_t)rem) {
         if (t == 0) st->all = 1;
         return;
     }
     if (excl < (uint32_t)rem && (uint32_t)rem <= incl) {
         st->remaining = rem - (int32_t)excl;
-        if (pass < 6) st->key_prefix |= (unsigned long long)d << (40 - 8 * pass);
-        else st->idx_prefix |= (uint32_t)d << (24 - 8 * (pass - 6));
+        if (pass < 6) st->key_prefix |= (unsigned long long)dg << (40 - 8 * pass);
+        else st->idx_prefix |= (uint32_t)dg << (24 - 8 * (pass - 6));
     }
 }
 
 // ---------------------------------------------------------------- compaction
-struct PoolPred {
-    const int64_t *keys;
-    const PoolSel *sel;
-    int64_t c;
-    int pool_max;
-    __device__ bool operator()(int i) const {
-        const int64_t key = keys[i];
-        if (!pct_keep(key, sel, c)) return false;
-        if (pool_max == 0 || sel->cap.all) return true;
-        const unsigned long long tk = sel->cap.key_prefix;
-        const uint32_t ti = sel->cap.idx_prefix;
+struct PoolOp {
+    int mult = 1;
+    __device__ int items(const ImgLvl &d) const { return d.nd; }
+    __device__ bool pred(const ImgLvl &d, int i) const {
+        const int64_t key = d.keys[i];
+        if (!pct_keep(key, d.sel, d.c)) return false;
+        if (d.pool_max == 0 || d.sel->cap.all) return true;
+        const unsigned long long tk = d.sel->cap.key_prefix;
+        const uint32_t ti = d.sel->cap.idx_prefix;
         return (unsigned long long)key < tk || ((unsigned long long)key == tk && (uint32_t)i <= ti);
     }
-};
-
-struct PoolEmit {
-    const int64_t *keys;
-    int nx, L;
-    uint32_t *xy;
-    int64_t *key_out;
-    __device__ void operator()(int i, int pos) const {
-        const int cy = i / nx, cx = i - cy * nx;
-        xy[pos] = ((uint32_t)(cy * L) << 16) | (uint32_t)(cx * L);
-        key_out[pos] = keys[i];
+    __device__ void emit(const ImgLvl &d, int i, int pos) const {
+        const int cy = i / d.nx, cx = i - cy * d.nx;
+        d.pxy[pos] = ((uint32_t)(cy * d.L) << 16) | (uint32_t)(cx * d.L);
+        d.pkey[pos] = d.keys[i];
     }
+    __device__ int *sums(const ImgLvl &d) const { return d.pblocksum; }
+    __device__ int *offs(const ImgLvl &d) const { return d.pblockoff; }
+    __device__ int32_t *total(const ImgLvl &d) const { return d.pcount; }
 };
 
 // Per pool entry: sum of the raw pixels and A = n*sum(D4^2) - (sum D4)^2.
-__global__ __launch_bounds__(256) void k_pool_moments(const uint8_t *__restrict__ img, int pitch, int B, int cap,
-                                                      const int32_t *count, const uint32_t *__restrict__ xy,
-                                                      uint32_t *__restrict__ sum4, int64_t *__restrict__ a) {
+__global__ __launch_bounds__(256) void k_pool_moments(BatchDev b) {
+    const int *pre = b.pre + K_MOM * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + w;
-    if (p >= min(*count, cap)) return;
-    const uint32_t v = xy[p];
+    const int p = (blockIdx.x - pre[im]) * 4 + w;
+    if (p >= min(*d.pcount, d.pool_cap)) return;
+    const int B = d.B, pitch = d.pitch;
+    const uint32_t v = d.pxy[p];
     const int x0 = v & 0xffff, y0 = v >> 16;
     int64_t s = 0, ss = 0;
     for (int c = lane; c < B * B; c += 64) {
         const int cy = c / B, cx = c - cy * B;
-        const uint8_t *q = img + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
+        const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
         const int d4 = q[0] + q[1] + q[pitch] + q[pitch + 1];
         s += d4;
         ss += (int64_t)d4 * d4;
@@ -215,52 +226,28 @@ __global__ __launch_bounds__(256) void k_pool_moments(const uint8_t *__restrict_
     s = wave_sum_i64(s);
     ss = wave_sum_i64(ss);
     if (lane == 0) {
-        sum4[p] = (uint32_t)s;
-        a[p] = (int64_t)B * B * ss - s * s;
+        d.psum4[p] = (uint32_t)s;
+        d.pa[p] = (int64_t)B * B * ss - s * s;
     }
 }
 
-// ---------------------------------------------------------------- launchers
-// k_sel_init must run first on the stream: it resets gmin.
-hipError_t launch_pool_keys(const uint8_t *img, int pitch, int nx, int nd, int L, int dsz, const int64_t *table,
-                            int64_t *keys, PoolSel *sel, hipStream_t st) {
-    const int ny = nx > 0 ? nd / nx : 0;
-    const dim3 grid((nx + 63) / 64, (ny + kStripRows - 1) / kStripRows);
-    if (nd > 0) k_pool_keys<<<grid, 64, 0, st>>>(img, pitch, nx, ny, L, dsz, table, keys, &sel->gmin);
-    return hipGetLastError();
-}
-
-hipError_t launch_sel_init(PoolSel *sel, int64_t c, int pool_max, hipStream_t st) {
-    k_sel_init<<<1, 256, 0, st>>>(sel, c, pool_max);
-    return hipGetLastError();
-}
-
-hipError_t launch_pool_select(const int64_t *keys, int nd, int64_t c, int pool_max, PoolSel *sel, hipStream_t st) {
-    const int blocks = max(1, min(1024, (nd + 255) / 256));
-    if (c > 0)
-        for (int pass = 0; pass < 6; ++pass) {
-            k_sel_hist<<<blocks, 256, 0, st>>>(keys, nd, pass, 0, c, sel, &sel->pct);
-            k_sel_pick<<<1, 256, 0, st>>>(pass, 1, &sel->pct);
-        }
-    if (pool_max > 0)
+// ---------------------------------------------------------------- launcher
+hipError_t launch_pool_b(const BatchHost &b, const int64_t *table, hipStream_t st) {
+    const BatchDev &dv = b.dev;
+    k_sel_init<<<dv.n, 256, 0, st>>>(dv);
+    if (b.blocks[K_KEYS] > 0) k_pool_keys<<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table);
+    for (int pass = 0; pass < 6; ++pass) {
+        k_sel_hist<<<b.blocks[K_HIST], 256, 0, st>>>(dv, pass, 0);
+        k_sel_pick<<<dv.n, 256, 0, st>>>(dv, pass, 0);
+    }
+    if (b.any_cap)
         for (int pass = 0; pass < 10; ++pass) {
-            k_sel_hist<<<blocks, 256, 0, st>>>(keys, nd, pass, 1, c, sel, &sel->cap);
-            k_sel_pick<<<1, 256, 0, st>>>(pass, 0, &sel->cap);
+            k_sel_hist<<<b.blocks[K_HIST], 256, 0, st>>>(dv, pass, 1);
+            k_sel_pick<<<dv.n, 256, 0, st>>>(dv, pass, 1);
         }
-    return hipGetLastError();
-}
-
-hipError_t launch_pool_compact(const int64_t *keys, int nd, int nx, int L, int64_t c, int pool_max,
-                               const PoolSel *sel, int *blocksum, int *blockoff, fic_pool *pool, hipStream_t st) {
-    PoolPred pred{keys, sel, c, pool_max};
-    PoolEmit emit{keys, nx, L, pool->xy, pool->key};
-    return compact(nd, nullptr, pred, emit, blocksum, blockoff, pool->count, 1, st);
-}
-
-hipError_t launch_pool_moments(const uint8_t *img, int pitch, int B, int cap, fic_pool *pool, hipStream_t st) {
-    const int blocks = (cap + 3) / 4;
-    if (blocks > 0)
-        k_pool_moments<<<blocks, 256, 0, st>>>(img, pitch, B, cap, pool->count, pool->xy, pool->sum4, pool->a);
+    hipError_t e = compact_b(dv, K_PCMP, b.blocks[K_PCMP], PoolOp{}, st);
+    if (e != hipSuccess) return e;
+    if (b.blocks[K_MOM] > 0) k_pool_moments<<<b.blocks[K_MOM], 256, 0, st>>>(dv);
     return hipGetLastError();
 }
 

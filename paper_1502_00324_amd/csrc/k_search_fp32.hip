@@ -33,18 +33,25 @@ void fp32_geometry(int B, int range_cap, int pool_cap, int *nchunk, int *tiles_p
 int fp32_rpad(int range_cap) { return (range_cap + kF32Ranges - 1) / kF32Ranges * kF32Ranges; }
 int fp32_ppad(int pool_cap) { return (pool_cap + kF32Doms - 1) / kF32Doms * kF32Doms; }
 
-__global__ __launch_bounds__(256) void k_fp32_views(const uint8_t *__restrict__ img, int pitch, int B,
-                                                    const uint32_t *__restrict__ rxy, const int32_t *nr, int cap,
-                                                    int Rpad, float *__restrict__ vf) {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    const int n = B * B;
+int fp32_blocks(int B, int range_cap, int pool_cap) {
+    int nchunk, tpc;
+    fp32_geometry(B, range_cap, pool_cap, &nchunk, &tpc);
+    return (range_cap + kF32Ranges - 1) / kF32Ranges * nchunk;
+}
+
+__global__ __launch_bounds__(256) void k_fp32_views(BatchDev b) {
+    const int *pre = b.pre + K_VIEWS * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
+    const int e = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    const int B = d.B, n = B * B, Rpad = d.rpad;
     if (e >= n * Rpad) return;
     const int j = e / Rpad, r = e - j * Rpad;
     const int cy = j / B, cx = j - cy * B;
-    const bool valid = r < min(*nr, cap);
+    const bool valid = r < min(*d.nr, d.range_cap);
     int x0 = 0, y0 = 0;
     if (valid) {
-        const uint32_t v = rxy[r];
+        const uint32_t v = d.rxy[r];
         x0 = v & 0xffff;
         y0 = v >> 16;
     }
@@ -54,40 +61,35 @@ __global__ __launch_bounds__(256) void k_fp32_views(const uint8_t *__restrict__ 
         if (valid) {
             int sy, sx;
             iso_src(iso_inv(t), B, cy, cx, sy, sx);
-            val = (float)((int)img[(size_t)(y0 + sy) * pitch + x0 + sx] - 128);
+            val = (float)((int)d.pix[(size_t)(y0 + sy) * d.pitch + x0 + sx] - 128);
         }
-        vf[(size_t)e * 8 + t] = val;
+        d.vf[(size_t)e * 8 + t] = val;
     }
 }
 
-__global__ __launch_bounds__(256) void k_fp32_doms(const uint8_t *__restrict__ img, int pitch, int B,
-                                                   const uint32_t *__restrict__ pxy, const int32_t *np, int cap,
-                                                   int Ppad, const uint32_t *__restrict__ sum4,
-                                                   const int64_t *__restrict__ pa, float *__restrict__ df,
-                                                   float2 *__restrict__ dinfo) {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    const int n = B * B;
+__global__ __launch_bounds__(256) void k_fp32_doms(BatchDev b) {
+    const int *pre = b.pre + K_DOMS * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
+    const int e = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    const int B = d.B, n = B * B, Ppad = d.ppad, pitch = d.pitch;
     if (e >= n * Ppad) return;
     const int j = e / Ppad, p = e - j * Ppad;
-    const bool valid = p < min(*np, cap);
+    const bool valid = p < min(*d.pcount, d.pool_cap);
     float val = 0.f;
     if (valid) {
-        const uint32_t v = pxy[p];
+        const uint32_t v = d.pxy[p];
         const int cy = j / B, cx = j - cy * B;
-        const uint8_t *q = img + (size_t)((v >> 16) + 2 * cy) * pitch + (v & 0xffff) + 2 * cx;
+        const uint8_t *q = d.pix + (size_t)((v >> 16) + 2 * cy) * pitch + (v & 0xffff) + 2 * cx;
         val = (float)(q[0] + q[1] + q[pitch] + q[pitch + 1] - 512);
     }
-    df[e] = val;
-    if (j == 0) dinfo[p] = valid ? make_float2((float)sum4[p], sqrt_down((double)pa[p])) : make_float2(0.f, 0.f);
+    d.df[e] = val;
+    if (j == 0)
+        d.dinfo[p] = valid ? make_float2((float)d.psum4[p], sqrt_down((double)d.pa[p])) : make_float2(0.f, 0.f);
 }
 
 template <int B>
-__global__ __launch_bounds__(256) void k_fp32_search(const float *__restrict__ vf, const float *__restrict__ df,
-                                                     const float2 *__restrict__ dinfo, const RInfo *__restrict__ ri,
-                                                     const int32_t *nr, int range_cap, int Rpad, const int32_t *np,
-                                                     int pool_cap, int Ppad, const uint32_t *__restrict__ sum4,
-                                                     const int64_t *__restrict__ pa, SSet ss, int tiles_per_chunk,
-                                                     int nchunk, Partial *__restrict__ part) {
+__global__ __launch_bounds__(256) void k_fp32_search(BatchDev bt, SSet ss) {
     constexpr int n = B * B;
     constexpr int KC = n < 16 ? n : 16;
     constexpr int NKC = n / KC;
@@ -97,12 +99,26 @@ __global__ __launch_bounds__(256) void k_fp32_search(const float *__restrict__ v
     const int tid = threadIdx.x, tr = tid >> 5, td = tid & 31;
     load_sset(sl, ss);
     __syncthreads();
-    const int R = min(*nr, range_cap), P = min(*np, pool_cap);
-    const int rg = blockIdx.x;
-    if (rg * kF32Ranges >= R) return;  // uniform over the block
+    const int *bpre = bt.pre + K_SEARCH * (bt.n + 1);
+    const int im = find_img(bpre, bt.n, blockIdx.x);
+    const ImgLvl &dsc = bt.d[im];
+    const float *__restrict__ vf = dsc.vf;
+    const float *__restrict__ df = dsc.df;
+    const float2 *__restrict__ dinfo = dsc.dinfo;
+    const RInfo *__restrict__ ri = dsc.ri;
+    const uint32_t *__restrict__ sum4 = dsc.psum4;
+    const int64_t *__restrict__ pa = dsc.pa;
+    Partial *__restrict__ part = dsc.part;
+    const int Rpad = dsc.rpad, Ppad = dsc.ppad, tiles_per_chunk = dsc.ftpc, nchunk = dsc.fnchunk;
+    const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap;
+    const int R = min(*dsc.nr, range_cap), P = min(*dsc.pcount, pool_cap);
+    const int lb = blockIdx.x - bpre[im];
+    const int nrg = (range_cap + kF32Ranges - 1) / kF32Ranges;
+    const int rg = lb % nrg;
+    if (lb >= nrg * nchunk || rg * kF32Ranges >= R) return;  // uniform over the block
     const int r = rg * kF32Ranges + tr;
     const bool rvalid = r < R;
-    const int chunk = blockIdx.y;
+    const int chunk = lb / nrg;
     const int ntiles = (P + kF32Doms - 1) / kF32Doms;
     const int t0 = chunk * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
     const RInfo x = ri[rvalid ? r : rg * kF32Ranges];
@@ -183,40 +199,21 @@ __global__ __launch_bounds__(256) void k_fp32_search(const float *__restrict__ v
     }
 }
 
-hipError_t launch_fp32_prep(const uint8_t *img, int pitch, int B, const uint32_t *rxy, const int32_t *nr,
-                            int range_cap, const fic_pool *pool, int pool_cap, float *vf, float *df, float2 *dinfo,
-                            hipStream_t st) {
-    const int n = B * B, Rpad = fp32_rpad(range_cap), Ppad = fp32_ppad(pool_cap);
-    const long nv = (long)n * Rpad, nd = (long)n * Ppad;
-    if (nv > 0) k_fp32_views<<<(unsigned)((nv + 255) / 256), 256, 0, st>>>(img, pitch, B, rxy, nr, range_cap, Rpad, vf);
-    if (nd > 0)
-        k_fp32_doms<<<(unsigned)((nd + 255) / 256), 256, 0, st>>>(img, pitch, B, pool->xy, pool->count, pool_cap,
-                                                                  Ppad, pool->sum4, pool->a, df, dinfo);
+hipError_t launch_fp32_prep_b(const BatchHost &b, hipStream_t st) {
+    if (b.blocks[K_VIEWS] > 0) k_fp32_views<<<b.blocks[K_VIEWS], 256, 0, st>>>(b.dev);
+    if (b.blocks[K_DOMS] > 0) k_fp32_doms<<<b.blocks[K_DOMS], 256, 0, st>>>(b.dev);
     return hipGetLastError();
 }
 
-template <int B>
-static void fp32_launch_t(dim3 grid, hipStream_t st, const float *vf, const float *df, const float2 *dinfo,
-                          const RInfo *ri, const int32_t *nr, int range_cap, const fic_pool *pool, int pool_cap,
-                          SSet ss, int tpc, int nchunk, Partial *part) {
-    k_fp32_search<B><<<grid, 256, 0, st>>>(vf, df, dinfo, ri, nr, range_cap, fp32_rpad(range_cap), pool->count,
-                                           pool_cap, fp32_ppad(pool_cap), pool->sum4, pool->a, ss, tpc, nchunk,
-                                           part);
-}
-
-hipError_t launch_fp32_search(int B, const float *vf, const float *df, const float2 *dinfo, const RInfo *ri,
-                              const int32_t *nr, int range_cap, const fic_pool *pool, int pool_cap, SSet ss,
-                              Partial *part, hipStream_t st) {
-    int nchunk, tpc;
-    fp32_geometry(B, range_cap, pool_cap, &nchunk, &tpc);
-    const dim3 grid((range_cap + kF32Ranges - 1) / kF32Ranges, nchunk);
-    if (grid.x == 0) return hipSuccess;
-    switch (B) {
-        case 2: fp32_launch_t<2>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
-        case 4: fp32_launch_t<4>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
-        case 8: fp32_launch_t<8>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
-        case 16: fp32_launch_t<16>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
-        case 32: fp32_launch_t<32>(grid, st, vf, df, dinfo, ri, nr, range_cap, pool, pool_cap, ss, tpc, nchunk, part); break;
+hipError_t launch_fp32_search_b(const BatchHost &b, hipStream_t st) {
+    const int nb = b.blocks[K_SEARCH];
+    if (nb == 0) return hipSuccess;
+    switch (b.B) {
+        case 2: k_fp32_search<2><<<nb, 256, 0, st>>>(b.dev, b.ss); break;
+        case 4: k_fp32_search<4><<<nb, 256, 0, st>>>(b.dev, b.ss); break;
+        case 8: k_fp32_search<8><<<nb, 256, 0, st>>>(b.dev, b.ss); break;
+        case 16: k_fp32_search<16><<<nb, 256, 0, st>>>(b.dev, b.ss); break;
+        case 32: k_fp32_search<32><<<nb, 256, 0, st>>>(b.dev, b.ss); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -102,10 +102,13 @@ MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap) {
 }
 
 // ---------------------------------------------------------------- operands
-__global__ __launch_bounds__(256) void k_mfma_afrag(const uint8_t *__restrict__ img, int pitch, int B, int KS,
-                                                    const uint32_t *__restrict__ rxy, const int32_t *nr, int cap,
-                                                    int nquads, uint4 *__restrict__ afrag) {
-    const int slot = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
+    const int *pre = b.pre + K_AFRAG * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
+    const int B = d.B, KS = B * B / 16;
+    const int nquads = d.geo.nrg * (d.geo.rpw / 4);
+    const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
     if (slot >= nquads * 2 * KS * 64) return;
     const int lane = slot & 63;
     int rest = slot >> 6;
@@ -116,52 +119,53 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(const uint8_t *__restrict__ 
     const int t = 4 * h + (i & 3);
     const int r = q * 4 + (i >> 2);
     uint32_t w[4] = {0u, 0u, 0u, 0u};
-    if (r < min(*nr, cap)) {
-        const uint32_t v = rxy[r];
+    if (r < min(*d.nr, d.range_cap)) {
+        const uint32_t v = d.rxy[r];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int ti = iso_inv(t), D = 2 * B;
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            const int k = 64 * s + 16 * kg + b;
+        for (int bb = 0; bb < 16; ++bb) {
+            const int k = 64 * s + 16 * kg + bb;
             const int dy = k / D, dx = k - dy * D;
             int sy, sx;
             iso_src(ti, B, dy >> 1, dx >> 1, sy, sx);
-            const int val = (int)img[(size_t)(y0 + sy) * pitch + x0 + sx] - 128;
-            w[b >> 2] |= (uint32_t)(uint8_t)(int8_t)val << (8 * (b & 3));
+            const int val = (int)d.pix[(size_t)(y0 + sy) * d.pitch + x0 + sx] - 128;
+            w[bb >> 2] |= (uint32_t)(uint8_t)(int8_t)val << (8 * (bb & 3));
         }
     }
-    afrag[slot] = make_uint4(w[0], w[1], w[2], w[3]);
+    d.afrag[slot] = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-__global__ __launch_bounds__(256) void k_mfma_bfrag(const uint8_t *__restrict__ img, int pitch, int B, int KS,
-                                                    const uint32_t *__restrict__ pxy, const int32_t *np, int cap,
-                                                    int ntiles, const uint32_t *__restrict__ sum4,
-                                                    const int64_t *__restrict__ pa, uint4 *__restrict__ bfrag,
-                                                    float2 *__restrict__ dinfo) {
-    const int slot = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
+    const int *pre = b.pre + K_BFRAG * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
+    const int B = d.B, KS = B * B / 16;
+    const int ntiles = (d.pool_cap + kDomTile - 1) / kDomTile;
+    const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
     if (slot >= ntiles * KS * 64) return;
     const int lane = slot & 63;
     const int rest = slot >> 6;
     const int s = rest % KS, tile = rest / KS;
     const int j = lane & 15, kg = lane >> 4;
     const int p = tile * kDomTile + j;
-    const bool valid = p < min(*np, cap);
+    const bool valid = p < min(*d.pcount, d.pool_cap);
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     if (valid) {
-        const uint32_t v = pxy[p];
+        const uint32_t v = d.pxy[p];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int D = 2 * B;
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            const int k = 64 * s + 16 * kg + b;
+        for (int bb = 0; bb < 16; ++bb) {
+            const int k = 64 * s + 16 * kg + bb;
             const int dy = k / D, dx = k - dy * D;
-            const int val = (int)img[(size_t)(y0 + dy) * pitch + x0 + dx] - 128;
-            w[b >> 2] |= (uint32_t)(uint8_t)(int8_t)val << (8 * (b & 3));
+            const int val = (int)d.pix[(size_t)(y0 + dy) * d.pitch + x0 + dx] - 128;
+            w[bb >> 2] |= (uint32_t)(uint8_t)(int8_t)val << (8 * (bb & 3));
         }
     }
-    bfrag[slot] = make_uint4(w[0], w[1], w[2], w[3]);
+    d.bfrag[slot] = make_uint4(w[0], w[1], w[2], w[3]);
     if (s == 0 && kg == 0)
-        dinfo[p] = valid ? make_float2((float)sum4[p], sqrt_down((double)pa[p])) : make_float2(0.f, 0.f);
+        d.dinfo[p] = valid ? make_float2((float)d.psum4[p], sqrt_down((double)d.pa[p])) : make_float2(0.f, 0.f);
 }
 
 // ---------------------------------------------------------------- search
@@ -170,12 +174,7 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(const uint8_t *__restrict__ 
 // of DT tiles, double-buffered: the loads for stage s+1 are issued before the
 // MFMAs of stage s and written to the other LDS buffer after them.
 template <int KS, int RQ, int DT>
-__global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afrag, const uint4 *__restrict__ bfrag,
-                                                     const float2 *__restrict__ dinfo, const RInfo *__restrict__ ri,
-                                                     const int32_t *nr, int range_cap, const int32_t *np,
-                                                     int pool_cap, const uint32_t *__restrict__ sum4,
-                                                     const int64_t *__restrict__ pa, SSet ss, int n, MfmaGeom geo,
-                                                     Partial *__restrict__ part) {
+__global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
     constexpr int STAGE = DT * KS * 64;          // uint4 per stage
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
@@ -184,17 +183,32 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
     __shared__ SLds sl;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
+    const int *bpre = bt.pre + K_SEARCH * (bt.n + 1);
+    const int im = find_img(bpre, bt.n, blockIdx.x);
+    const ImgLvl &dsc = bt.d[im];
+    const MfmaGeom geo = dsc.geo;
+    const int lb = blockIdx.x - bpre[im];   // image blocks start at multiples of 8
+    if (lb >= geo.nwg) return;
+    const v4i *__restrict__ afrag = (const v4i *)dsc.afrag;
+    const uint4 *__restrict__ bfrag = dsc.bfrag;
+    const float2 *__restrict__ dinfo = dsc.dinfo;
+    const RInfo *__restrict__ ri = dsc.ri;
+    const uint32_t *__restrict__ sum4 = dsc.psum4;
+    const int64_t *__restrict__ pa = dsc.pa;
+    Partial *__restrict__ part = dsc.part;
+    const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
+    const int32_t *nr = dsc.nr, *np = dsc.pcount;
     int rg, cfirst, cstep, ncs, slot;
     if (geo.xcd) {  // XCD-aware: workgroup w runs on XCD w % 8
-        const int w = blockIdx.x, xcd = w & 7, k = w >> 3, grp = k / geo.nrg;
+        const int w = lb, xcd = w & 7, k = w >> 3, grp = k / geo.nrg;
         rg = k % geo.nrg;
         cfirst = xcd + 8 * grp * geo.G;
         cstep = 8;
         ncs = geo.G;
         slot = xcd + 8 * grp;
     } else {
-        rg = blockIdx.x % geo.nrg;
-        cfirst = slot = blockIdx.x / geo.nrg;
+        rg = lb % geo.nrg;
+        cfirst = slot = lb / geo.nrg;
         cstep = 1;
         ncs = 1;
     }
@@ -342,44 +356,24 @@ __global__ __launch_bounds__(256) void k_mfma_search(const v4i *__restrict__ afr
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_mfma_prep(const uint8_t *img, int pitch, int B, const uint32_t *rxy, const int32_t *nr,
-                            int range_cap, const fic_pool *pool, int pool_cap, void *afrag, void *bfrag,
-                            float2 *dinfo, hipStream_t st) {
-    const int KS = B * B / 16;
-    const int nquads = mfma_quads_padded(B, range_cap);
-    const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
-    const long na = (long)nquads * 2 * KS * 64, nb = (long)ntiles * KS * 64;
-    if (na > 0)
-        k_mfma_afrag<<<(unsigned)((na + 255) / 256), 256, 0, st>>>(img, pitch, B, KS, rxy, nr, range_cap, nquads,
-                                                                   (uint4 *)afrag);
-    if (nb > 0)
-        k_mfma_bfrag<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(img, pitch, B, KS, pool->xy, pool->count,
-                                                                   pool_cap, ntiles, pool->sum4, pool->a,
-                                                                   (uint4 *)bfrag, dinfo);
+hipError_t launch_mfma_prep_b(const BatchHost &b, hipStream_t st) {
+    if (b.blocks[K_AFRAG] > 0) k_mfma_afrag<<<b.blocks[K_AFRAG], 256, 0, st>>>(b.dev);
+    if (b.blocks[K_BFRAG] > 0) k_mfma_bfrag<<<b.blocks[K_BFRAG], 256, 0, st>>>(b.dev);
     return hipGetLastError();
 }
 
 template <int KS, int RQ, int DT>
-static hipError_t launch_search_t(const MfmaGeom &g, hipStream_t st, const void *afrag, const void *bfrag,
-                                  const float2 *dinfo, const RInfo *ri, const int32_t *nr, int range_cap,
-                                  const fic_pool *pool, int pool_cap, SSet ss, int n, Partial *part) {
-    k_mfma_search<KS, RQ, DT><<<g.nwg, 256, 0, st>>>((const v4i *)afrag, (const uint4 *)bfrag, dinfo, ri, nr,
-                                                     range_cap, pool->count, pool_cap, pool->sum4, pool->a, ss, n,
-                                                     g, part);
+static hipError_t launch_search_t(const BatchHost &b, hipStream_t st) {
+    k_mfma_search<KS, RQ, DT><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
     return hipGetLastError();
 }
 
-hipError_t launch_mfma_search(int B, const void *afrag, const void *bfrag, const float2 *dinfo, const RInfo *ri,
-                              const int32_t *nr, int range_cap, const fic_pool *pool, int pool_cap, SSet ss,
-                              Partial *part, hipStream_t st) {
-    const MfmaGeom g = mfma_geometry(B, range_cap, pool_cap);
-    if (g.nrg == 0) return hipSuccess;
-    const int n = B * B;
+hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
+    if (b.blocks[K_SEARCH] == 0) return hipSuccess;
+    const int B = b.B;
     const Shape sh = mfma_shape(B);
-#define FIC_SEARCH(KS, RQ, DT)                                                                                  \
-    if (sh.rq == RQ && sh.dt == DT)                                                                             \
-        return launch_search_t<KS, RQ, DT>(g, st, afrag, bfrag, dinfo, ri, nr, range_cap, pool, pool_cap, ss, n, \
-                                           part)
+#define FIC_SEARCH(KS, RQ, DT) \
+    if (sh.rq == RQ && sh.dt == DT) return launch_search_t<KS, RQ, DT>(b, st)
     if (B == 4) {
         FIC_SEARCH(1, 2, 16);
         FIC_SEARCH(1, 1, 16);
@@ -393,8 +387,8 @@ hipError_t launch_mfma_search(int B, const void *afrag, const void *bfrag, const
         FIC_SEARCH(16, 1, 1);
         FIC_SEARCH(16, 1, 2);
     }
-    return hipErrorInvalidValue;
 #undef FIC_SEARCH
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fic

@@ -39,51 +39,85 @@ __device__ inline int block_sum_256(int v) {
     return total;
 }
 
-// ---- stable compaction: items [0, n) in kScanBlock chunks, 4 consecutive per thread
-template <class Pred>
-__global__ __launch_bounds__(256) void k_flag_count(int n_cap, const int32_t *n_dev, Pred pred, int *blocksum) {
-    const int n = n_dev ? min(*n_dev, n_cap) : n_cap;
-    const int base = blockIdx.x * kScanBlock + threadIdx.x * 4;
+// ---- batched stable compaction: image i owns flattened blocks
+// [pre[i], pre[i+1]) of kScanBlock items each, 4 consecutive per thread.
+// Op supplies items(d), pred(d, idx), emit(d, idx, pos), sums(d), offs(d),
+// total(d) and mult.
+template <class Op>
+__global__ __launch_bounds__(256) void k_bcount(BatchDev b, int kind, Op op) {
+    const int *pre = b.pre + kind * (b.n + 1);
+    const int i = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[i];
+    const int lb = blockIdx.x - pre[i];
+    const int n = op.items(d);
+    const int base = lb * kScanBlock + threadIdx.x * 4;
     int c = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-        if (base + j < n && pred(base + j)) ++c;
+        if (base + j < n && op.pred(d, base + j)) ++c;
     c = block_sum_256(c);
-    if (threadIdx.x == 0) blocksum[blockIdx.x] = c;
+    if (threadIdx.x == 0) op.sums(d)[lb] = c;
 }
 
-// One 1024-thread block: exclusive offsets of nb block counts, total * mult to
-// *total_out (written also when nb == 0).
-hipError_t launch_scan_blocks(int nb, const int *blocksum, int *blockoff, int32_t *total_out, int mult,
-                              hipStream_t st);
+// One 1024-thread workgroup per image: exclusive block offsets, total * mult.
+template <class Op>
+__global__ __launch_bounds__(1024) void k_bscan(BatchDev b, int kind, Op op) {
+    __shared__ int wsum[16];
+    __shared__ int carry_s;
+    const int *pre = b.pre + kind * (b.n + 1);
+    const ImgLvl &d = b.d[blockIdx.x];
+    const int nb = pre[blockIdx.x + 1] - pre[blockIdx.x];
+    const int *sums = op.sums(d);
+    int *offs = op.offs(d);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) carry_s = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int v = base + t < nb ? sums[base + t] : 0;
+        const int incl = wave_incl_scan(v);
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int before = 0, all = 0;
+        for (int k = 0; k < 16; ++k) {
+            before += k < w ? wsum[k] : 0;
+            all += wsum[k];
+        }
+        const int carry = carry_s;
+        if (base + t < nb) offs[base + t] = carry + before + incl - v;
+        __syncthreads();
+        if (t == 0) carry_s = carry + all;
+        __syncthreads();
+    }
+    if (t == 0) *op.total(d) = carry_s * op.mult;
+}
 
-template <class Pred, class Emit>
-__global__ __launch_bounds__(256) void k_flag_scatter(int n_cap, const int32_t *n_dev, Pred pred, const int *blockoff,
-                                                      Emit emit) {
-    const int n = n_dev ? min(*n_dev, n_cap) : n_cap;
-    const int base = blockIdx.x * kScanBlock + threadIdx.x * 4;
+template <class Op>
+__global__ __launch_bounds__(256) void k_bscatter(BatchDev b, int kind, Op op) {
+    const int *pre = b.pre + kind * (b.n + 1);
+    const int i = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[i];
+    const int lb = blockIdx.x - pre[i];
+    const int n = op.items(d);
+    const int base = lb * kScanBlock + threadIdx.x * 4;
     bool f[4];
     int c = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        f[j] = base + j < n && pred(base + j);
+        f[j] = base + j < n && op.pred(d, base + j);
         c += f[j] ? 1 : 0;
     }
     int total;
-    int pos = blockoff[blockIdx.x] + block_excl_scan_256(c, &total);
+    int pos = op.offs(d)[lb] + block_excl_scan_256(c, &total);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-        if (f[j]) emit(base + j, pos++);
+        if (f[j]) op.emit(d, base + j, pos++);
 }
 
-template <class Pred, class Emit>
-hipError_t compact(int n_cap, const int32_t *n_dev, Pred pred, Emit emit, int *blocksum, int *blockoff,
-                   int32_t *total_out, int mult, hipStream_t st) {
-    const int nb = (n_cap + kScanBlock - 1) / kScanBlock;
-    if (nb > 0) k_flag_count<Pred><<<nb, 256, 0, st>>>(n_cap, n_dev, pred, blocksum);
-    hipError_t e = launch_scan_blocks(nb, blocksum, blockoff, total_out, mult, st);
-    if (e != hipSuccess) return e;
-    if (nb > 0) k_flag_scatter<Pred, Emit><<<nb, 256, 0, st>>>(n_cap, n_dev, pred, blockoff, emit);
+template <class Op>
+hipError_t compact_b(const BatchDev &b, int kind, int blocks, Op op, hipStream_t st) {
+    if (blocks > 0) k_bcount<Op><<<blocks, 256, 0, st>>>(b, kind, op);
+    k_bscan<Op><<<b.n, 1024, 0, st>>>(b, kind, op);
+    if (blocks > 0) k_bscatter<Op><<<blocks, 256, 0, st>>>(b, kind, op);
     return hipGetLastError();
 }
 
