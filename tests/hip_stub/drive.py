@@ -1,0 +1,152 @@
+"""Runs libfic.so's host logic against the stub HIP runtime (started by
+tests/test_host_logic.py with LD_LIBRARY_PATH pointing at the stub).
+
+Every batched launch is checked against the per-kind workgroup prefix table
+that the library uploaded for it: the grid must cover exactly the planned
+workgroups, the prefixes must be non-decreasing, and each image's share of
+the MFMA search must start on a multiple of 8 workgroups (the XCD mapping
+relies on it).  Prints one JSON object with the results of each scenario.
+"""
+import ctypes
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from paper_1502_00324_amd import fic  # noqa: E402
+from paper_1502_00324_amd.synth import make_image  # noqa: E402
+
+K_LEVEL0, K_KEYS, K_HIST, K_PCMP, K_MOM, K_RANGE, K_AFRAG, K_BFRAG, K_VIEWS, K_DOMS, K_SEARCH, K_FINAL, K_CCMP = \
+    range(13)
+KIND_OF = [("k_level0", K_LEVEL0), ("k_pool_keys", K_KEYS), ("k_sel_hist", K_HIST), ("k_pool_moments", K_MOM),
+           ("k_range_info", K_RANGE), ("k_mfma_afrag", K_AFRAG), ("k_mfma_bfrag", K_BFRAG),
+           ("k_fp32_views", K_VIEWS), ("k_fp32_doms", K_DOMS), ("k_mfma_search", K_SEARCH),
+           ("k_fp32_search", K_SEARCH), ("k_finalize", K_FINAL)]
+PER_IMAGE = ("k_sel_init", "k_sel_pick", "k_bscan")
+KIND_ARG = ("k_bcount", "k_bscatter")
+NUM_KINDS = 13
+
+
+class BatchDev(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_void_p), ("pre", ctypes.POINTER(ctypes.c_int32)), ("n", ctypes.c_int32)]
+
+
+HOOK = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_uint, ctypes.c_uint, ctypes.POINTER(ctypes.c_void_p))
+log = {"launches": [], "errors": []}
+
+
+def on_launch(name, grid, block, args):
+    name = name.decode()
+    short = next((k for k, _ in KIND_OF if k in name), None) or next(
+        (k for k in PER_IMAGE + KIND_ARG if k in name), None)
+    if short is None:
+        log["launches"].append((name, grid, None))
+        return
+    bd = ctypes.cast(args[0], ctypes.POINTER(BatchDev)).contents
+    n = bd.n
+    pre = np.ctypeslib.as_array(bd.pre, shape=(NUM_KINDS * (n + 1),)).reshape(NUM_KINDS, n + 1).copy()
+    if (np.diff(pre, axis=1) < 0).any() or (pre[:, 0] != 0).any():
+        log["errors"].append("%s: prefix table not a prefix sum" % short)
+    if short in PER_IMAGE:
+        want, kind = n, None
+    elif short in KIND_ARG:
+        kind = ctypes.cast(args[1], ctypes.POINTER(ctypes.c_int32)).contents.value
+        want = pre[kind, n]
+    else:
+        kind = dict(KIND_OF)[short]
+        want = pre[kind, n]
+        if short == "k_finalize":
+            want = max(1, want)
+        if short == "k_mfma_search" and (pre[kind] % 8 != 0).any():
+            log["errors"].append("k_mfma_search: an image's workgroups do not start on a multiple of 8")
+    if grid != want:
+        log["errors"].append("%s: grid %d, planned %d" % (short, grid, want))
+    log["launches"].append((short, grid, kind))
+
+
+def buffers(keep, shape_caps):
+    P, R = shape_caps
+
+    def buf(m, dt):
+        a = np.zeros(max(m, 1), dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    cnt = np.zeros(1, np.int32)
+    keep.append(cnt)
+    pool = fic.PoolC(P, buf(1, np.int32), buf(P, np.uint32), buf(P, np.int64), buf(P, np.uint32), buf(P, np.int64))
+    codes = fic.CodesC(R, cnt.ctypes.data, buf(R, np.uint32), buf(R, np.uint8), buf(R, np.uint32), buf(R, np.uint8),
+                       buf(R, np.uint8), buf(R, np.uint8), buf(R, np.int64))
+    return pool, codes, cnt
+
+
+def encode_case(L, h, shapes, levels, engine, pool_max=0, reps=2, timing_toggle=False):
+    keep = []
+    images = [make_image(11 + i, w, hh, 8) for i, (w, hh) in enumerate(shapes)]
+    keep += images
+    p = fic.make_params(levels, pool_max=pool_max, engine=engine)
+    n, NL = len(images), p.levels
+    imgs = (fic.Image * max(n, 1))(*[fic.Image(im.ctypes.data, im.shape[1], im.shape[0], im.shape[1])
+                                     for im in images])
+    pools = (fic.PoolC * max(n * NL, 1))()
+    codes = (fic.CodesC * max(n * NL, 1))()
+    for i, im in enumerate(images):
+        pc = np.zeros(4, np.int64)
+        rc = np.zeros(4, np.int64)
+        L.fic_query_capacity(ctypes.byref(p), im.shape[1], im.shape[0], pc.ctypes.data, rc.ctypes.data)
+        for l in range(NL):
+            pools[i * NL + l], codes[i * NL + l], cnt = buffers(keep, (int(pc[l]), int(rc[l])))
+            cnt[0] = int(rc[l])     # the kernels do not run: pretend every range splits
+    statuses = []
+    for r in range(reps):
+        if timing_toggle:
+            L.fic_ctx_set_timing(h, 1)
+        statuses.append(L.fic_encode(h, imgs, n, ctypes.byref(p), pools, codes, None))
+        if timing_toggle:
+            t = fic.Timing()
+            statuses.append(L.fic_ctx_read_timing(h, ctypes.byref(t)))
+            L.fic_ctx_set_timing(h, 0)
+    return statuses
+
+
+def main():
+    L = fic.lib()
+    hook = HOOK(on_launch)
+    L.mock_set_hook(hook)
+    L.mock_launches.restype = ctypes.c_long
+    h = ctypes.c_void_p()
+    assert L.fic_ctx_create(ctypes.byref(h), 0) == 0
+    out = {}
+
+    def scenario(name, fn):
+        log["launches"], log["errors"] = [], []
+        st = fn()
+        out[name] = {"status": st, "errors": list(log["errors"]), "launches": list(log["launches"])}
+
+    M, F = fic.ENGINE_MFMA, fic.ENGINE_FP32
+    mixed = [(128, 128), (256, 128), (64, 128), (1024, 512), (96, 96), (512, 512), (32, 32), (208, 144)]
+    scenario("single_mfma", lambda: encode_case(L, h, [(64, 64)], [(8, 1), (4, 1)], M))
+    scenario("single_fp32", lambda: encode_case(L, h, [(64, 64)], [(8, 1), (4, 1)], F))
+    scenario("mixed_mfma_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], M))
+    scenario("mixed_fp32_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], F))
+    scenario("mixed_b32_4lv", lambda: encode_case(L, h, [(256, 256), (128, 64), (64, 64)],
+                                                  [(32, 4), (16, 4), (8, 4), (4, 4)], M))
+    scenario("paper_b2_cap", lambda: encode_case(L, h, [(64, 64), (32, 48)], [(16, 4), (8, 4), (4, 4), (2, 4)], M,
+                                                 pool_max=64))
+    scenario("min_images", lambda: encode_case(L, h, [(8, 8), (16, 8)], [(4, 1)], M))
+    scenario("timing_toggle", lambda: encode_case(L, h, mixed[:3], [(16, 2), (8, 2)], M, reps=3,
+                                                  timing_toggle=True))
+    scenario("empty_batch", lambda: encode_case(L, h, [], [(8, 1), (4, 1)], M))
+    L.fic_ctx_set_scratch_limit(h, 1 << 10)
+    scenario("over_limit", lambda: encode_case(L, h, [(1024, 1024)], [(8, 1), (4, 1)], M, reps=1))
+    L.fic_ctx_set_scratch_limit(h, 0)
+    L.fic_ctx_destroy(h)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,79 @@
+"""Host logic of libfic.so on the CPU: the library is bound to a stub HIP
+runtime (tests/hip_stub) in a child process, so its planning, scratch
+binding, table upload, launch geometry and context life cycle run without a
+GPU while no kernel executes.  The kernels themselves are covered by the GPU
+parity tests."""
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+STUB = os.path.join(HERE, "hip_stub")
+LIB = os.path.join(ROOT, "paper_1502_00324_amd", "libfic.so")
+
+
+@pytest.fixture(scope="module")
+def runs(tmp_path_factory):
+    if not os.path.exists(LIB):
+        pytest.skip("libfic.so is not built")
+    if not shutil.which("g++") or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("no host compiler or HIP headers")
+    d = tmp_path_factory.mktemp("hipstub")
+    so = str(d / "libamdhip64.so.7")
+    subprocess.run(["g++", "-O1", "-fPIC", "-shared", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    "-Wl,--version-script=" + os.path.join(STUB, "stub.map"), "-Wl,-soname,libamdhip64.so.7",
+                    os.path.join(STUB, "stub.cpp"), "-o", so], check=True)
+    env = dict(os.environ, LD_LIBRARY_PATH=str(d))
+    r = subprocess.run([sys.executable, "-X", "faulthandler", os.path.join(STUB, "drive.py")], env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+SCENARIOS = ["single_mfma", "single_fp32", "mixed_mfma_3lv", "mixed_fp32_3lv", "mixed_b32_4lv", "paper_b2_cap",
+             "min_images", "timing_toggle"]
+
+
+@pytest.mark.parametrize("name", SCENARIOS)
+def test_launch_grids_match_plans(runs, name):
+    s = runs[name]
+    assert all(v == 0 for v in s["status"]), s["status"]
+    assert s["errors"] == []
+    assert len(s["launches"]) > 0
+
+
+def kinds(s):
+    return [k for (k, _, _) in s["launches"]]
+
+
+def test_one_launch_set_per_level(runs):
+    # a batch of 8 images runs the same kernels as a batch of one
+    k8, k1 = kinds(runs["mixed_mfma_3lv"]), kinds(runs["single_mfma"])
+    per_rep8 = len(k8) // 2
+    assert k8.count("k_mfma_search") == 2 * 3 and k1.count("k_mfma_search") == 2 * 2
+    assert k8.count("k_level0") == 2
+    assert per_rep8 < 120
+
+
+def test_engine_choice(runs):
+    assert "k_fp32_search" not in kinds(runs["mixed_mfma_3lv"])
+    assert "k_mfma_search" not in kinds(runs["mixed_fp32_3lv"])
+    # B=32 and B=2 levels take the FP32 engine even when MFMA is asked for
+    assert "k_fp32_search" in kinds(runs["mixed_b32_4lv"]) and "k_mfma_search" in kinds(runs["mixed_b32_4lv"])
+    assert "k_fp32_search" in kinds(runs["paper_b2_cap"])
+
+
+def test_pool_size_select_runs_only_with_a_cap(runs):
+    per_level_uncapped = kinds(runs["single_mfma"]).count("k_sel_hist") // (2 * 2)
+    per_level_capped = kinds(runs["paper_b2_cap"]).count("k_sel_hist") // (2 * 4)
+    assert per_level_uncapped == 6 and per_level_capped == 16
+
+
+def test_empty_batch_and_scratch_limit(runs):
+    assert runs["empty_batch"]["status"] == [0, 0] and runs["empty_batch"]["launches"] == []
+    assert runs["over_limit"]["status"] == [-2] and runs["over_limit"]["launches"] == []
