@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3_1024")
+    ap.add_argument("--engine", default="mfma", choices=["mfma", "mfma_i8", "mfma_f16"],
+                    help="matrix engine of the timed steps (mfma = the faster form per block size)")
     ap.add_argument("--fp32-steps", type=int, default=2, help="timed steps of the plain FP32 engine (0 skips)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample budget (0 skips)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -118,7 +120,8 @@ def main():
     ctx = fic.Context(0)
     mk = lambda engine: fic.make_params(wl.levels, pct=wl.pct, pool_max=wl.pool_max, s_num=wl.s_num,
                                         s_den=wl.s_den, split_rms=wl.split_rms, engine=engine)
-    p = mk(fic.ENGINE_MFMA)
+    engine = {"mfma": fic.ENGINE_MFMA, "mfma_i8": fic.ENGINE_MFMA_I8, "mfma_f16": fic.ENGINE_MFMA_F16}[args.engine]
+    p = mk(engine)
     bufs = ctx.alloc_encode([(im.shape[1], im.shape[0]) for im in images], p, dev)
     for _ in range(args.warmup):
         ctx.encode(imgs, p, bufs)

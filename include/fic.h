@@ -54,7 +54,15 @@ enum {
     FIC_E_ARCH = -5       /* the device is not gfx950 */
 };
 
-enum { FIC_ENGINE_MFMA = 0, FIC_ENGINE_FP32 = 1 };
+/* Search engines; all give identical codes.
+ *   MFMA:     matrix cores, the faster form per block size: MFMA_F16 at
+ *             B = 4, MFMA_I8 at B = 8 and 16; FP32 for B = 2 and B = 32.
+ *   FP32:     plain vector FP32 with the same exact epilogue (baseline).
+ *   MFMA_I8:  int8 matrix cores for B = 4, 8, 16 (raw pixels at B = 4,
+ *             decimated hi/lo planes above); FP32 elsewhere.
+ *   MFMA_F16: f16 matrix cores with exact f32 accumulation over the B^2
+ *             decimated positions for B = 4, 8, 16; FP32 elsewhere. */
+enum { FIC_ENGINE_MFMA = 0, FIC_ENGINE_FP32 = 1, FIC_ENGINE_MFMA_I8 = 2, FIC_ENGINE_MFMA_F16 = 3 };
 enum { FIC_MAX_LEVELS = 4, FIC_MAX_S = 32 };
 
 typedef struct fic_ctx fic_ctx;
@@ -76,7 +84,7 @@ typedef struct {
     int32_t s_den[FIC_MAX_LEVELS];   /* 1..1024 */
     int32_t s_num[FIC_MAX_LEVELS][FIC_MAX_S]; /* strictly ascending, 0 <= num <= den */
     fic_ratio split_rms[FIC_MAX_LEVELS]; /* split iff RMS error > num/den; den 1..16; unused at the last level */
-    int32_t engine;                  /* FIC_ENGINE_MFMA (default) or FIC_ENGINE_FP32 */
+    int32_t engine;                  /* FIC_ENGINE_MFMA (default), _FP32, _MFMA_I8 or _MFMA_F16 */
 } fic_params;
 
 /* Domain pool of one level (Sec. 3.3: the domain address is the list index).

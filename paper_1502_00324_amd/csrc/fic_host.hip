@@ -121,6 +121,8 @@ void build_table() {
 // ---------------------------------------------------------------- validation
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+bool engine_ok(int e) { return e >= FIC_ENGINE_MFMA && e <= FIC_ENGINE_MFMA_F16; }
+
 int check_sset(const int32_t *num, int count, int den) {
     if (!num || count < 1 || count > kMaxS || den < 1 || den > 1024) return FIC_E_INVALID;
     for (int k = 0; k < count; ++k) {
@@ -196,8 +198,16 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
     memset(&pl.bh, 0, sizeof(pl.bh));
     const int B = in[0].B;
     const int KS = B * B / 16;
-    const bool mfma = do_search && engine == FIC_ENGINE_MFMA && mfma_supported(B);
+    // the matrix engine measured fastest per block size: f16 at B = 4 (no
+    // replicated operands), int8 hi/lo planes at B = 8 and 16
+    const int eng = !do_search                                             ? E_FP32
+                    : engine == FIC_ENGINE_MFMA && B == 4                  ? E_F16
+                    : engine == FIC_ENGINE_MFMA && mfma_supported(B)       ? E_I8
+                    : engine == FIC_ENGINE_MFMA_I8 && mfma_supported(B)    ? E_I8
+                    : engine == FIC_ENGINE_MFMA_F16 && f16_supported(B)    ? E_F16
+                                                                           : E_FP32;
     pl.bh.B = B;
+    pl.bh.eng = eng;
     pl.bh.L = in[0].L;
     pl.bh.KS = KS;
     size_t off[S_NUM_SLOTS] = {0};
@@ -237,7 +247,7 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
         }
         d.children = x.children;
         d.nchildren = x.nchildren;
-        d.mfma = mfma ? 1 : 0;
+        d.eng = eng;
         pl.bh.any_cap |= x.pool_max > 0;
         // block counts
         int blk[K_NUM] = {0};
@@ -264,18 +274,21 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
             d.ri = (RInfo *)take(S_RINFO, sizeof(RInfo) * (size_t)(d.range_cap + 1));
             d.cblocksum = (int *)take(S_CBLOCK, sizeof(int) * (size_t)(blk[K_CCMP] + 1));
             d.cblockoff = (int *)take(S_CBLOCK, sizeof(int) * (size_t)(blk[K_CCMP] + 1));
-            if (mfma) {
-                d.geo = mfma_geometry(d.B, d.range_cap, d.pool_cap);
+            if (eng != E_FP32) {
+                // int8: A fragments per quad and half; f16: per quad (32 rows)
+                const bool f16 = eng == E_F16;
+                d.geo = f16 ? f16_geometry(d.B, d.range_cap, d.pool_cap) : mfma_geometry(d.B, d.range_cap, d.pool_cap);
                 const int nquads = d.geo.nrg * (d.geo.rpw / 4);
-                const int ntiles = cdiv(d.pool_cap, kDomTile);
-                blk[K_AFRAG] = cdiv((long)nquads * 2 * KS * 64, 256);
-                blk[K_BFRAG] = cdiv((long)ntiles * KS * 64, 256);
+                const int tile = f16 ? kDomTile32 : kDomTile;
+                const int ntiles = cdiv(d.pool_cap, tile);
+                const long afr = (long)nquads * (f16 ? 1 : 2) * d.geo.ka;   // 1 KiB fragments
+                blk[K_AFRAG] = cdiv(afr * 64, 256);
+                blk[K_BFRAG] = cdiv((long)ntiles * d.geo.kt * 64, 256);
                 blk[K_SEARCH] = cdiv(d.geo.nwg, 8) * 8;  // image blocks start at multiples of 8
                 d.nslot = d.geo.nslot;
-                d.afrag = (uint4 *)take(S_AFRAG, (size_t)nquads * 2 * KS * 1024);
-                d.bfrag = (uint4 *)take(S_BFRAG, (size_t)ntiles * KS * 1024);
-                d.dinfo = (float2 *)take(S_DINFO, (size_t)ntiles * kDomTile * sizeof(float2));
-                pl.bh.any_mfma = 1;
+                d.afrag = (uint4 *)take(S_AFRAG, (size_t)afr * 1024);
+                d.bfrag = (uint4 *)take(S_BFRAG, (size_t)ntiles * d.geo.kt * 1024);
+                d.dinfo = (float2 *)take(S_DINFO, (size_t)ntiles * tile * sizeof(float2));
             } else {
                 fp32_geometry(d.B, d.range_cap, d.pool_cap, &d.fnchunk, &d.ftpc);
                 d.rpad = fp32_rpad(d.range_cap);
@@ -287,7 +300,6 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
                 d.vf = (float *)take(S_VF32, (size_t)n2 * d.rpad * 8 * sizeof(float));
                 d.df = (float *)take(S_DF32, (size_t)n2 * d.ppad * sizeof(float));
                 d.dinfo = (float2 *)take(S_DINFO, (size_t)d.ppad * sizeof(float2));
-                pl.bh.any_fp32 = 1;
             }
             d.part = (Partial *)take(S_PARTIAL, sizeof(Partial) * (size_t)d.range_cap * d.nslot);
         }
@@ -322,7 +334,7 @@ void bind(fic_ctx *ctx, LevelPlan &pl) {
             rb(d.cblockoff, S_CBLOCK);
             rb(d.part, S_PARTIAL);
             rb(d.dinfo, S_DINFO);
-            if (d.mfma) {
+            if (d.eng != E_FP32) {
                 rb(d.afrag, S_AFRAG);
                 rb(d.bfrag, S_BFRAG);
             } else {
@@ -392,10 +404,12 @@ int run_search(fic_ctx *ctx, LevelPlan &pl, hipStream_t st) {
     const BatchHost &b = pl.bh;
     mark(ctx, FIC_T_PREP, b.B, st);
     FIC_TRY(launch_range_info_b(b, st));
-    if (b.any_mfma) FIC_TRY(launch_mfma_prep_b(b, st));
+    if (b.eng == E_F16) FIC_TRY(launch_f16_prep_b(b, st));
+    else if (b.eng == E_I8) FIC_TRY(launch_mfma_prep_b(b, st));
     else FIC_TRY(launch_fp32_prep_b(b, st));
     mark(ctx, FIC_T_SEARCH, b.B, st);
-    if (b.any_mfma) FIC_TRY(launch_mfma_search_b(b, st));
+    if (b.eng == E_F16) FIC_TRY(launch_f16_search_b(b, st));
+    else if (b.eng == E_I8) FIC_TRY(launch_mfma_search_b(b, st));
     else FIC_TRY(launch_fp32_search_b(b, st));
     mark(ctx, FIC_T_FINAL, b.B, st);
     FIC_TRY(launch_finalize_b(b, st));
@@ -529,7 +543,7 @@ int fic_validate_params(const fic_params *p, int32_t width, int32_t height) {
     if (width < 2 * p->block0 || height < 2 * p->block0 || width % p->block0 || height % p->block0) return FIC_E_INVALID;
     if (width > 65535 || height > 65535 || (int64_t)width * height > (1 << 28)) return FIC_E_INVALID;
     if (check_pct(p->pool_pct) != FIC_OK || p->pool_max < 0) return FIC_E_INVALID;
-    if (p->engine != FIC_ENGINE_MFMA && p->engine != FIC_ENGINE_FP32) return FIC_E_INVALID;
+    if (!engine_ok(p->engine)) return FIC_E_INVALID;
     for (int l = 0; l < p->levels; ++l) {
         if (p->step[l] < 1) return FIC_E_INVALID;
         if (check_sset(p->s_num[l], p->s_count[l], p->s_den[l]) != FIC_OK) return FIC_E_INVALID;
@@ -661,7 +675,7 @@ int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, c
                      fic_level_codes *out, uint32_t *children_xy, int32_t *n_children, fic_stream stream) {
     if (!ctx || !pow2(B) || B < 2 || B > 32 || !image_ok(img, B) || !pool_ok(pool) || !ranges_xy || !n_ranges ||
         range_capacity < 0 || check_sset(s_num, s_count, s_den) != FIC_OK || check_rms(split_rms) != FIC_OK ||
-        !codes_ok(out) || (engine != FIC_ENGINE_MFMA && engine != FIC_ENGINE_FP32) ||
+        !codes_ok(out) || !engine_ok(engine) ||
         (!is_last && (!children_xy || !n_children)))
         return FIC_E_INVALID;
     if (out->capacity < range_capacity) return FIC_E_CAPACITY;

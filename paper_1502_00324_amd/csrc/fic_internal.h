@@ -14,7 +14,8 @@ constexpr int kMaxLevels = FIC_MAX_LEVELS;
 constexpr int kMaxS = FIC_MAX_S;
 constexpr int kTableSize = 4097;       // entropy table entries, q = 0..4096
 constexpr int kScanBlock = 1024;       // items per block in stable compaction
-constexpr int kDomTile = 16;           // domains per MFMA column tile
+constexpr int kDomTile = 16;           // domains per column tile of the int8 engine
+constexpr int kDomTile32 = 32;         // domains per column tile of the f16 engine
 
 // ---------------------------------------------------------------- small PODs
 // Contrast set of one level, passed by value to kernels.
@@ -115,6 +116,9 @@ inline void *sp(fic_ctx *ctx, Slot s) { return ctx->slot[s].ptr; }
 
 // ---------------------------------------------------------------- search geometry
 struct MfmaGeom {
+    int pl;       // operand form: 1 = raw pixels (K = 4B^2), 2 = decimated hi/lo planes (K = 2 B^2)
+    int ka;       // 64-deep K-steps of a range fragment (per half)
+    int kt;       // 64-deep K-steps of a domain tile (ka * pl)
     int rpw;      // ranges per workgroup
     int nrg;      // range groups
     int tpc;      // domain tiles per chunk
@@ -124,13 +128,36 @@ struct MfmaGeom {
     int nslot;    // partial results per range
     int nwg;      // workgroups
 };
-MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap);
+MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap);   // int8 engine
+MfmaGeom f16_geometry(int B, int range_cap, int pool_cap);    // f16 engine
+void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt);
+
+// Range group, chunk walk and partial-result slot of search workgroup lb.
+__device__ inline void chunk_walk(const MfmaGeom &geo, int lb, int &rg, int &cfirst, int &cstep, int &ncs,
+                                  int &slot) {
+    if (geo.xcd) {  // XCD-aware: workgroup w runs on XCD w % 8
+        const int xcd = lb & 7, k = lb >> 3, grp = k / geo.nrg;
+        rg = k % geo.nrg;
+        cfirst = xcd + 8 * grp * geo.G;
+        cstep = 8;
+        ncs = geo.G;
+        slot = xcd + 8 * grp;
+    } else {
+        rg = lb % geo.nrg;
+        cfirst = slot = lb / geo.nrg;
+        cstep = 1;
+        ncs = 1;
+    }
+}
 
 // ---------------------------------------------------------------- batched levels
 // One quadtree level of a batch of images runs as ~25 launches whatever the
 // number of images: every kernel takes the device table of per-image level
 // state below, and a launch of kind k gives image i the workgroups
 // [pre[k][i], pre[k][i+1]) (found by binary search on the prefix table).
+// Search engine of a level: every image of a level uses the same one.
+enum Engine { E_FP32 = 0, E_I8 = 1, E_F16 = 2 };
+
 enum Kind {
     K_LEVEL0, K_KEYS, K_HIST, K_PCMP, K_MOM, K_RANGE, K_AFRAG, K_BFRAG, K_VIEWS, K_DOMS, K_SEARCH, K_FINAL,
     K_CCMP, K_NUM
@@ -170,8 +197,8 @@ struct ImgLvl {
     float2 *dinfo;
     float *vf, *df;
     // search geometry of the engine in use
-    int mfma;            // 1 = int8 MFMA engine, 0 = FP32 engine
-    MfmaGeom geo;        // MFMA
+    int eng;             // search engine of this level (Engine)
+    MfmaGeom geo;        // matrix engines
     int rpad, ppad, fnchunk, ftpc;  // FP32
     int nslot;           // partial results per range
 };
@@ -196,7 +223,7 @@ __device__ inline int find_img(const int *pre, int n, int b) {
 struct BatchHost {
     BatchDev dev;
     int blocks[K_NUM];   // total workgroups per kind
-    int B, L, KS, any_cap, any_fp32, any_mfma;
+    int B, L, KS, any_cap, eng;
     SSet ss;
     fic_ratio rms;
     int is_last;
@@ -210,8 +237,10 @@ hipError_t launch_range_info_b(const BatchHost &b, hipStream_t st);
 hipError_t launch_finalize_b(const BatchHost &b, hipStream_t st);
 hipError_t launch_children_b(const BatchHost &b, hipStream_t st);
 // MFMA engine
-bool mfma_supported(int B);
-int mfma_quads_padded(int B, int range_cap);
+bool mfma_supported(int B);   // int8 engine
+bool f16_supported(int B);    // f16 engine
+hipError_t launch_f16_prep_b(const BatchHost &b, hipStream_t st);
+hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st);
 hipError_t launch_mfma_prep_b(const BatchHost &b, hipStream_t st);
 hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st);
 // FP32 engine

@@ -1,0 +1,366 @@
+// Half-precision MFMA search engine (gfx950, v_mfma_f32_32x32x16_f16).
+//
+// The cross term of every (range, isometry) x domain pair is contracted over
+// the K = B^2 decimated positions (Sec. 3.1) with no replicated or split
+// operands:
+//   rows    = (range, isometry): the range seen through the inverse isometry,
+//             minus 128, in [-128, 127];
+//   columns = pool domains: D4 - 512, in [-512, 508] (D4 = 2x2 sum);
+//   C' = sum (r - 128)(D4 - 512), the same integer as the int8 engines.
+// Every operand is an integer below 2^11, so exact in f16, and every product
+// and partial sum is an integer of magnitude <= B^2 2^16 <= 2^24 for B <= 16,
+// so exact in the f32 accumulator whatever the summation order.  The prune
+// test and the isometry maximum then run on the float results directly.
+//
+// Fragment layouts (16 bytes = 8 halves per lane, 64 lanes per 1 KiB; lane L
+// feeds A row L%32 and B column L%32 with K-values 8(L/32)..+7 of the
+// 16-deep step; result lane L holds column L%32, rows 8j + 4(L/32) + i for
+// value 4j + i):
+//   A: quad q of 4 ranges, K-step s:   afrag[(q*KS + s)*64 + L]
+//      row m: j = m/8, h = (m/4)%2, i = m%4 -> range 4q + 2h + j/2,
+//      isometry 4(j%2) + i
+//   B: tile of 32 domains, K-step s:   bfrag[(tile*KS + s)*64 + L]
+//   K index k = 16 s + 8 (L/32) + e -> decimated position (k / B, k % B).
+// With rows arranged this way lane L holds all 8 isometries of two ranges
+// (4q + 2(L/32) and the next) against domain L%32: values 0..7 and 8..15.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include "fic_internal.h"
+#include "search_common.h"
+
+namespace fic {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f16x __attribute__((ext_vector_type(16)));
+
+bool f16_supported(int B) { return B == 4 || B == 8 || B == 16; }
+
+// Range quads per wave (RQ) and domain tiles per LDS stage (DT); the first
+// entry per size is the measured default, FIC_F16_SHAPE="rq,dt" selects
+// another compiled one.
+struct F16Shape { int B, rq, dt; };
+static const F16Shape kF16Shapes[] = {
+    {4, 1, 8}, {4, 2, 8}, {4, 4, 8}, {4, 2, 16},
+    {8, 2, 4}, {8, 1, 4}, {8, 2, 2}, {8, 4, 4},
+    {16, 1, 1}, {16, 2, 1}, {16, 1, 2},
+};
+static F16Shape f16_shape(int B) {
+    const char *e = getenv("FIC_F16_SHAPE");
+    int rq = 0, dt = 0;
+    if (e && sscanf(e, "%d,%d", &rq, &dt) == 2)
+        for (const F16Shape &s : kF16Shapes)
+            if (s.B == B && s.rq == rq && s.dt == dt) return s;
+    for (const F16Shape &s : kF16Shapes)
+        if (s.B == B) return s;
+    return F16Shape{B, 1, 1};
+}
+
+MfmaGeom f16_geometry(int B, int range_cap, int pool_cap) {
+    const F16Shape sh = f16_shape(B);
+    MfmaGeom g;
+    g.pl = 0;
+    g.ka = B * B / 16;
+    g.kt = g.ka;
+    g.rpw = 16 * sh.rq;
+    const int ntiles = (pool_cap + kDomTile32 - 1) / kDomTile32;
+    split_chunks(g, range_cap, ntiles, g.kt, sh.dt);
+    return g;
+}
+
+// ---------------------------------------------------------------- operands
+__global__ __launch_bounds__(256) void k_f16_afrag(BatchDev b) {
+    const int *pre = b.pre + K_AFRAG * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
+    const int B = d.B, KS = d.geo.ka;
+    const int nquads = d.geo.nrg * (d.geo.rpw / 4);
+    const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    if (slot >= nquads * KS * 64) return;
+    const int lane = slot & 63;
+    const int rest = slot >> 6;
+    const int s = rest % KS, q = rest / KS;
+    const int m = lane & 31, kb = lane >> 5;
+    const int j = m >> 3, h = (m >> 2) & 1, i = m & 3;
+    const int r = 4 * q + 2 * h + (j >> 1);
+    const int t = 4 * (j & 1) + i;
+    h8 w;
+    if (r < min(*d.nr, d.range_cap)) {
+        const uint32_t v = d.rxy[r];
+        const int x0 = v & 0xffff, y0 = v >> 16;
+        const int ti = iso_inv(t);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 16 * s + 8 * kb + e;
+            const int cy = k / B, cx = k - cy * B;
+            int sy, sx;
+            iso_src(ti, B, cy, cx, sy, sx);
+            w[e] = (_Float16)((int)d.pix[(size_t)(y0 + sy) * d.pitch + x0 + sx] - 128);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[e] = (_Float16)0;
+    }
+    ((h8 *)d.afrag)[slot] = w;
+}
+
+__global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
+    const int *pre = b.pre + K_BFRAG * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
+    const int B = d.B, KS = d.geo.kt;
+    const int ntiles = (d.pool_cap + kDomTile32 - 1) / kDomTile32;
+    const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    if (slot >= ntiles * KS * 64) return;
+    const int lane = slot & 63;
+    const int rest = slot >> 6;
+    const int s = rest % KS, tile = rest / KS;
+    const int col = lane & 31, kb = lane >> 5;
+    const int p = tile * kDomTile32 + col;
+    const bool valid = p < min(*d.pcount, d.pool_cap);
+    h8 w;
+    if (valid) {
+        const uint32_t v = d.pxy[p];
+        const int x0 = v & 0xffff, y0 = v >> 16, pitch = d.pitch;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 16 * s + 8 * kb + e;
+            const int cy = k / B, cx = k - cy * B;
+            const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
+            w[e] = (_Float16)(q[0] + q[1] + q[pitch] + q[pitch + 1] - 512);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[e] = (_Float16)0;
+    }
+    ((h8 *)d.bfrag)[slot] = w;
+    if (s == 0 && kb == 0)
+        d.dinfo[p] = valid ? make_float2((float)d.psum4[p], sqrt_down((double)d.pa[p]))
+                           : make_float2(__builtin_nanf(""), __builtin_nanf(""));  // never passes
+}
+
+// ---------------------------------------------------------------- search
+// A workgroup of 4 waves owns 16 RQ ranges (each wave RQ quads) and the
+// domain tiles of its chunks.  Domain fragments go global -> registers -> LDS
+// in stages of DT tiles, double-buffered; the MFMAs of tile t+1 are issued
+// before the prune test of tile t.
+template <int KS, int RQ, int DT>
+__global__ __launch_bounds__(256) void k_f16_search(BatchDev bt, SSet ss) {
+    constexpr int STAGE = DT * KS * 64;          // uint4 per stage
+    constexpr int PER_T = STAGE / 256;
+    static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
+    __shared__ uint4 bl[2][STAGE];
+    __shared__ float2 dl[2][DT * kDomTile32];
+    __shared__ SLds sl;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    load_sset(sl, ss);
+    const SConst sc = make_sconst(ss);
+    const int *bpre = bt.pre + K_SEARCH * (bt.n + 1);
+    const int im = find_img(bpre, bt.n, blockIdx.x);
+    const ImgLvl &dsc = bt.d[im];
+    const MfmaGeom geo = dsc.geo;
+    const int lb = blockIdx.x - bpre[im];   // image blocks start at multiples of 8
+    if (lb >= geo.nwg) return;
+    const h8 *__restrict__ afrag = (const h8 *)dsc.afrag;
+    const uint4 *__restrict__ bfrag = dsc.bfrag;
+    const float2 *__restrict__ dinfo = dsc.dinfo;
+    const RInfo *__restrict__ ri = dsc.ri;
+    const uint32_t *__restrict__ sum4 = dsc.psum4;
+    const int64_t *__restrict__ pa = dsc.pa;
+    Partial *__restrict__ part = dsc.part;
+    const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
+    int rg, cfirst, cstep, ncs, slot;
+    chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
+    const int R = min(*dsc.nr, range_cap), P = min(*dsc.pcount, pool_cap);
+    if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
+    const int ntiles = (P + kDomTile32 - 1) / kDomTile32;
+    const int q0 = (rg * 4 + wave) * RQ;
+    const bool wave_on = q0 * 4 < R;
+    const int hh = lane >> 5;
+
+    // per lane: two ranges per quad, 4 q + 2 hh + u for u = 0, 1
+    h8 A[RQ][KS];
+    float tn[RQ][2], bn[RQ][2], an[RQ][2];
+    int64_t best[RQ][2];
+    int bp[RQ][2], bk[RQ][2], rr[RQ][2];
+#pragma unroll
+    for (int qi = 0; qi < RQ; ++qi) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) A[qi][s] = afrag[((size_t)(q0 + qi) * KS + s) * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int r = (q0 + qi) * 4 + 2 * hh + u;
+            rr[qi][u] = r < R ? r : -1;
+            const RInfo x = ri[r < R ? r : 0];
+            bn[qi][u] = x.bn;
+            an[qi][u] = x.an;
+            tn[qi][u] = r < R ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
+            best[qi][u] = INT64_MAX;
+            bp[qi][u] = INT32_MAX;
+            bk[qi][u] = 0;
+        }
+    }
+    // drain the one-time loads: vmcnt is in-order, so a wait for them inside
+    // the tile loop would also wait for the stage prefetch
+    __builtin_amdgcn_s_waitcnt(0);
+
+    uint4 pre[PER_T];
+    float2 dpre = make_float2(0.f, 0.f);
+    int t0 = 0, t1 = 0;
+    auto gload = [&](int stg) {
+        const int tbase = t0 + stg * DT;
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) {
+            const int e = tid + 256 * i;
+            pre[i] = tbase + e / (KS * 64) < t1 ? bfrag[(size_t)tbase * KS * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        // tiles past the chunk end get NaN moments: no pair on them passes
+        if (tid < DT * kDomTile32)
+            dpre = tbase + tid / kDomTile32 < t1 ? dinfo[(size_t)tbase * kDomTile32 + tid]
+                                                 : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
+        if (tid < DT * kDomTile32) dl[buf][tid] = dpre;
+    };
+    // the tile's fragments are read up front (in groups of up to 8 K-steps),
+    // so one LDS wait covers a group rather than every MFMA
+    constexpr int KG = KS < 8 ? KS : 8;
+    auto mfma_tile = [&](f16x (&acc)[RQ], int buf, int dt) {
+#pragma unroll
+        for (int qi = 0; qi < RQ; ++qi) acc[qi] = f16x{0.f};
+#pragma unroll
+        for (int s0 = 0; s0 < KS; s0 += KG) {
+            h8 bf[KG];
+#pragma unroll
+            for (int s = 0; s < KG; ++s) {
+                const uint4 u = bl[buf][(dt * KS + s0 + s) * 64 + lane];
+                __builtin_memcpy(&bf[s], &u, sizeof(h8));
+            }
+#pragma unroll
+            for (int s = 0; s < KG; ++s)
+#pragma unroll
+                for (int qi = 0; qi < RQ; ++qi)
+                    acc[qi] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[qi][s0 + s], bf[s], acc[qi], 0, 0, 0);
+        }
+    };
+    for (int cj = 0; cj < ncs; ++cj) {
+        const int chunk = cfirst + cj * cstep;
+        t0 = chunk * geo.tpc;
+        t1 = min(ntiles, t0 + geo.tpc);
+        const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
+        if (nstage > 0) {
+            gload(0);
+            swrite(0);
+        }
+        __syncthreads();
+        for (int stg = 0; stg < nstage; ++stg) {
+            const int buf = stg & 1;
+            if (stg + 1 < nstage) gload(stg + 1);
+            if (wave_on) {
+                const int tbase = t0 + stg * DT;
+                f16x acc[2][RQ];
+                mfma_tile(acc[0], buf, 0);
+#pragma unroll
+                for (int dt = 0; dt < DT; ++dt) {
+                    const int cur = dt & 1;
+                    if (dt + 1 < DT) mfma_tile(acc[cur ^ 1], buf, dt + 1);
+                    const float2 di = dl[buf][dt * kDomTile32 + (lane & 31)];
+                    bool pass[RQ][2];
+                    float mx[RQ][2];
+                    bool any = false;
+#pragma unroll
+                    for (int qi = 0; qi < RQ; ++qi)
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const f16x &a = acc[cur][qi];
+                            const int o = 8 * u;
+                            mx[qi][u] = max8f(a[o], a[o + 1], a[o + 2], a[o + 3], a[o + 4], a[o + 5], a[o + 6], a[o + 7]);
+                            const float rhs = fmaf(tn[qi][u], di.y, fmaf(-bn[qi][u], di.x, -an[qi][u]));
+                            // false on NaN: rows past the ranges, domains past the
+                            // pool or the chunk, and ranges already at val 0
+                            pass[qi][u] = mx[qi][u] > rhs;
+                            any |= pass[qi][u];
+                        }
+                    if (__builtin_amdgcn_ballot_w64(any)) {  // rare: exact evaluation, then share the best
+                        const int p = (tbase + dt) * kDomTile32 + (lane & 31);
+#pragma unroll
+                        for (int qi = 0; qi < RQ; ++qi)
+#pragma unroll
+                            for (int u = 0; u < 2; ++u) {
+                                if (pass[qi][u])
+                                    confirm_pair((int)mx[qi][u], p, rr[qi][u], n, ri, sum4, pa, sl, sc, best[qi][u],
+                                                 bp[qi][u], bk[qi][u]);
+                                if (__builtin_amdgcn_ballot_w64(pass[qi][u])) {
+                                    // the 32 lanes holding this range share their best: a
+                                    // pair is only rejected when it cannot even tie it
+                                    const int64_t gb = group_min_val<32>(best[qi][u]);
+                                    if (rr[qi][u] >= 0) tn[qi][u] = tn_from(gb, ri[rr[qi][u]].cr, sc, n);
+                                }
+                            }
+                    }
+                }
+            }
+            if (stg + 1 < nstage) swrite(buf ^ 1);
+            __syncthreads();
+        }
+    }
+
+    if (!wave_on) return;
+#pragma unroll
+    for (int qi = 0; qi < RQ; ++qi)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            int64_t v = best[qi][u];
+            int p = bp[qi][u], k = bk[qi][u];
+            group_min<32>(v, p, k);
+            if ((lane & 31) == 0 && rr[qi][u] >= 0) {
+                Partial o;
+                o.val = v;
+                o.p = p == INT32_MAX ? -1 : p;
+                o.k = k;
+                part[(size_t)rr[qi][u] * geo.nslot + slot] = o;
+            }
+        }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_f16_prep_b(const BatchHost &b, hipStream_t st) {
+    if (b.blocks[K_AFRAG] > 0) k_f16_afrag<<<b.blocks[K_AFRAG], 256, 0, st>>>(b.dev);
+    if (b.blocks[K_BFRAG] > 0) k_f16_bfrag<<<b.blocks[K_BFRAG], 256, 0, st>>>(b.dev);
+    return hipGetLastError();
+}
+
+template <int KS, int RQ, int DT>
+static hipError_t launch_f16_t(const BatchHost &b, hipStream_t st) {
+    k_f16_search<KS, RQ, DT><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
+    return hipGetLastError();
+}
+
+hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st) {
+    if (b.blocks[K_SEARCH] == 0) return hipSuccess;
+    const int B = b.B;
+    const F16Shape sh = f16_shape(B);
+#define FIC_F16(KS, RQ, DT) \
+    if (sh.rq == RQ && sh.dt == DT) return launch_f16_t<KS, RQ, DT>(b, st)
+    if (B == 4) {
+        FIC_F16(1, 2, 8);
+        FIC_F16(1, 1, 8);
+        FIC_F16(1, 4, 8);
+        FIC_F16(1, 2, 16);
+    } else if (B == 8) {
+        FIC_F16(4, 2, 4);
+        FIC_F16(4, 1, 4);
+        FIC_F16(4, 2, 2);
+        FIC_F16(4, 4, 4);
+    } else if (B == 16) {
+        FIC_F16(16, 1, 1);
+        FIC_F16(16, 2, 1);
+        FIC_F16(16, 1, 2);
+    }
+#undef FIC_F16
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fic

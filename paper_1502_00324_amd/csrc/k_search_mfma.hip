@@ -1,20 +1,28 @@
 // Int8 MFMA search engine (gfx950, v_mfma_i32_16x16x64_i8).
 //
 // The cross term of every (range, isometry) x domain pair is a dense
-// contraction over the K = 4B^2 raw pixels of the 2B x 2B domain:
-//   rows    = (range, isometry): the range seen through the inverse isometry,
-//             each range pixel replicated over its 2x2 domain cell, minus 128;
-//   columns = pool domains, raw pixels minus 128;
-// both fit int8 exactly and int32 accumulation is exact (|C'| <= 4B^2 2^14).
+// contraction.  Centred at 128, both operands fit int8 and the int32
+// accumulators are exact.  Two operand forms give the same integer
+//   C' = sum over decimated positions of (r - 128) (D4 - 512)
+// (D4 the 2x2 sum of the domain, Sec. 3.1):
+//   raw (pl = 1, K = 4B^2): rows hold the range, each pixel replicated over
+//       its 2x2 domain cell; columns hold the raw domain pixels minus 128;
+//   planes (pl = 2, K = 2B^2): D4 - 512 = 4 hi + lo with hi = floor(D4/4) - 128
+//       and lo = D4 mod 4; rows hold the range once per decimated position,
+//       the hi and lo planes are contracted separately and C' = 4 C_hi + C_lo.
+// The planes form does half the MFMA work and moves half the domain bytes;
+// it needs B^2 >= 64, so B = 4 keeps the raw form.
 //
 // Fragment layouts (16 bytes per lane, 64 lanes per 1 KiB fragment, verified
 // for this instruction: lane L feeds A row L%16 and B column L%16 with the
 // 16 K-values of group L/16; result lane L holds rows 4(L/16)..+3 of column
 // L%16):
-//   A: quad q of 4 ranges, half h, K-step s:  afrag[((q*2 + h)*KS + s)*64 + L]
+//   A: quad q of 4 ranges, half h, K-step s < ka:  afrag[((q*2 + h)*ka + s)*64 + L]
 //      row i = L%16 -> range 4q + i/4, isometry 4h + i%4
-//   B: tile of 16 domains, K-step s:         bfrag[(tile*KS + s)*64 + L]
-//   K index k = 64 s + 16 (L/16) + byte -> raw pixel (k / 2B, k % 2B).
+//   B: tile of 16 domains, K-step s < kt:         bfrag[(tile*kt + s)*64 + L]
+//      planes form: steps [0, ka) hold hi, [ka, 2 ka) hold lo
+//   K index k = 64 s + 16 (L/16) + byte -> raw pixel (k / 2B, k % 2B), or
+//   decimated position (k / B, k % B) in the planes form.
 // With rows arranged this way the two halves give each lane all 8 isometries
 // of one (range, domain) pair, so the isometry max stays in registers.
 #include <stdio.h>
@@ -29,65 +37,50 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 bool mfma_supported(int B) { return B == 4 || B == 8 || B == 16; }
 
-// Tile shape: range quads per wave (RQ) and domain tiles per LDS stage (DT).
-// Each range size has a measured default; FIC_MFMA_SHAPE="rq,dt" selects
-// another compiled shape (used to tune).
-struct Shape { int B, rq, dt; };
+// Operand form (pl), range quads per wave (RQ) and domain tiles per LDS
+// stage (DT).  Each range size has a measured default (its first entry);
+// FIC_MFMA_SHAPE="pl,rq,dt" selects another compiled shape (used to tune).
+struct Shape { int B, pl, rq, dt; };
 static const Shape kShapes[] = {
-    {4, 2, 16}, {4, 1, 16}, {4, 4, 16},
-    {8, 2, 8}, {8, 2, 4}, {8, 1, 8}, {8, 3, 8},
-    {16, 1, 1}, {16, 1, 2},
+    {4, 1, 2, 16}, {4, 1, 1, 16}, {4, 1, 4, 16},
+    {8, 2, 2, 8}, {8, 2, 2, 16}, {8, 2, 1, 8}, {8, 2, 3, 8}, {8, 2, 4, 8}, {8, 1, 2, 8},
+    {16, 2, 2, 1}, {16, 2, 2, 2}, {16, 2, 1, 1}, {16, 2, 1, 2}, {16, 1, 1, 1},
 };
 static Shape mfma_shape(int B) {
     const char *e = getenv("FIC_MFMA_SHAPE");
-    int rq = 0, dt = 0;
-    if (e && sscanf(e, "%d,%d", &rq, &dt) == 2)
+    int pl = 0, rq = 0, dt = 0;
+    if (e && sscanf(e, "%d,%d,%d", &pl, &rq, &dt) == 3)
         for (const Shape &s : kShapes)
-            if (s.B == B && s.rq == rq && s.dt == dt) return s;
+            if (s.B == B && s.pl == pl && s.rq == rq && s.dt == dt) return s;
     for (const Shape &s : kShapes)
-        if (s.B == B) return s;  // the first entry per size is the default
-    return Shape{B, 1, 1};
-}
-static int mfma_rq(int B) { return mfma_shape(B).rq; }
-static int mfma_dt(int B) { return mfma_shape(B).dt; }
-
-// Quads of 4 ranges covered by the search grid (every wave reads RQ whole quads).
-int mfma_quads_padded(int B, int range_cap) {
-    const int rpw = 16 * mfma_rq(B);
-    return (range_cap + rpw - 1) / rpw * (rpw / 4);
+        if (s.B == B) return s;
+    return Shape{B, 1, 1, 1};
 }
 
-// Work split.  A workgroup owns rpw = 16 RQ ranges (a range group) and
-// streams domain tiles in chunks of about 1.5 MB of fragments, small enough
-// to stay resident in one XCD's 4 MB L2 while every range group running on
-// that XCD reads it.  With 8 or more chunks the mapping is XCD-aware:
-// workgroups are dispatched round-robin (id % 8 = XCD), XCD x owns chunks
-// x, x+8, x+16, ..., and consecutive workgroups of an XCD take consecutive
-// range groups of the same chunks.  A workgroup walks G chunks of its XCD
-// with one running best over them (about a quarter of the XCD's chunks, and
-// enough to keep the partial results, one per range and slot, under 256 MB).
-MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap) {
-    MfmaGeom g;
-    const int rq = mfma_rq(B), dt = mfma_dt(B), KS = B * B / 16;
-    g.rpw = 16 * rq;
+// Work split (both matrix engines).  A workgroup owns rpw ranges (a range
+// group) and streams domain tiles in chunks of about 1.5 MB of fragments,
+// small enough to stay resident in one XCD's 4 MB L2 while every range group
+// running on that XCD reads it.  With 8 or more chunks the mapping is
+// XCD-aware: workgroups are dispatched round-robin (id % 8 = XCD), XCD x owns
+// chunks x, x+8, x+16, ..., and consecutive workgroups of an XCD take
+// consecutive range groups of the same chunks.  A workgroup walks G chunks of
+// its XCD with one running best over them (about a quarter of the XCD's
+// chunks, and enough to keep the partial results, one per range and slot,
+// under 256 MB).  tile_kib is the fragment size of one domain tile in KiB.
+void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt) {
     g.nrg = (range_cap + g.rpw - 1) / g.rpw;
-    const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
-    g.tpc = max(8 * dt, 1536 / KS);
+    g.tpc = max(8 * dt, 1536 / tile_kib);
     g.nchunk = (ntiles + g.tpc - 1) / g.tpc;
     if (g.nchunk < 8) {
         // small pool: split finer only to give the GPU enough workgroups
         int nc = max(g.nchunk, min((ntiles + 8 * dt - 1) / (8 * dt), (2048 + g.nrg - 1) / max(1, g.nrg)));
-        nc = max(1, min(nc, 8));
-        if (nc >= 8) nc = 8;
-        g.nchunk = nc;
+        g.nchunk = max(1, min(nc, 8));
     } else {
         g.nchunk = (g.nchunk + 7) / 8 * 8;
     }
     g.tpc = max(1, (ntiles + g.nchunk - 1) / g.nchunk);
     g.xcd = g.nchunk % 8 == 0 ? 1 : 0;
     if (g.xcd) {
-        // a workgroup walks about a quarter of its XCD's chunks, so each range
-        // group reads its operands ~4 times per XCD rather than once per chunk
         const int per_xcd = g.nchunk / 8;
         const long max_slots = max(8L, (256L << 20) / 16 / max(1, range_cap));
         const int groups_max = (int)max(1L, max_slots / 8);
@@ -98,6 +91,17 @@ MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap) {
         g.nslot = g.nchunk;
     }
     g.nwg = g.nrg * g.nslot;
+}
+
+MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap) {
+    MfmaGeom g;
+    const Shape sh = mfma_shape(B);
+    g.pl = sh.pl;
+    g.ka = sh.pl == 2 ? B * B / 64 : B * B / 16;
+    g.kt = g.ka * sh.pl;
+    g.rpw = 16 * sh.rq;
+    const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
+    split_chunks(g, range_cap, ntiles, g.kt, sh.dt);
     return g;
 }
 
@@ -106,14 +110,14 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
     const int *pre = b.pre + K_AFRAG * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int B = d.B, KS = B * B / 16;
+    const int B = d.B, KA = d.geo.ka, planes = d.geo.pl == 2;
     const int nquads = d.geo.nrg * (d.geo.rpw / 4);
     const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
-    if (slot >= nquads * 2 * KS * 64) return;
+    if (slot >= nquads * 2 * KA * 64) return;
     const int lane = slot & 63;
     int rest = slot >> 6;
-    const int s = rest % KS;
-    rest /= KS;
+    const int s = rest % KA;
+    rest /= KA;
     const int h = rest & 1, q = rest >> 1;
     const int i = lane & 15, kg = lane >> 4;
     const int t = 4 * h + (i & 3);
@@ -126,9 +130,16 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
 #pragma unroll
         for (int bb = 0; bb < 16; ++bb) {
             const int k = 64 * s + 16 * kg + bb;
-            const int dy = k / D, dx = k - dy * D;
+            int cy, cx;  // decimated position
+            if (planes) {
+                cy = k / B;
+                cx = k - cy * B;
+            } else {
+                cy = (k / D) >> 1;
+                cx = (k % D) >> 1;
+            }
             int sy, sx;
-            iso_src(ti, B, dy >> 1, dx >> 1, sy, sx);
+            iso_src(ti, B, cy, cx, sy, sx);
             const int val = (int)d.pix[(size_t)(y0 + sy) * d.pitch + x0 + sx] - 128;
             w[bb >> 2] |= (uint32_t)(uint8_t)(int8_t)val << (8 * (bb & 3));
         }
@@ -140,13 +151,13 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     const int *pre = b.pre + K_BFRAG * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int B = d.B, KS = B * B / 16;
+    const int B = d.B, KA = d.geo.ka, KT = d.geo.kt, planes = d.geo.pl == 2;
     const int ntiles = (d.pool_cap + kDomTile - 1) / kDomTile;
     const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
-    if (slot >= ntiles * KS * 64) return;
+    if (slot >= ntiles * KT * 64) return;
     const int lane = slot & 63;
     const int rest = slot >> 6;
-    const int s = rest % KS, tile = rest / KS;
+    const int s = rest % KT, tile = rest / KT;
     const int j = lane & 15, kg = lane >> 4;
     const int p = tile * kDomTile + j;
     const bool valid = p < min(*d.pcount, d.pool_cap);
@@ -154,18 +165,29 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     if (valid) {
         const uint32_t v = d.pxy[p];
         const int x0 = v & 0xffff, y0 = v >> 16;
-        const int D = 2 * B;
+        const int D = 2 * B, pitch = d.pitch;
+        const int lo = planes && s >= KA;
+        const int sk = planes ? s % KA : s;
 #pragma unroll
         for (int bb = 0; bb < 16; ++bb) {
-            const int k = 64 * s + 16 * kg + bb;
-            const int dy = k / D, dx = k - dy * D;
-            const int val = (int)d.pix[(size_t)(y0 + dy) * d.pitch + x0 + dx] - 128;
+            const int k = 64 * sk + 16 * kg + bb;
+            int val;
+            if (planes) {
+                const int cy = k / B, cx = k - cy * B;
+                const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
+                const int d4 = q[0] + q[1] + q[pitch] + q[pitch + 1];
+                val = lo ? (d4 & 3) : (d4 >> 2) - 128;
+            } else {
+                const int dy = k / D, dx = k - dy * D;
+                val = (int)d.pix[(size_t)(y0 + dy) * pitch + x0 + dx] - 128;
+            }
             w[bb >> 2] |= (uint32_t)(uint8_t)(int8_t)val << (8 * (bb & 3));
         }
     }
     d.bfrag[slot] = make_uint4(w[0], w[1], w[2], w[3]);
     if (s == 0 && kg == 0)
-        d.dinfo[p] = valid ? make_float2((float)d.psum4[p], sqrt_down((double)d.pa[p])) : make_float2(0.f, 0.f);
+        d.dinfo[p] = valid ? make_float2((float)d.psum4[p], sqrt_down((double)d.pa[p]))
+                           : make_float2(__builtin_nanf(""), __builtin_nanf(""));  // never passes
 }
 
 // ---------------------------------------------------------------- search
@@ -173,9 +195,10 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
 // of domain tiles.  Domain fragments go global -> registers -> LDS in stages
 // of DT tiles, double-buffered: the loads for stage s+1 are issued before the
 // MFMAs of stage s and written to the other LDS buffer after them.
-template <int KS, int RQ, int DT>
+template <int KA, int PL, int RQ, int DT>
 __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
-    constexpr int STAGE = DT * KS * 64;          // uint4 per stage
+    constexpr int KB = KA * PL;                  // K-steps of a domain tile
+    constexpr int STAGE = DT * KB * 64;          // uint4 per stage
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
     __shared__ uint4 bl[2][STAGE];
@@ -183,6 +206,7 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
     __shared__ SLds sl;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
+    const SConst sc = make_sconst(ss);
     const int *bpre = bt.pre + K_SEARCH * (bt.n + 1);
     const int im = find_img(bpre, bt.n, blockIdx.x);
     const ImgLvl &dsc = bt.d[im];
@@ -199,19 +223,7 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
     const int32_t *nr = dsc.nr, *np = dsc.pcount;
     int rg, cfirst, cstep, ncs, slot;
-    if (geo.xcd) {  // XCD-aware: workgroup w runs on XCD w % 8
-        const int w = lb, xcd = w & 7, k = w >> 3, grp = k / geo.nrg;
-        rg = k % geo.nrg;
-        cfirst = xcd + 8 * grp * geo.G;
-        cstep = 8;
-        ncs = geo.G;
-        slot = xcd + 8 * grp;
-    } else {
-        rg = lb % geo.nrg;
-        cfirst = slot = lb / geo.nrg;
-        cstep = 1;
-        ncs = 1;
-    }
+    chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
     const int R = min(*nr, range_cap), P = min(*np, pool_cap);
     if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
     const int ntiles = (P + kDomTile - 1) / kDomTile;
@@ -219,7 +231,7 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
     const bool wave_on = q0 * 4 < R;
     const int g = lane >> 4;
 
-    v4i A[RQ][2][KS];
+    v4i A[RQ][2][KA];
     float tn[RQ], bn[RQ], an[RQ];
     int64_t best[RQ];
     int bp[RQ], bk[RQ], rr[RQ];
@@ -228,13 +240,13 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int s = 0; s < KS; ++s) A[qi][h][s] = afrag[(((size_t)(q0 + qi) * 2 + h) * KS + s) * 64 + lane];
+            for (int s = 0; s < KA; ++s) A[qi][h][s] = afrag[(((size_t)(q0 + qi) * 2 + h) * KA + s) * 64 + lane];
         const int r = (q0 + qi) * 4 + g;
         rr[qi] = r < R ? r : -1;
         const RInfo x = ri[r < R ? r : 0];
         bn[qi] = x.bn;
         an[qi] = x.an;
-        tn[qi] = -1e30f;
+        tn[qi] = r < R ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
         best[qi] = INT64_MAX;
         bp[qi] = INT32_MAX;
         bk[qi] = 0;
@@ -252,41 +264,51 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
             const int e = tid + 256 * i;
-            pre[i] = tbase + e / (KS * 64) < t1 ? bfrag[(size_t)tbase * KS * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
+            pre[i] = tbase + e / (KB * 64) < t1 ? bfrag[(size_t)tbase * KB * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
         }
-        if (tid < DT * kDomTile && tbase + tid / kDomTile < t1) dpre = dinfo[(size_t)tbase * kDomTile + tid];
+        // tiles past the chunk end get NaN moments: no pair on them passes
+        if (tid < DT * kDomTile)
+            dpre = tbase + tid / kDomTile < t1 ? dinfo[(size_t)tbase * kDomTile + tid]
+                                               : make_float2(__builtin_nanf(""), __builtin_nanf(""));
     };
     auto swrite = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
         if (tid < DT * kDomTile) dl[buf][tid] = dpre;
     };
-    // lane l holds domain 16 t + (l % 16) of tile t: valid while t < lim (the
-    // chunk end and the pool end); tiles past t1 in the last stage are zeros
-    const int plim = (P - (lane & 15) + kDomTile - 1) / kDomTile;
-    auto mfma_tile = [&](v4i (&acc)[RQ][2], int buf, int dt) {
-        v4i Bf[KS];
+    // acc[qi][h][plane]: the planes are combined (4 hi + lo) at the test,
+    // one tile later, so no MFMA result is waited for at issue time
+    auto mfma_tile = [&](v4i (&acc)[RQ][2][PL], int buf, int dt) {
+        v4i Bf[KB];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const uint4 u = bl[buf][(dt * KS + s) * 64 + lane];
+        for (int s = 0; s < KB; ++s) {
+            const uint4 u = bl[buf][(dt * KB + s) * 64 + lane];
             Bf[s] = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
         }
 #pragma unroll
-        for (int qi = 0; qi < RQ; ++qi) acc[qi][0] = acc[qi][1] = v4i{0, 0, 0, 0};
+        for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+            for (int pl = 0; pl < PL; ++pl) acc[qi][0][pl] = acc[qi][1][pl] = v4i{0, 0, 0, 0};
 #pragma unroll
-            for (int qi = 0; qi < RQ; ++qi) {
-                acc[qi][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][0][s], Bf[s], acc[qi][0], 0, 0, 0);
-                acc[qi][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][1][s], Bf[s], acc[qi][1], 0, 0, 0);
-            }
+        for (int s = 0; s < KA; ++s)
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+                for (int qi = 0; qi < RQ; ++qi)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        acc[qi][h][pl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][h][s], Bf[pl * KA + s],
+                                                                               acc[qi][h][pl], 0, 0, 0);
+    };
+    auto cprime = [&](const v4i (&a)[PL]) -> v4i {
+        if constexpr (PL == 2) return (a[0] << 2) + a[1];
+        else return a[0];
     };
   for (int cj = 0; cj < ncs; ++cj) {
     const int chunk = cfirst + cj * cstep;
     t0 = chunk * geo.tpc;
     t1 = min(ntiles, t0 + geo.tpc);
     const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
-    const int lim = min(t1, plim);
     if (nstage > 0) {
         gload(0);
         swrite(0);
@@ -299,36 +321,37 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
             const int tbase = t0 + stg * DT;
             // software pipeline: the MFMAs of tile dt+1 are issued before the
             // prune test of tile dt, in the same basic block
-            v4i acc[2][RQ][2];
+            v4i acc[2][RQ][2][PL];
             mfma_tile(acc[0], buf, 0);
 #pragma unroll
             for (int dt = 0; dt < DT; ++dt) {
                 const int cur = dt & 1;
                 if (dt + 1 < DT) mfma_tile(acc[cur ^ 1], buf, dt + 1);
                 const float2 di = dl[buf][dt * kDomTile + (lane & 15)];
-                const bool pv = tbase + dt < lim;
                 bool pass[RQ];
                 bool any = false;
                 int mx[RQ];
 #pragma unroll
                 for (int qi = 0; qi < RQ; ++qi) {
-                    const v4i cx = acc[cur][qi][0], cy = acc[cur][qi][1];
+                    const v4i cx = cprime(acc[cur][qi][0]), cy = cprime(acc[cur][qi][1]);
                     mx[qi] = max8(cx.x, cx.y, cx.z, cx.w, cy.x, cy.y, cy.z, cy.w);
                     const float rhs = fmaf(tn[qi], di.y, fmaf(-bn[qi], di.x, -an[qi]));
-                    pass[qi] = pv & (rr[qi] >= 0) & ((float)mx[qi] > rhs);
+                    // false on NaN: rows past the ranges, domains past the
+                    // pool or the chunk, and ranges already at val 0
+                    pass[qi] = (float)mx[qi] > rhs;
                     any |= pass[qi];
                 }
                 if (__builtin_amdgcn_ballot_w64(any)) {  // rare: exact evaluation, then share the best
                     const int p = (tbase + dt) * kDomTile + (lane & 15);
 #pragma unroll
                     for (int qi = 0; qi < RQ; ++qi) {
-                        if (pass[qi]) confirm_pair(mx[qi], p, rr[qi], n, ri, sum4, pa, sl, best[qi], bp[qi], bk[qi]);
+                        if (pass[qi]) confirm_pair(mx[qi], p, rr[qi], n, ri, sum4, pa, sl, sc, best[qi], bp[qi], bk[qi]);
                         if (__builtin_amdgcn_ballot_w64(pass[qi])) {
                             // the 16 lanes holding this range share their best: the
                             // threshold may use it because a pair is only rejected
                             // when it cannot even tie it
                             const int64_t gb = group_min_val<16>(best[qi]);
-                            tn[qi] = rr[qi] >= 0 ? tn_from(gb, ri[rr[qi]].cr, sl.den, n) : -1e30f;
+                            if (rr[qi] >= 0) tn[qi] = tn_from(gb, ri[rr[qi]].cr, sc, n);
                         }
                     }
                 }
@@ -362,9 +385,9 @@ hipError_t launch_mfma_prep_b(const BatchHost &b, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int KS, int RQ, int DT>
+template <int KA, int PL, int RQ, int DT>
 static hipError_t launch_search_t(const BatchHost &b, hipStream_t st) {
-    k_mfma_search<KS, RQ, DT><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
+    k_mfma_search<KA, PL, RQ, DT><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
     return hipGetLastError();
 }
 
@@ -372,20 +395,25 @@ hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
     if (b.blocks[K_SEARCH] == 0) return hipSuccess;
     const int B = b.B;
     const Shape sh = mfma_shape(B);
-#define FIC_SEARCH(KS, RQ, DT) \
-    if (sh.rq == RQ && sh.dt == DT) return launch_search_t<KS, RQ, DT>(b, st)
+#define FIC_SEARCH(KA, PL, RQ, DT) \
+    if (sh.pl == PL && sh.rq == RQ && sh.dt == DT) return launch_search_t<KA, PL, RQ, DT>(b, st)
     if (B == 4) {
-        FIC_SEARCH(1, 2, 16);
-        FIC_SEARCH(1, 1, 16);
-        FIC_SEARCH(1, 4, 16);
+        FIC_SEARCH(1, 1, 2, 16);
+        FIC_SEARCH(1, 1, 1, 16);
+        FIC_SEARCH(1, 1, 4, 16);
     } else if (B == 8) {
-        FIC_SEARCH(4, 2, 8);
-        FIC_SEARCH(4, 2, 4);
-        FIC_SEARCH(4, 1, 8);
-        FIC_SEARCH(4, 3, 8);
+        FIC_SEARCH(1, 2, 2, 8);
+        FIC_SEARCH(1, 2, 2, 16);
+        FIC_SEARCH(1, 2, 1, 8);
+        FIC_SEARCH(1, 2, 3, 8);
+        FIC_SEARCH(1, 2, 4, 8);
+        FIC_SEARCH(4, 1, 2, 8);
     } else if (B == 16) {
-        FIC_SEARCH(16, 1, 1);
-        FIC_SEARCH(16, 1, 2);
+        FIC_SEARCH(4, 2, 1, 2);
+        FIC_SEARCH(4, 2, 2, 2);
+        FIC_SEARCH(4, 2, 1, 1);
+        FIC_SEARCH(4, 2, 2, 1);
+        FIC_SEARCH(16, 1, 1, 1);
     }
 #undef FIC_SEARCH
     return hipErrorInvalidValue;

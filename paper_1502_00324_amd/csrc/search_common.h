@@ -35,6 +35,17 @@ __device__ __forceinline__ int max8(int a0, int a1, int a2, int a3, int b0, int 
     return max(max(m1, m2), m3);
 }
 
+// Maximum of 8 floats as four v_maximum3_f32.  The NaN-propagating maximum
+// needs no input canonicalisation (fmaxf would add one v_max per input in IEEE
+// mode); the inputs here are finite integers, where both agree.
+__device__ __forceinline__ float max8f(float a0, float a1, float a2, float a3, float b0, float b1, float b2,
+                                       float b3) {
+#define FIC_MAX2(x, y) __builtin_elementwise_maximum(x, y)
+    const float m1 = FIC_MAX2(FIC_MAX2(a0, a1), a2), m2 = FIC_MAX2(FIC_MAX2(a3, b0), b1);
+    return FIC_MAX2(FIC_MAX2(m1, m2), FIC_MAX2(b2, b3));
+#undef FIC_MAX2
+}
+
 __device__ inline float sqrt_down(double v) {
     const double s = sqrt(v);
     float f = (float)s;
@@ -45,15 +56,27 @@ __device__ inline float sqrt_down(double v) {
 // Contrast numerators in LDS, so lanes may index them independently.
 struct SLds {
     int32_t num[kMaxS];
-    int32_t count, den;
 };
 
 __device__ inline void load_sset(SLds &dst, const SSet &ss) {
     if (threadIdx.x < kMaxS) dst.num[threadIdx.x] = ss.num[threadIdx.x];
-    if (threadIdx.x == 0) {
-        dst.count = ss.count;
-        dst.den = ss.den;
-    }
+}
+
+// Uniform constants of the contrast set, built once per workgroup from the
+// kernel argument (scalar registers), so the tile loop reloads nothing.
+struct SConst {
+    int count;
+    int64_t den, scale;   // scale = 16 den^2 (<= 2^24, exact in float)
+    float inv_scale;      // 1 / scale, correctly rounded
+};
+
+__device__ inline SConst make_sconst(const SSet &ss) {
+    SConst c;
+    c.count = ss.count;
+    c.den = ss.den;
+    c.scale = 16 * c.den * c.den;
+    c.inv_scale = 1.0f / (float)c.scale;
+    return c;
 }
 
 // Exact evaluation of one (range, domain) pair given C'max.  Updates the
@@ -61,24 +84,25 @@ __device__ inline void load_sset(SLds &dst, const SSet &ss) {
 // only grows, so equal values keep the earlier domain.
 __device__ __forceinline__ void confirm_pair(int cmax, int p, int r, int n, const RInfo *__restrict__ ri,
                                              const uint32_t *__restrict__ sum4, const int64_t *__restrict__ pa,
-                                             const SLds &ss, int64_t &best, int &bp, int &bk) {
+                                             const SLds &ss, const SConst &sc, int64_t &best, int &bp,
+                                             int &bk) {
     const RInfo x = ri[r];
     const int64_t sd4 = sum4[p], A = pa[p];
     const int64_t sr = x.sr;
     const int64_t x4 = (int64_t)cmax + 128 * sd4 + 512 * sr - 65536 * (int64_t)n;
     const int64_t bx = (int64_t)n * x4 - sr * sd4;
-    const int64_t den = ss.den;
+    const int64_t den = sc.den;
     const int64_t lhs = 8 * den * bx;
     // midpoint rule: s_{j+1} beats s_j iff 8 den Bx > A (num_j + num_{j+1}); the
     // predicate is monotone (true, then false) in j, so k* = the first false j
-    int lo = 0, hi = ss.count - 1;
+    int lo = 0, hi = sc.count - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (lhs > A * (int64_t)(ss.num[mid] + ss.num[mid + 1])) lo = mid + 1;
         else hi = mid;
     }
     const int64_t nk = ss.num[lo];
-    const int64_t val = nk * nk * A - 8 * nk * den * bx + 16 * den * den * x.cr;
+    const int64_t val = nk * nk * A - 8 * nk * den * bx + sc.scale * x.cr;
     if (val < best) {
         best = val;
         bp = p;
@@ -92,13 +116,12 @@ __device__ __forceinline__ void confirm_pair(int cmax, int p, int r, int n, cons
 // A best of 0 cannot be beaten (val >= 0) and later domains lose ties, so the
 // range is done: NaN makes every later comparison false.  This matters for
 // flat ranges, where every pair ties at 0 and would pass a non-strict test.
-__device__ __forceinline__ float tn_from(int64_t best, int64_t cr, int den, int n) {
-    const int64_t scale = 16 * (int64_t)den * den;
+__device__ __forceinline__ float tn_from(int64_t best, int64_t cr, const SConst &sc, int n) {
     if (best == 0) return __builtin_nanf("");
     if (best == INT64_MAX) return -1e30f;
-    const int64_t num = scale * cr - best;
+    const int64_t num = sc.scale * cr - best;
     if (num < 0) return -1e30f;
-    const float c = (float)num * (1.0f / (float)scale);
+    const float c = (float)num * sc.inv_scale;
     return sqrtf(c) * (1.0f - 1.0f / 1048576.0f) / (float)n;
 }
 

@@ -24,8 +24,9 @@ K_LEVEL0, K_KEYS, K_HIST, K_PCMP, K_MOM, K_RANGE, K_AFRAG, K_BFRAG, K_VIEWS, K_D
     range(13)
 KIND_OF = [("k_level0", K_LEVEL0), ("k_pool_keys", K_KEYS), ("k_sel_hist", K_HIST), ("k_pool_moments", K_MOM),
            ("k_range_info", K_RANGE), ("k_mfma_afrag", K_AFRAG), ("k_mfma_bfrag", K_BFRAG),
+           ("k_f16_afrag", K_AFRAG), ("k_f16_bfrag", K_BFRAG),
            ("k_fp32_views", K_VIEWS), ("k_fp32_doms", K_DOMS), ("k_mfma_search", K_SEARCH),
-           ("k_fp32_search", K_SEARCH), ("k_finalize", K_FINAL)]
+           ("k_f16_search", K_SEARCH), ("k_fp32_search", K_SEARCH), ("k_finalize", K_FINAL)]
 PER_IMAGE = ("k_sel_init", "k_sel_pick", "k_bscan")
 KIND_ARG = ("k_bcount", "k_bscatter")
 NUM_KINDS = 13
@@ -61,8 +62,8 @@ def on_launch(name, grid, block, args):
         want = pre[kind, n]
         if short == "k_finalize":
             want = max(1, want)
-        if short == "k_mfma_search" and (pre[kind] % 8 != 0).any():
-            log["errors"].append("k_mfma_search: an image's workgroups do not start on a multiple of 8")
+        if short in ("k_mfma_search", "k_f16_search") and (pre[kind] % 8 != 0).any():
+            log["errors"].append("%s: an image's workgroups do not start on a multiple of 8" % short)
     if grid != want:
         log["errors"].append("%s: grid %d, planned %d" % (short, grid, want))
     log["launches"].append((short, grid, kind))
@@ -127,12 +128,14 @@ def main():
         st = fn()
         out[name] = {"status": st, "errors": list(log["errors"]), "launches": list(log["launches"])}
 
-    M, F = fic.ENGINE_MFMA, fic.ENGINE_FP32
+    M, F, I8, H = fic.ENGINE_MFMA, fic.ENGINE_FP32, fic.ENGINE_MFMA_I8, fic.ENGINE_MFMA_F16
     mixed = [(128, 128), (256, 128), (64, 128), (1024, 512), (96, 96), (512, 512), (32, 32), (208, 144)]
     scenario("single_mfma", lambda: encode_case(L, h, [(64, 64)], [(8, 1), (4, 1)], M))
     scenario("single_fp32", lambda: encode_case(L, h, [(64, 64)], [(8, 1), (4, 1)], F))
     scenario("mixed_mfma_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], M))
     scenario("mixed_fp32_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], F))
+    scenario("mixed_i8_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], I8))
+    scenario("mixed_f16_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], H))
     scenario("mixed_b32_4lv", lambda: encode_case(L, h, [(256, 256), (128, 64), (64, 64)],
                                                   [(32, 4), (16, 4), (8, 4), (4, 4)], M))
     scenario("paper_b2_cap", lambda: encode_case(L, h, [(64, 64), (32, 48)], [(16, 4), (8, 4), (4, 4), (2, 4)], M,

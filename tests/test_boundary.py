@@ -73,7 +73,8 @@ BAD = [
     ("rms_den0", lambda p: p.split_rms.__setitem__(0, fic.Ratio(8, 0))),
     ("rms_den17", lambda p: p.split_rms.__setitem__(0, fic.Ratio(8, 17))),
     ("rms_neg", lambda p: p.split_rms.__setitem__(0, fic.Ratio(-1, 1))),
-    ("engine2", lambda p: setattr(p, "engine", 2)),
+    ("engine4", lambda p: setattr(p, "engine", 4)),
+    ("engine_neg", lambda p: setattr(p, "engine", -1)),
 ]
 
 

@@ -1,7 +1,7 @@
 """Parity of the HIP encoder and decoder with the oracle, element by element:
 pools (xy, key, sum4, A), codes (range xy, split, domain, isometry, s index,
-offset, val_q), the child lists and the decoded image, for both search
-engines.  Inputs are seeded synthetic images (paper_1502_00324_amd.synth)."""
+offset, val_q), the child lists and the decoded image, for every search
+engine (default MFMA mix, plain FP32, int8 MFMA, f16 MFMA).  Inputs are seeded synthetic images (paper_1502_00324_amd.synth)."""
 import math
 import os
 
@@ -16,8 +16,8 @@ from paper_1502_00324_amd.synth import make_image
 
 pytestmark = pytest.mark.gpu
 WORKERS = max(1, min(16, os.cpu_count() or 1))
-ENGINES = [fic.ENGINE_MFMA, fic.ENGINE_FP32]
-ENGINE_IDS = ["mfma", "fp32"]
+ENGINES = [fic.ENGINE_MFMA, fic.ENGINE_FP32, fic.ENGINE_MFMA_I8, fic.ENGINE_MFMA_F16]
+ENGINE_IDS = ["mfma", "fp32", "mfma_i8", "mfma_f16"]
 
 
 @pytest.fixture(scope="module")

@@ -35,8 +35,9 @@ def runs(tmp_path_factory):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-SCENARIOS = ["single_mfma", "single_fp32", "mixed_mfma_3lv", "mixed_fp32_3lv", "mixed_b32_4lv", "paper_b2_cap",
-             "min_images", "timing_toggle"]
+SCENARIOS = ["single_mfma", "single_fp32", "mixed_mfma_3lv", "mixed_fp32_3lv", "mixed_i8_3lv", "mixed_f16_3lv",
+             "mixed_b32_4lv",
+             "paper_b2_cap", "min_images", "timing_toggle"]
 
 
 @pytest.mark.parametrize("name", SCENARIOS)
@@ -55,16 +56,24 @@ def test_one_launch_set_per_level(runs):
     # a batch of 8 images runs the same kernels as a batch of one
     k8, k1 = kinds(runs["mixed_mfma_3lv"]), kinds(runs["single_mfma"])
     per_rep8 = len(k8) // 2
-    assert k8.count("k_mfma_search") == 2 * 3 and k1.count("k_mfma_search") == 2 * 2
+    n8 = k8.count("k_f16_search") + k8.count("k_mfma_search")
+    n1 = k1.count("k_f16_search") + k1.count("k_mfma_search")
+    assert n8 == 2 * 3 and n1 == 2 * 2
     assert k8.count("k_level0") == 2
     assert per_rep8 < 120
 
 
 def test_engine_choice(runs):
-    assert "k_fp32_search" not in kinds(runs["mixed_mfma_3lv"])
-    assert "k_mfma_search" not in kinds(runs["mixed_fp32_3lv"])
+    m, f = kinds(runs["mixed_mfma_3lv"]), kinds(runs["mixed_fp32_3lv"])
+    i8, h = kinds(runs["mixed_i8_3lv"]), kinds(runs["mixed_f16_3lv"])
+    # default: f16 at B=4, int8 at B=8 and 16
+    assert "k_fp32_search" not in m and m.count("k_f16_search") == 2 and m.count("k_mfma_search") == 4
+    assert "k_mfma_search" not in f and "k_f16_search" not in f
+    assert i8.count("k_mfma_search") == 2 * 3 and "k_f16_search" not in i8
+    assert h.count("k_f16_search") == 2 * 3 and "k_mfma_search" not in h
     # B=32 and B=2 levels take the FP32 engine even when MFMA is asked for
-    assert "k_fp32_search" in kinds(runs["mixed_b32_4lv"]) and "k_mfma_search" in kinds(runs["mixed_b32_4lv"])
+    assert "k_fp32_search" in kinds(runs["mixed_b32_4lv"]) and "k_f16_search" in kinds(runs["mixed_b32_4lv"])
+    assert "k_mfma_search" in kinds(runs["mixed_b32_4lv"])
     assert "k_fp32_search" in kinds(runs["paper_b2_cap"])
 
 
