@@ -36,24 +36,25 @@ typedef float f16x __attribute__((ext_vector_type(16)));
 
 bool f16_supported(int B) { return B == 4 || B == 8 || B == 16; }
 
-// Range quads per wave (RQ) and domain tiles per LDS stage (DT); the first
-// entry per size is the measured default, FIC_F16_SHAPE="rq,dt" selects
-// another compiled one.
-struct F16Shape { int B, rq, dt; };
+// Range quads per wave (RQ), domain tiles per LDS stage (DT) and the
+// occupancy the register allocation aims at (waves per SIMD); the first entry
+// per size is the measured default, FIC_F16_SHAPE="rq,dt,wpe" selects another
+// compiled one.
+struct F16Shape { int B, rq, dt, wpe; };
 static const F16Shape kF16Shapes[] = {
-    {4, 1, 8}, {4, 2, 8}, {4, 4, 8}, {4, 2, 16},
-    {8, 2, 4}, {8, 1, 4}, {8, 2, 2}, {8, 4, 4},
-    {16, 1, 1}, {16, 2, 1}, {16, 1, 2},
+    {4, 1, 8, 4}, {4, 2, 8, 2}, {4, 1, 16, 4}, {4, 2, 4, 3},
+    {8, 2, 4, 2}, {8, 1, 4, 3}, {8, 1, 8, 3}, {8, 2, 2, 2},
+    {16, 1, 1, 3}, {16, 1, 2, 2},
 };
 static F16Shape f16_shape(int B) {
     const char *e = getenv("FIC_F16_SHAPE");
-    int rq = 0, dt = 0;
-    if (e && sscanf(e, "%d,%d", &rq, &dt) == 2)
+    int rq = 0, dt = 0, wpe = 0;
+    if (e && sscanf(e, "%d,%d,%d", &rq, &dt, &wpe) == 3)
         for (const F16Shape &s : kF16Shapes)
-            if (s.B == B && s.rq == rq && s.dt == dt) return s;
+            if (s.B == B && s.rq == rq && s.dt == dt && s.wpe == wpe) return s;
     for (const F16Shape &s : kF16Shapes)
         if (s.B == B) return s;
-    return F16Shape{B, 1, 1};
+    return F16Shape{B, 1, 1, 1};
 }
 
 MfmaGeom f16_geometry(int B, int range_cap, int pool_cap) {
@@ -144,13 +145,14 @@ __global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
 // domain tiles of its chunks.  Domain fragments go global -> registers -> LDS
 // in stages of DT tiles, double-buffered; the MFMAs of tile t+1 are issued
 // before the prune test of tile t.
-template <int KS, int RQ, int DT>
-__global__ __launch_bounds__(256) void k_f16_search(BatchDev bt, SSet ss) {
+template <int KS, int RQ, int DT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_f16_search(BatchDev bt, SSet ss) {
     constexpr int STAGE = DT * KS * 64;          // uint4 per stage
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
     __shared__ uint4 bl[2][STAGE];
-    __shared__ float2 dl[2][DT * kDomTile32];
+    __shared__ float2 dl[2][DT * kDomTile32];     // (Sd4, sqrt A) per domain
+    __shared__ int64_t dla[2][DT * kDomTile32];   // exact A per domain
     __shared__ SLds sl;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
@@ -165,10 +167,10 @@ __global__ __launch_bounds__(256) void k_f16_search(BatchDev bt, SSet ss) {
     const uint4 *__restrict__ bfrag = dsc.bfrag;
     const float2 *__restrict__ dinfo = dsc.dinfo;
     const RInfo *__restrict__ ri = dsc.ri;
-    const uint32_t *__restrict__ sum4 = dsc.psum4;
     const int64_t *__restrict__ pa = dsc.pa;
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
+    const float tfac = tn_factor(n);
     int rg, cfirst, cstep, ncs, slot;
     chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
     const int R = min(*dsc.nr, range_cap), P = min(*dsc.pcount, pool_cap);
@@ -181,8 +183,8 @@ __global__ __launch_bounds__(256) void k_f16_search(BatchDev bt, SSet ss) {
     // per lane: two ranges per quad, 4 q + 2 hh + u for u = 0, 1
     h8 A[RQ][KS];
     float tn[RQ][2], bn[RQ][2], an[RQ][2];
-    int64_t best[RQ][2];
-    int bp[RQ][2], bk[RQ][2], rr[RQ][2];
+    int64_t best[RQ][2], cr[RQ][2];
+    int bp[RQ][2], bk[RQ][2], rr[RQ][2], sr[RQ][2];
 #pragma unroll
     for (int qi = 0; qi < RQ; ++qi) {
 #pragma unroll
@@ -194,6 +196,8 @@ __global__ __launch_bounds__(256) void k_f16_search(BatchDev bt, SSet ss) {
             const RInfo x = ri[r < R ? r : 0];
             bn[qi][u] = x.bn;
             an[qi][u] = x.an;
+            sr[qi][u] = (int)x.sr;
+            cr[qi][u] = x.cr;
             tn[qi][u] = r < R ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
             best[qi][u] = INT64_MAX;
             bp[qi][u] = INT32_MAX;
@@ -206,6 +210,7 @@ __global__ __launch_bounds__(256) void k_f16_search(BatchDev bt, SSet ss) {
 
     uint4 pre[PER_T];
     float2 dpre = make_float2(0.f, 0.f);
+    int64_t apre = 0;
     int t0 = 0, t1 = 0;
     auto gload = [&](int stg) {
         const int tbase = t0 + stg * DT;
@@ -215,14 +220,19 @@ __global__ __launch_bounds__(256) void k_f16_search(BatchDev bt, SSet ss) {
             pre[i] = tbase + e / (KS * 64) < t1 ? bfrag[(size_t)tbase * KS * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
         }
         // tiles past the chunk end get NaN moments: no pair on them passes
-        if (tid < DT * kDomTile32)
-            dpre = tbase + tid / kDomTile32 < t1 ? dinfo[(size_t)tbase * kDomTile32 + tid]
-                                                 : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+        if (tid < DT * kDomTile32) {
+            const int p = tbase * kDomTile32 + tid;
+            dpre = tbase + tid / kDomTile32 < t1 ? dinfo[p] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+            apre = p < P ? pa[p] : 0;
+        }
     };
     auto swrite = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
-        if (tid < DT * kDomTile32) dl[buf][tid] = dpre;
+        if (tid < DT * kDomTile32) {
+            dl[buf][tid] = dpre;
+            dla[buf][tid] = apre;
+        }
     };
     // the tile's fragments are read up front (in groups of up to 8 K-steps),
     // so one LDS wait covers a group rather than every MFMA
@@ -284,19 +294,22 @@ __global__ __launch_bounds__(256) void k_f16_search(BatchDev bt, SSet ss) {
                             any |= pass[qi][u];
                         }
                     if (__builtin_amdgcn_ballot_w64(any)) {  // rare: exact evaluation, then share the best
-                        const int p = (tbase + dt) * kDomTile32 + (lane & 31);
+                        const int col = dt * kDomTile32 + (lane & 31);
+                        const int p = tbase * kDomTile32 + col;
+                        const int64_t sd4 = (int64_t)di.x, A = dla[buf][col];  // Sd4 < 2^24: exact in float
 #pragma unroll
                         for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
                             for (int u = 0; u < 2; ++u) {
+                                bool imp = false;
                                 if (pass[qi][u])
-                                    confirm_pair((int)mx[qi][u], p, rr[qi][u], n, ri, sum4, pa, sl, sc, best[qi][u],
-                                                 bp[qi][u], bk[qi][u]);
-                                if (__builtin_amdgcn_ballot_w64(pass[qi][u])) {
+                                    imp = confirm_pair((int)mx[qi][u], p, sd4, A, sr[qi][u], cr[qi][u], n, sl, sc,
+                                                       best[qi][u], bp[qi][u], bk[qi][u]);
+                                if (__builtin_amdgcn_ballot_w64(imp)) {
                                     // the 32 lanes holding this range share their best: a
                                     // pair is only rejected when it cannot even tie it
                                     const int64_t gb = group_min_val<32>(best[qi][u]);
-                                    if (rr[qi][u] >= 0) tn[qi][u] = tn_from(gb, ri[rr[qi][u]].cr, sc, n);
+                                    if (rr[qi][u] >= 0) tn[qi][u] = tn_from(gb, cr[qi][u], sc, tfac);
                                 }
                             }
                     }
@@ -332,9 +345,9 @@ hipError_t launch_f16_prep_b(const BatchHost &b, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int KS, int RQ, int DT>
+template <int KS, int RQ, int DT, int WPE>
 static hipError_t launch_f16_t(const BatchHost &b, hipStream_t st) {
-    k_f16_search<KS, RQ, DT><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
+    k_f16_search<KS, RQ, DT, WPE><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
     return hipGetLastError();
 }
 
@@ -342,22 +355,21 @@ hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st) {
     if (b.blocks[K_SEARCH] == 0) return hipSuccess;
     const int B = b.B;
     const F16Shape sh = f16_shape(B);
-#define FIC_F16(KS, RQ, DT) \
-    if (sh.rq == RQ && sh.dt == DT) return launch_f16_t<KS, RQ, DT>(b, st)
+#define FIC_F16(KS, RQ, DT, WPE) \
+    if (sh.rq == RQ && sh.dt == DT && sh.wpe == WPE) return launch_f16_t<KS, RQ, DT, WPE>(b, st)
     if (B == 4) {
-        FIC_F16(1, 2, 8);
-        FIC_F16(1, 1, 8);
-        FIC_F16(1, 4, 8);
-        FIC_F16(1, 2, 16);
+        FIC_F16(1, 1, 8, 4);
+        FIC_F16(1, 2, 8, 2);
+        FIC_F16(1, 1, 16, 4);
+        FIC_F16(1, 2, 4, 3);
     } else if (B == 8) {
-        FIC_F16(4, 2, 4);
-        FIC_F16(4, 1, 4);
-        FIC_F16(4, 2, 2);
-        FIC_F16(4, 4, 4);
+        FIC_F16(4, 2, 4, 2);
+        FIC_F16(4, 1, 4, 3);
+        FIC_F16(4, 1, 8, 3);
+        FIC_F16(4, 2, 2, 2);
     } else if (B == 16) {
-        FIC_F16(16, 1, 1);
-        FIC_F16(16, 2, 1);
-        FIC_F16(16, 1, 2);
+        FIC_F16(16, 1, 1, 3);
+        FIC_F16(16, 1, 2, 2);
     }
 #undef FIC_F16
     return hipErrorInvalidValue;

@@ -99,6 +99,7 @@ __global__ __launch_bounds__(256) void k_fp32_search(BatchDev bt, SSet ss) {
     const int tid = threadIdx.x, tr = tid >> 5, td = tid & 31;
     load_sset(sl, ss);
     const SConst sc = make_sconst(ss);
+    const float tfac = tn_factor(B * B);
     __syncthreads();
     const int *bpre = bt.pre + K_SEARCH * (bt.n + 1);
     const int im = find_img(bpre, bt.n, blockIdx.x);
@@ -182,12 +183,12 @@ __global__ __launch_bounds__(256) void k_fp32_search(BatchDev bt, SSet ss) {
             const float2 di = dinfo[p];
             const float rhs = fmaf(tn, di.y, fmaf(-bn, di.x, -an));
             const bool pass = (p < P) & rvalid & ((float)m > rhs);
-            if (pass) confirm_pair(m, p, r, n, ri, sum4, pa, sl, sc, best, bp, bk);
+            if (pass) confirm_pair(m, p, sum4[p], pa[p], x.sr, x.cr, n, sl, sc, best, bp, bk);
             any |= pass;
         }
         if (__ballot(any)) {  // share the best of the 32 threads holding this range
             const int64_t gb = group_min_val<32>(best);
-            tn = rvalid ? tn_from(gb, x.cr, sc, n) : -1e30f;
+            tn = rvalid ? tn_from(gb, x.cr, sc, tfac) : -1e30f;
         }
     }
     group_min<32>(best, bp, bk);

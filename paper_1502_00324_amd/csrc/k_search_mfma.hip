@@ -37,24 +37,25 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 bool mfma_supported(int B) { return B == 4 || B == 8 || B == 16; }
 
-// Operand form (pl), range quads per wave (RQ) and domain tiles per LDS
-// stage (DT).  Each range size has a measured default (its first entry);
-// FIC_MFMA_SHAPE="pl,rq,dt" selects another compiled shape (used to tune).
-struct Shape { int B, pl, rq, dt; };
+// Operand form (pl), range quads per wave (RQ), domain tiles per LDS stage
+// (DT) and the occupancy the register allocation aims at (waves per SIMD).
+// Each range size has a measured default (its first entry);
+// FIC_MFMA_SHAPE="pl,rq,dt,wpe" selects another compiled shape (used to tune).
+struct Shape { int B, pl, rq, dt, wpe; };
 static const Shape kShapes[] = {
-    {4, 1, 2, 16}, {4, 1, 1, 16}, {4, 1, 4, 16},
-    {8, 2, 2, 8}, {8, 2, 2, 16}, {8, 2, 1, 8}, {8, 2, 3, 8}, {8, 2, 4, 8}, {8, 1, 2, 8},
-    {16, 2, 2, 1}, {16, 2, 2, 2}, {16, 2, 1, 1}, {16, 2, 1, 2}, {16, 1, 1, 1},
+    {4, 1, 2, 16, 3}, {4, 1, 1, 16, 3}, {4, 1, 4, 16, 2},
+    {8, 2, 2, 8, 3}, {8, 2, 2, 16, 2}, {8, 2, 1, 8, 4}, {8, 2, 3, 8, 2}, {8, 2, 4, 8, 2}, {8, 1, 2, 8, 2},
+    {16, 2, 2, 1, 3}, {16, 2, 2, 1, 2}, {16, 2, 1, 2, 3}, {16, 2, 2, 2, 2}, {16, 2, 1, 1, 4}, {16, 1, 1, 1, 2},
 };
 static Shape mfma_shape(int B) {
     const char *e = getenv("FIC_MFMA_SHAPE");
-    int pl = 0, rq = 0, dt = 0;
-    if (e && sscanf(e, "%d,%d,%d", &pl, &rq, &dt) == 3)
+    int pl = 0, rq = 0, dt = 0, wpe = 0;
+    if (e && sscanf(e, "%d,%d,%d,%d", &pl, &rq, &dt, &wpe) == 4)
         for (const Shape &s : kShapes)
-            if (s.B == B && s.pl == pl && s.rq == rq && s.dt == dt) return s;
+            if (s.B == B && s.pl == pl && s.rq == rq && s.dt == dt && s.wpe == wpe) return s;
     for (const Shape &s : kShapes)
         if (s.B == B) return s;
-    return Shape{B, 1, 1, 1};
+    return Shape{B, 1, 1, 1, 1};
 }
 
 // Work split (both matrix engines).  A workgroup owns rpw ranges (a range
@@ -195,14 +196,15 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
 // of domain tiles.  Domain fragments go global -> registers -> LDS in stages
 // of DT tiles, double-buffered: the loads for stage s+1 are issued before the
 // MFMAs of stage s and written to the other LDS buffer after them.
-template <int KA, int PL, int RQ, int DT>
-__global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
+template <int KA, int PL, int RQ, int DT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_mfma_search(BatchDev bt, SSet ss) {
     constexpr int KB = KA * PL;                  // K-steps of a domain tile
     constexpr int STAGE = DT * KB * 64;          // uint4 per stage
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
     __shared__ uint4 bl[2][STAGE];
-    __shared__ float2 dl[2][DT * kDomTile];
+    __shared__ float2 dl[2][DT * kDomTile];     // (Sd4, sqrt A) per domain
+    __shared__ int64_t dla[2][DT * kDomTile];   // exact A per domain
     __shared__ SLds sl;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
@@ -217,10 +219,10 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
     const uint4 *__restrict__ bfrag = dsc.bfrag;
     const float2 *__restrict__ dinfo = dsc.dinfo;
     const RInfo *__restrict__ ri = dsc.ri;
-    const uint32_t *__restrict__ sum4 = dsc.psum4;
     const int64_t *__restrict__ pa = dsc.pa;
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
+    const float tfac = tn_factor(n);
     const int32_t *nr = dsc.nr, *np = dsc.pcount;
     int rg, cfirst, cstep, ncs, slot;
     chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
@@ -233,8 +235,8 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
 
     v4i A[RQ][2][KA];
     float tn[RQ], bn[RQ], an[RQ];
-    int64_t best[RQ];
-    int bp[RQ], bk[RQ], rr[RQ];
+    int64_t best[RQ], cr[RQ];
+    int bp[RQ], bk[RQ], rr[RQ], sr[RQ];
 #pragma unroll
     for (int qi = 0; qi < RQ; ++qi) {
 #pragma unroll
@@ -246,6 +248,8 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
         const RInfo x = ri[r < R ? r : 0];
         bn[qi] = x.bn;
         an[qi] = x.an;
+        sr[qi] = (int)x.sr;
+        cr[qi] = x.cr;
         tn[qi] = r < R ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
         best[qi] = INT64_MAX;
         bp[qi] = INT32_MAX;
@@ -258,6 +262,7 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
 
     uint4 pre[PER_T];
     float2 dpre = make_float2(0.f, 0.f);
+    int64_t apre = 0;
     int t0 = 0, t1 = 0;  // tile range of the chunk being streamed
     auto gload = [&](int stg) {
         const int tbase = t0 + stg * DT;
@@ -267,14 +272,19 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
             pre[i] = tbase + e / (KB * 64) < t1 ? bfrag[(size_t)tbase * KB * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
         }
         // tiles past the chunk end get NaN moments: no pair on them passes
-        if (tid < DT * kDomTile)
-            dpre = tbase + tid / kDomTile < t1 ? dinfo[(size_t)tbase * kDomTile + tid]
-                                               : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+        if (tid < DT * kDomTile) {
+            const int p = tbase * kDomTile + tid;
+            dpre = tbase + tid / kDomTile < t1 ? dinfo[p] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+            apre = p < P ? pa[p] : 0;
+        }
     };
     auto swrite = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
-        if (tid < DT * kDomTile) dl[buf][tid] = dpre;
+        if (tid < DT * kDomTile) {
+            dl[buf][tid] = dpre;
+            dla[buf][tid] = apre;
+        }
     };
     // acc[qi][h][plane]: the planes are combined (4 hi + lo) at the test,
     // one tile later, so no MFMA result is waited for at issue time
@@ -342,16 +352,19 @@ __global__ __launch_bounds__(256) void k_mfma_search(BatchDev bt, SSet ss) {
                     any |= pass[qi];
                 }
                 if (__builtin_amdgcn_ballot_w64(any)) {  // rare: exact evaluation, then share the best
-                    const int p = (tbase + dt) * kDomTile + (lane & 15);
+                    const int col = dt * kDomTile + (lane & 15);
+                    const int p = tbase * kDomTile + col;
+                    const int64_t sd4 = (int64_t)di.x, A = dla[buf][col];  // Sd4 < 2^24: exact in float
 #pragma unroll
                     for (int qi = 0; qi < RQ; ++qi) {
-                        if (pass[qi]) confirm_pair(mx[qi], p, rr[qi], n, ri, sum4, pa, sl, sc, best[qi], bp[qi], bk[qi]);
-                        if (__builtin_amdgcn_ballot_w64(pass[qi])) {
+                        bool imp = false;
+                        if (pass[qi]) imp = confirm_pair(mx[qi], p, sd4, A, sr[qi], cr[qi], n, sl, sc, best[qi], bp[qi], bk[qi]);
+                        if (__builtin_amdgcn_ballot_w64(imp)) {
                             // the 16 lanes holding this range share their best: the
                             // threshold may use it because a pair is only rejected
                             // when it cannot even tie it
                             const int64_t gb = group_min_val<16>(best[qi]);
-                            if (rr[qi] >= 0) tn[qi] = tn_from(gb, ri[rr[qi]].cr, sc, n);
+                            if (rr[qi] >= 0) tn[qi] = tn_from(gb, cr[qi], sc, tfac);
                         }
                     }
                 }
@@ -385,9 +398,9 @@ hipError_t launch_mfma_prep_b(const BatchHost &b, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int KA, int PL, int RQ, int DT>
+template <int KA, int PL, int RQ, int DT, int WPE>
 static hipError_t launch_search_t(const BatchHost &b, hipStream_t st) {
-    k_mfma_search<KA, PL, RQ, DT><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
+    k_mfma_search<KA, PL, RQ, DT, WPE><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
     return hipGetLastError();
 }
 
@@ -395,25 +408,26 @@ hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
     if (b.blocks[K_SEARCH] == 0) return hipSuccess;
     const int B = b.B;
     const Shape sh = mfma_shape(B);
-#define FIC_SEARCH(KA, PL, RQ, DT) \
-    if (sh.pl == PL && sh.rq == RQ && sh.dt == DT) return launch_search_t<KA, PL, RQ, DT>(b, st)
+#define FIC_SEARCH(KA, PL, RQ, DT, WPE) \
+    if (sh.pl == PL && sh.rq == RQ && sh.dt == DT && sh.wpe == WPE) return launch_search_t<KA, PL, RQ, DT, WPE>(b, st)
     if (B == 4) {
-        FIC_SEARCH(1, 1, 2, 16);
-        FIC_SEARCH(1, 1, 1, 16);
-        FIC_SEARCH(1, 1, 4, 16);
+        FIC_SEARCH(1, 1, 2, 16, 3);
+        FIC_SEARCH(1, 1, 1, 16, 3);
+        FIC_SEARCH(1, 1, 4, 16, 2);
     } else if (B == 8) {
-        FIC_SEARCH(1, 2, 2, 8);
-        FIC_SEARCH(1, 2, 2, 16);
-        FIC_SEARCH(1, 2, 1, 8);
-        FIC_SEARCH(1, 2, 3, 8);
-        FIC_SEARCH(1, 2, 4, 8);
-        FIC_SEARCH(4, 1, 2, 8);
+        FIC_SEARCH(1, 2, 2, 8, 3);
+        FIC_SEARCH(1, 2, 2, 16, 2);
+        FIC_SEARCH(1, 2, 1, 8, 4);
+        FIC_SEARCH(1, 2, 3, 8, 2);
+        FIC_SEARCH(1, 2, 4, 8, 2);
+        FIC_SEARCH(4, 1, 2, 8, 2);
     } else if (B == 16) {
-        FIC_SEARCH(4, 2, 1, 2);
-        FIC_SEARCH(4, 2, 2, 2);
-        FIC_SEARCH(4, 2, 1, 1);
-        FIC_SEARCH(4, 2, 2, 1);
-        FIC_SEARCH(16, 1, 1, 1);
+        FIC_SEARCH(4, 2, 2, 1, 3);
+        FIC_SEARCH(4, 2, 2, 1, 2);
+        FIC_SEARCH(4, 2, 1, 2, 3);
+        FIC_SEARCH(4, 2, 2, 2, 2);
+        FIC_SEARCH(4, 2, 1, 1, 4);
+        FIC_SEARCH(16, 1, 1, 1, 2);
     }
 #undef FIC_SEARCH
     return hipErrorInvalidValue;

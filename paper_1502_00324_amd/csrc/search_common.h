@@ -79,16 +79,13 @@ __device__ inline SConst make_sconst(const SSet &ss) {
     return c;
 }
 
-// Exact evaluation of one (range, domain) pair given C'max.  Updates the
-// lane's running best with a strict comparison: along a lane the domain index
-// only grows, so equal values keep the earlier domain.
-__device__ __forceinline__ void confirm_pair(int cmax, int p, int r, int n, const RInfo *__restrict__ ri,
-                                             const uint32_t *__restrict__ sum4, const int64_t *__restrict__ pa,
-                                             const SLds &ss, const SConst &sc, int64_t &best, int &bp,
-                                             int &bk) {
-    const RInfo x = ri[r];
-    const int64_t sd4 = sum4[p], A = pa[p];
-    const int64_t sr = x.sr;
+// Exact evaluation of one (range, domain) pair given C'max, the domain
+// moments (Sd4, A) and the range moments (Sr, Cr), all exact integers.
+// Updates the lane's running best with a strict comparison (along a lane the
+// domain index only grows, so equal values keep the earlier domain) and
+// returns whether it improved.
+__device__ __forceinline__ bool confirm_pair(int cmax, int p, int64_t sd4, int64_t A, int64_t sr, int64_t cr, int n,
+                                             const SLds &ss, const SConst &sc, int64_t &best, int &bp, int &bk) {
     const int64_t x4 = (int64_t)cmax + 128 * sd4 + 512 * sr - 65536 * (int64_t)n;
     const int64_t bx = (int64_t)n * x4 - sr * sd4;
     const int64_t den = sc.den;
@@ -102,27 +99,33 @@ __device__ __forceinline__ void confirm_pair(int cmax, int p, int r, int n, cons
         else hi = mid;
     }
     const int64_t nk = ss.num[lo];
-    const int64_t val = nk * nk * A - 8 * nk * den * bx + sc.scale * x.cr;
+    const int64_t val = nk * nk * A - 8 * nk * den * bx + sc.scale * cr;
     if (val < best) {
         best = val;
         bp = p;
         bk = lo;
+        return true;
     }
+    return false;
 }
 
-// Prune threshold tn = sqrt(Cr - best/(16 den^2)) / n, rounded down: every
-// float step below rounds by at most 2^-24 relative, and the 1 - 2^-20
-// factor covers them all.  No improvement yet (or c < 0): every pair passes.
-// A best of 0 cannot be beaten (val >= 0) and later domains lose ties, so the
-// range is done: NaN makes every later comparison false.  This matters for
-// flat ranges, where every pair ties at 0 and would pass a non-strict test.
-__device__ __forceinline__ float tn_from(int64_t best, int64_t cr, const SConst &sc, int n) {
+// (1 - 2^-20) / n, the final factor of the prune threshold below.
+__device__ inline float tn_factor(int n) { return (1.0f - 1.0f / 1048576.0f) / (float)n; }
+
+// Prune threshold tn = sqrt(Cr - best/(16 den^2)) / n, rounded down: the int
+// to float conversion, the two products, the square root and the factor each
+// round by at most 2^-24 relative, and the 1 - 2^-20 in the factor covers
+// them all.  No improvement yet (or c < 0): every pair passes.  A best of 0
+// cannot be beaten (val >= 0) and later domains lose ties, so the range is
+// done: NaN makes every later comparison false.  This matters for flat
+// ranges, where every pair ties at 0 and would pass a non-strict test.
+__device__ __forceinline__ float tn_from(int64_t best, int64_t cr, const SConst &sc, float factor) {
     if (best == 0) return __builtin_nanf("");
     if (best == INT64_MAX) return -1e30f;
     const int64_t num = sc.scale * cr - best;
     if (num < 0) return -1e30f;
     const float c = (float)num * sc.inv_scale;
-    return sqrtf(c) * (1.0f - 1.0f / 1048576.0f) / (float)n;
+    return sqrtf(c) * factor;
 }
 
 template <int WIDTH>
