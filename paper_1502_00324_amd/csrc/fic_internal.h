@@ -33,6 +33,7 @@ struct RInfo {
     float bn;        // (128 n - Sr) / n
     float an;        // (512 n Sr - 65536 n^2) / n + margin
     float pad;
+    int64_t gbest;   // best val found so far by any search workgroup (atomic min)
 };
 
 // One search partial: the best code of a range within one domain chunk.

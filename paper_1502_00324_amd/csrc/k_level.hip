@@ -54,6 +54,7 @@ __global__ __launch_bounds__(256) void k_range_info(BatchDev b) {
         o.bn = (float)(128.0 - (double)s / n);
         o.an = (float)(512.0 * s - 65536.0 * n + (n / 4 + 4));
         o.pad = 0.f;
+        o.gbest = INT64_MAX;
         d.ri[r] = o;
     }
 }

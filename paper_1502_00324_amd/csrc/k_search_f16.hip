@@ -148,6 +148,9 @@ __global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
 template <int KS, int RQ, int DT, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_f16_search(BatchDev bt, SSet ss) {
     constexpr int STAGE = DT * KS * 64;          // uint4 per stage
+    // share range bests across workgroups only when a stage is long enough
+    // (>= 4 tiles) to hide the coherent load of the shared values
+    constexpr bool SHARE = DT >= 4;
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
     __shared__ uint4 bl[2][STAGE];
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const h8 *__restrict__ afrag = (const h8 *)dsc.afrag;
     const uint4 *__restrict__ bfrag = dsc.bfrag;
     const float2 *__restrict__ dinfo = dsc.dinfo;
-    const RInfo *__restrict__ ri = dsc.ri;
+    RInfo *__restrict__ ri = dsc.ri;
     const int64_t *__restrict__ pa = dsc.pa;
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // per lane: two ranges per quad, 4 q + 2 hh + u for u = 0, 1
     h8 A[RQ][KS];
     float tn[RQ][2], bn[RQ][2], an[RQ][2];
-    int64_t best[RQ][2], cr[RQ][2];
+    int64_t best[RQ][2], cr[RQ][2], tb[RQ][2];  // tb: the best value tn reflects
     int bp[RQ][2], bk[RQ][2], rr[RQ][2], sr[RQ][2];
 #pragma unroll
     for (int qi = 0; qi < RQ; ++qi) {
@@ -199,6 +202,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             sr[qi][u] = (int)x.sr;
             cr[qi][u] = x.cr;
             tn[qi][u] = r < R ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
+            tb[qi][u] = INT64_MAX;
             best[qi][u] = INT64_MAX;
             bp[qi][u] = INT32_MAX;
             bk[qi][u] = 0;
@@ -268,6 +272,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         for (int stg = 0; stg < nstage; ++stg) {
             const int buf = stg & 1;
             if (stg + 1 < nstage) gload(stg + 1);
+            // the range bests of other workgroups: issued after the stage
+            // prefetch (so its wait does not include them), applied at the end
+            int64_t gl[RQ][2];
+#pragma unroll
+            for (int qi = 0; qi < RQ; ++qi)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    gl[qi][u] = SHARE && rr[qi][u] >= 0 ? gbest_load(&ri[rr[qi][u]].gbest) : INT64_MAX;
             if (wave_on) {
                 const int tbase = t0 + stg * DT;
                 f16x acc[2][RQ];
@@ -309,13 +321,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                     // the 32 lanes holding this range share their best: a
                                     // pair is only rejected when it cannot even tie it
                                     const int64_t gb = group_min_val<32>(best[qi][u]);
-                                    if (rr[qi][u] >= 0) tn[qi][u] = tn_from(gb, cr[qi][u], sc, tfac);
+                                    if (rr[qi][u] >= 0 && gb <= tb[qi][u]) {
+                                        tb[qi][u] = gb;
+                                        tn[qi][u] = tn_from(gb, cr[qi][u], sc, tfac);
+                                        if (SHARE && (lane & 31) == 0) gbest_push(&ri[rr[qi][u]].gbest, gb);
+                                    }
                                 }
                             }
                     }
                 }
             }
             if (stg + 1 < nstage) swrite(buf ^ 1);
+#pragma unroll
+            for (int qi = 0; qi < RQ; ++qi)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (gl[qi][u] < tb[qi][u]) {
+                        tb[qi][u] = gl[qi][u];
+                        tn[qi][u] = tn_shared(gl[qi][u], cr[qi][u], sc, tfac);
+                    }
             __syncthreads();
         }
     }

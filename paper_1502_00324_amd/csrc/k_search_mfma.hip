@@ -68,6 +68,13 @@ static Shape mfma_shape(int B) {
 // its XCD with one running best over them (about a quarter of the XCD's
 // chunks, and enough to keep the partial results, one per range and slot,
 // under 256 MB).  tile_kib is the fragment size of one domain tile in KiB.
+// Partial-result slots per XCD and range group (FIC_SLOTS_PER_XCD overrides).
+static int slots_per_xcd() {
+    const char *e = getenv("FIC_SLOTS_PER_XCD");
+    const int v = e ? atoi(e) : 0;
+    return v >= 1 && v <= 64 ? v : 2;
+}
+
 void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt) {
     g.nrg = (range_cap + g.rpw - 1) / g.rpw;
     g.tpc = max(8 * dt, 1536 / tile_kib);
@@ -85,7 +92,8 @@ void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt) 
         const int per_xcd = g.nchunk / 8;
         const long max_slots = max(8L, (256L << 20) / 16 / max(1, range_cap));
         const int groups_max = (int)max(1L, max_slots / 8);
-        g.G = max((per_xcd + groups_max - 1) / groups_max, (per_xcd + 3) / 4);
+        const int spx = slots_per_xcd();
+        g.G = max((per_xcd + groups_max - 1) / groups_max, (per_xcd + spx - 1) / spx);
         g.nslot = 8 * ((per_xcd + g.G - 1) / g.G);
     } else {
         g.G = 1;
@@ -199,6 +207,9 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
 template <int KA, int PL, int RQ, int DT, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_mfma_search(BatchDev bt, SSet ss) {
     constexpr int KB = KA * PL;                  // K-steps of a domain tile
+    // share range bests across workgroups only when a stage is long enough
+    // (>= 4 tiles) to hide the coherent load of the shared values
+    constexpr bool SHARE = DT >= 4;
     constexpr int STAGE = DT * KB * 64;          // uint4 per stage
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
@@ -218,7 +229,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const v4i *__restrict__ afrag = (const v4i *)dsc.afrag;
     const uint4 *__restrict__ bfrag = dsc.bfrag;
     const float2 *__restrict__ dinfo = dsc.dinfo;
-    const RInfo *__restrict__ ri = dsc.ri;
+    RInfo *__restrict__ ri = dsc.ri;
     const int64_t *__restrict__ pa = dsc.pa;
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
@@ -235,7 +246,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 
     v4i A[RQ][2][KA];
     float tn[RQ], bn[RQ], an[RQ];
-    int64_t best[RQ], cr[RQ];
+    int64_t best[RQ], cr[RQ], tb[RQ];  // tb: the best value tn reflects
     int bp[RQ], bk[RQ], rr[RQ], sr[RQ];
 #pragma unroll
     for (int qi = 0; qi < RQ; ++qi) {
@@ -251,6 +262,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         sr[qi] = (int)x.sr;
         cr[qi] = x.cr;
         tn[qi] = r < R ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
+        tb[qi] = INT64_MAX;
         best[qi] = INT64_MAX;
         bp[qi] = INT32_MAX;
         bk[qi] = 0;
@@ -327,6 +339,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     for (int stg = 0; stg < nstage; ++stg) {
         const int buf = stg & 1;
         if (stg + 1 < nstage) gload(stg + 1);
+        // the range bests of other workgroups: issued after the stage prefetch
+        // (so its wait does not include them) and applied at the stage end
+        int64_t gl[RQ];
+#pragma unroll
+        for (int qi = 0; qi < RQ; ++qi) gl[qi] = SHARE && rr[qi] >= 0 ? gbest_load(&ri[rr[qi]].gbest) : INT64_MAX;
         if (wave_on) {
             const int tbase = t0 + stg * DT;
             // software pipeline: the MFMAs of tile dt+1 are issued before the
@@ -364,13 +381,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                             // threshold may use it because a pair is only rejected
                             // when it cannot even tie it
                             const int64_t gb = group_min_val<16>(best[qi]);
-                            if (rr[qi] >= 0) tn[qi] = tn_from(gb, cr[qi], sc, tfac);
+                            if (rr[qi] >= 0 && gb <= tb[qi]) {
+                                tb[qi] = gb;
+                                tn[qi] = tn_from(gb, cr[qi], sc, tfac);
+                                if (SHARE && (lane & 15) == 0) gbest_push(&ri[rr[qi]].gbest, gb);
+                            }
                         }
                     }
                 }
             }
         }
         if (stg + 1 < nstage) swrite(buf ^ 1);
+#pragma unroll
+        for (int qi = 0; qi < RQ; ++qi)
+            if (gl[qi] < tb[qi]) {
+                tb[qi] = gl[qi];
+                tn[qi] = tn_shared(gl[qi], cr[qi], sc, tfac);
+            }
         __syncthreads();
     }
   }

@@ -115,17 +115,32 @@ __device__ inline float tn_factor(int n) { return (1.0f - 1.0f / 1048576.0f) / (
 // Prune threshold tn = sqrt(Cr - best/(16 den^2)) / n, rounded down: the int
 // to float conversion, the two products, the square root and the factor each
 // round by at most 2^-24 relative, and the 1 - 2^-20 in the factor covers
-// them all.  No improvement yet (or c < 0): every pair passes.  A best of 0
-// cannot be beaten (val >= 0) and later domains lose ties, so the range is
-// done: NaN makes every later comparison false.  This matters for flat
-// ranges, where every pair ties at 0 and would pass a non-strict test.
-__device__ __forceinline__ float tn_from(int64_t best, int64_t cr, const SConst &sc, float factor) {
-    if (best == 0) return __builtin_nanf("");
+// them all.  No best yet (or c < 0): every pair passes.  A pair is rejected
+// only when it cannot even tie best, so best may come from any pair of the
+// range, found by this workgroup or another.
+__device__ __forceinline__ float tn_shared(int64_t best, int64_t cr, const SConst &sc, float factor) {
     if (best == INT64_MAX) return -1e30f;
     const int64_t num = sc.scale * cr - best;
     if (num < 0) return -1e30f;
     const float c = (float)num * sc.inv_scale;
     return sqrtf(c) * factor;
+}
+
+// Threshold from the best of this workgroup's own walk.  A best of 0 cannot
+// be beaten (val >= 0) and the walk's later domains have larger indices, so
+// they lose ties: NaN makes every later comparison false.  This matters for
+// flat ranges, where every pair ties at 0 and would pass a non-strict test.
+__device__ __forceinline__ float tn_from(int64_t best, int64_t cr, const SConst &sc, float factor) {
+    if (best == 0) return __builtin_nanf("");
+    return tn_shared(best, cr, sc, factor);
+}
+
+// The best of every workgroup searching a range, kept as an atomic minimum.
+__device__ __forceinline__ int64_t gbest_load(const int64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gbest_push(int64_t *p, int64_t v) {
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int WIDTH>
