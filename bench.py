@@ -20,11 +20,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-INT8_PEAK_TOPS = 5000.0          # MI355X dense int8 MFMA, published
+# MI355X published dense peaks per engine dtype (TFLOP/s, int8 in TOPS)
+PEAK = {"mfma_f16": 2500.0, "mfma_i8": 5000.0, "fp32": 157.3}
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_search_mfma.json")
-KERNEL_SOURCES = ["paper_1502_00324_amd/csrc/k_search_mfma.hip", "paper_1502_00324_amd/csrc/search_common.h",
-                  "paper_1502_00324_amd/csrc/fic_internal.h"]
+KERNEL_SOURCES = ["paper_1502_00324_amd/csrc/k_search_mfma.hip", "paper_1502_00324_amd/csrc/k_search_f16.hip",
+                  "paper_1502_00324_amd/csrc/search_common.h", "paper_1502_00324_amd/csrc/fic_internal.h"]
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", "traffic_search_%s.json" % workload)
+
+
+def issued_ops(engine_name, B):
+    """MFMA ops the engine issues per comparison (the algorithmic count is 2 B^2)."""
+    if engine_name == "mfma_f16":
+        return 2 * B * B                       # K = B^2 decimated positions
+    if engine_name == "mfma_i8":
+        return 8 * B * B if B == 4 else 4 * B * B   # raw pixels at B=4, hi/lo planes above
+    return 2 * B * B
 
 
 def kernel_source_hash():
@@ -121,6 +134,7 @@ def main():
     mk = lambda engine: fic.make_params(wl.levels, pct=wl.pct, pool_max=wl.pool_max, s_num=wl.s_num,
                                         s_den=wl.s_den, split_rms=wl.split_rms, engine=engine)
     engine = {"mfma": fic.ENGINE_MFMA, "mfma_i8": fic.ENGINE_MFMA_I8, "mfma_f16": fic.ENGINE_MFMA_F16}[args.engine]
+    ENGINE_NAME = {fic.ENGINE_MFMA_F16: "mfma_f16", fic.ENGINE_MFMA_I8: "mfma_i8", fic.ENGINE_FP32: "fp32"}
     p = mk(engine)
     bufs = ctx.alloc_encode([(im.shape[1], im.shape[0]) for im in images], p, dev)
     for _ in range(args.warmup):
@@ -145,20 +159,27 @@ def main():
     ms_tot, launches = search[dom_B]
     avg_ms = ms_tot / launches
     launches_per_step = launches / max(args.steps, 1)
+    dom_engine = ENGINE_NAME[fic.level_engine(engine, dom_B)]
     alg_ops = triples_by_B[dom_B] * 2 * dom_B * dom_B / launches_per_step   # decimated MACs x 2 per launch
     achieved = alg_ops / (avg_ms * 1e-3) / 1e12
+    peak = PEAK[dom_engine]
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
+    tf = traffic_file(wl.name)
+    if os.path.exists(tf):
+        with open(tf) as f:
             tr = json.load(f)
-        if tr.get("source_hash") == kernel_source_hash() and tr.get("workload") == wl.name:
+        if tr.get("source_hash") == kernel_source_hash():
             traffic = tr.get("per_launch_bytes", {}).get(str(dom_B))
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": traffic,
-                "kernel": "k_mfma_search (B=%d)" % dom_B, "avg_launch_ms": round(avg_ms, 4),
+    issued = issued_ops(dom_engine, dom_B) / (2 * dom_B * dom_B)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel": "search B=%d (%s engine)" % (dom_B, dom_engine), "avg_launch_ms": round(avg_ms, 4),
                 "ops_per_launch": alg_ops,
-                "ops_note": "algorithmic int8 ops = 2 B^2 per comparison (decimated inner product); the MFMA form "
-                            "issues 8 B^2 (4B^2 int8 MACs), i.e. %.2f TOPS issued" % (4 * achieved)}
+                "ops_note": "algorithmic ops = 2 B^2 per comparison (the decimated inner product); this engine "
+                            "issues %gx that on the matrix cores (%.1f TFLOP/s issued), peak is the %s dense peak"
+                            % (issued, issued * achieved, dom_engine.replace("mfma_", ""))}
+    if traffic:
+        roofline["hbm_frac"] = round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     fp32 = None
     if args.fp32_steps > 0:
@@ -195,13 +216,17 @@ def main():
         "metric": "range x domain x isometry comparisons/s (whole encode, all quadtree levels)",
         "value": value, "unit": "comparisons/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(sec * 1e3, 3), "encode_ms_per_image": round(sec * 1e3 / len(images), 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "+".join(sorted({ENGINE_NAME[fic.level_engine(engine, B)].replace("mfma_", "")
+                                  for (B, L) in wl.levels})),
         "data": "synthetic (seeded 1/f^2 noise + rectangles)",
         "config": {"workload": wl.name + ": " + wl.notes, "images": len(images),
                    "levels": [{"B": B, "L": L} for (B, L) in wl.levels],
                    "pool": "drop ceil(%d/%d * Nd) lowest-entropy candidates" % wl.pct,
                    "s_set": "k/16, k=0..16" if wl.s_den == 16 else str(wl.s_num), "split_rms": wl.split_rms[0],
-                   "engine": "int8 MFMA", "parallelism": "single GPU"},
+                   "engine": args.engine + ": " + ", ".join("B=%d %s" % (B, ENGINE_NAME[fic.level_engine(engine, B)])
+                                                            for (B, L) in wl.levels),
+                   "parallelism": "single GPU"},
         "comparisons_per_step": triples,
         "levels": [{"B": B, "ranges": R, "pool": P, "comparisons": R * P * 8} for (B, R, P) in counts[0]]
         if len(counts) == 1 else None,

@@ -154,6 +154,12 @@ int fic_validate_params(const fic_params *p, int32_t width, int32_t height);
 int fic_query_capacity(const fic_params *p, int32_t width, int32_t height,
                        int64_t *pool_cap, int64_t *range_cap);
 
+/* The engine that runs the search of a level with block size B when engine
+ * is requested: FIC_ENGINE_MFMA resolves to MFMA_F16, MFMA_I8 or FP32 per B,
+ * and the matrix engines fall back to FP32 where they have no form.
+ * Returns FIC_E_INVALID for an unknown engine or B outside 2..32. */
+int fic_level_engine(int32_t engine, int32_t B);
+
 /* Copies the first n (<= 4097) entries of the entropy key table
  * T[q] = q * sum over prime powers p^e || q of e * round(ln p * 2^32), so the
  * key of a block is G = sum over gray levels of T[count]. */

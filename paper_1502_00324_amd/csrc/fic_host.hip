@@ -123,6 +123,17 @@ bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 bool engine_ok(int e) { return e >= FIC_ENGINE_MFMA && e <= FIC_ENGINE_MFMA_F16; }
 
+// The engine that searches a level of block size B: the matrix engine
+// measured fastest per block size for MFMA (f16 at B = 4, where it needs no
+// replicated operands; int8 hi/lo planes at B = 8 and 16), FP32 where the
+// requested matrix engine has no form.
+int engine_for(int engine, int B) {
+    if (engine == FIC_ENGINE_MFMA) return B == 4 ? E_F16 : mfma_supported(B) ? E_I8 : E_FP32;
+    if (engine == FIC_ENGINE_MFMA_I8) return mfma_supported(B) ? E_I8 : E_FP32;
+    if (engine == FIC_ENGINE_MFMA_F16) return f16_supported(B) ? E_F16 : E_FP32;
+    return E_FP32;
+}
+
 int check_sset(const int32_t *num, int count, int den) {
     if (!num || count < 1 || count > kMaxS || den < 1 || den > 1024) return FIC_E_INVALID;
     for (int k = 0; k < count; ++k) {
@@ -198,14 +209,7 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
     memset(&pl.bh, 0, sizeof(pl.bh));
     const int B = in[0].B;
     const int KS = B * B / 16;
-    // the matrix engine measured fastest per block size: f16 at B = 4 (no
-    // replicated operands), int8 hi/lo planes at B = 8 and 16
-    const int eng = !do_search                                             ? E_FP32
-                    : engine == FIC_ENGINE_MFMA && B == 4                  ? E_F16
-                    : engine == FIC_ENGINE_MFMA && mfma_supported(B)       ? E_I8
-                    : engine == FIC_ENGINE_MFMA_I8 && mfma_supported(B)    ? E_I8
-                    : engine == FIC_ENGINE_MFMA_F16 && f16_supported(B)    ? E_F16
-                                                                           : E_FP32;
+    const int eng = do_search ? engine_for(engine, B) : E_FP32;
     pl.bh.B = B;
     pl.bh.eng = eng;
     pl.bh.L = in[0].L;
@@ -550,6 +554,12 @@ int fic_validate_params(const fic_params *p, int32_t width, int32_t height) {
         if (check_rms(p->split_rms[l]) != FIC_OK) return FIC_E_INVALID;
     }
     return FIC_OK;
+}
+
+int fic_level_engine(int32_t engine, int32_t B) {
+    if (!engine_ok(engine) || B < 2 || B > 32 || !pow2(B)) return FIC_E_INVALID;
+    const int e = engine_for(engine, B);
+    return e == E_F16 ? FIC_ENGINE_MFMA_F16 : e == E_I8 ? FIC_ENGINE_MFMA_I8 : FIC_ENGINE_FP32;
 }
 
 int fic_query_capacity(const fic_params *p, int32_t width, int32_t height, int64_t *pool_cap, int64_t *range_cap) {

@@ -75,9 +75,16 @@ static int slots_per_xcd() {
     return v >= 1 && v <= 64 ? v : 2;
 }
 
+// Target chunk size in KiB of fragments (FIC_CHUNK_KIB overrides).
+static int chunk_kib() {
+    const char *e = getenv("FIC_CHUNK_KIB");
+    const int v = e ? atoi(e) : 0;
+    return v >= 64 && v <= 16384 ? v : 1536;
+}
+
 void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt) {
     g.nrg = (range_cap + g.rpw - 1) / g.rpw;
-    g.tpc = max(8 * dt, 1536 / tile_kib);
+    g.tpc = max(8 * dt, chunk_kib() / tile_kib);
     g.nchunk = (ntiles + g.tpc - 1) / g.tpc;
     if (g.nchunk < 8) {
         // small pool: split finer only to give the GPU enough workgroups

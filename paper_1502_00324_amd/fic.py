@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
         L.fic_validate_params.argtypes = [ctypes.POINTER(Params), i32, i32]
         L.fic_query_capacity.argtypes = [ctypes.POINTER(Params), i32, i32, vp, vp]
         L.fic_entropy_table.argtypes = [vp, i32]
+        L.fic_level_engine.argtypes = [i32, i32]
         L.fic_build_domain_pool.argtypes = [vp, ctypes.POINTER(Image), i32, i32, Ratio, i32, ctypes.POINTER(PoolC),
                                             vp]
         L.fic_encode_level.argtypes = [vp, ctypes.POINTER(Image), ctypes.POINTER(PoolC), vp, vp, i32, i32, vp, i32,
@@ -96,7 +97,8 @@ def lib() -> ctypes.CDLL:
 
 EXPORTED = ("fic_ctx_create", "fic_ctx_destroy", "fic_ctx_set_scratch_limit", "fic_ctx_set_timing",
             "fic_ctx_read_timing", "fic_strerror",
-            "fic_validate_params", "fic_query_capacity", "fic_entropy_table", "fic_build_domain_pool",
+            "fic_validate_params", "fic_query_capacity", "fic_level_engine", "fic_entropy_table",
+            "fic_build_domain_pool",
             "fic_encode_level", "fic_encode", "fic_decode")
 
 
@@ -135,6 +137,13 @@ def make_params(levels, block0=None, pct=(3, 10), pool_max=0, s_num=tuple(range(
     p.pool_max = pool_max
     p.engine = engine
     return p
+
+
+def level_engine(engine: int, B: int) -> int:
+    """The engine that runs a level of block size B when `engine` is asked for."""
+    e = lib().fic_level_engine(engine, B)
+    _check(min(e, 0), "fic_level_engine")
+    return e
 
 
 def validate_params(p: Params, width: int, height: int) -> int:
