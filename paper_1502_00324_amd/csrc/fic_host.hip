@@ -201,7 +201,10 @@ struct LevelPlan {
 
 // Fills geometry, block counts and scratch offsets (as byte offsets cast to
 // pointers; bind() rebases them once the slots are allocated).
-void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int engine, int level0) {
+// build_integ: this plan computes the images' summed-area tables (every plan
+// of one encode lays them out identically, so later levels reuse them).
+void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int engine, int level0,
+                bool build_integ) {
     const int n = (int)in.size();
     pl.h.assign(n, ImgLvl());
     pl.pre.assign((size_t)K_NUM * (n + 1), 0);
@@ -259,20 +262,27 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
         blk[K_KEYS] = cdiv(d.nx, 64) * cdiv(d.ny, 16);
         blk[K_HIST] = max(1, min(256, cdiv(d.nd, 256)));
         blk[K_PCMP] = cdiv(d.nd, kScanBlock);
-        blk[K_MOM] = cdiv(d.pool_cap, 4);
+        blk[K_MOM] = cdiv(d.pool_cap, 256);
+        if (build_integ) {
+            blk[K_IROW] = cdiv(d.H + 1, 4);
+            blk[K_ICOL] = cdiv(integ_col_items(d.W, d.H), 256);
+            blk[K_ICSCAN] = cdiv(integ_scan_items(d.W, d.H), 256);
+        }
         // pool scratch
         auto take = [&](Slot s, size_t bytes) {
             const size_t o = off[s];
             off[s] += al(bytes);
             return o;
         };
+        d.integ = (uint32_t *)take(S_INTEG, sizeof(uint32_t) * integ_words(d.W, d.H));
+        d.itmp = (uint32_t *)take(S_ITMP, sizeof(uint32_t) * (size_t)integ_col_items(d.W, d.H));
         d.keys = (int64_t *)take(S_KEYS, sizeof(int64_t) * (size_t)d.nd);
         d.sel = (PoolSel *)take(S_SEL, sizeof(PoolSel));
         d.pblocksum = (int *)take(S_PBLOCK, sizeof(int) * (size_t)(blk[K_PCMP] + 1));
         d.pblockoff = (int *)take(S_PBLOCK, sizeof(int) * (size_t)(blk[K_PCMP] + 1));
         if (do_search) {
             const int n2 = d.B * d.B;
-            blk[K_RANGE] = cdiv(d.range_cap, 4);
+            blk[K_RANGE] = cdiv(d.range_cap, 256);
             blk[K_FINAL] = cdiv(d.range_cap, 4);
             blk[K_CCMP] = cdiv(d.range_cap, kScanBlock);
             d.ri = (RInfo *)take(S_RINFO, sizeof(RInfo) * (size_t)(d.range_cap + 1));
@@ -328,6 +338,8 @@ void rebase(fic_ctx *ctx, T *&p, Slot s) {
 void bind(fic_ctx *ctx, LevelPlan &pl) {
     auto rb = [&](auto &p, Slot s) { rebase(ctx, p, s); };
     for (auto &d : pl.h) {
+        rb(d.integ, S_INTEG);
+        rb(d.itmp, S_ITMP);
         rb(d.keys, S_KEYS);
         rb(d.sel, S_SEL);
         rb(d.pblocksum, S_PBLOCK);
@@ -395,6 +407,13 @@ int reserve_plans(fic_ctx *ctx, std::vector<LevelPlan> &plans, size_t extra_dec0
     need[S_TABLES] = tables;
     need[S_DEC0] = max(need[S_DEC0], extra_dec0);
     return reserve(ctx, need);
+}
+
+int run_integ(fic_ctx *ctx, LevelPlan &pl, hipStream_t st) {
+    mark(ctx, FIC_T_POOL, pl.bh.B, st);
+    FIC_TRY(launch_integ_b(pl.bh, st));
+    mark(ctx, -1, 0, st);
+    return FIC_OK;
 }
 
 int run_pool(fic_ctx *ctx, LevelPlan &pl, hipStream_t st) {
@@ -669,12 +688,14 @@ int fic_build_domain_pool(fic_ctx *ctx, const fic_image *img, int32_t B, int32_t
     std::vector<ImgIn> in(1);
     in[0] = ImgIn{img, B, L, pct.num, pct.den, pool_max, out, nullptr, nullptr, 0, nullptr, nullptr, nullptr};
     std::vector<LevelPlan> plans(1);
-    plan_level(plans[0], in, false, FIC_ENGINE_MFMA, 0);
+    plan_level(plans[0], in, false, FIC_ENGINE_MFMA, 0, true);
     st = reserve_plans(ctx, plans, 0);
     if (st != FIC_OK) return st;
     bind(ctx, plans[0]);
     hipStream_t s = (hipStream_t)stream;
     st = upload(ctx, plans, s);
+    if (st != FIC_OK) return st;
+    st = run_integ(ctx, plans[0], s);
     if (st != FIC_OK) return st;
     return run_pool(ctx, plans[0], s);
 }
@@ -696,7 +717,7 @@ int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, c
     in[0] = ImgIn{img, B, B, 0, 1, 0, const_cast<fic_pool *>(pool), ranges_xy, n_ranges, range_capacity, out,
                   children_xy, n_children};
     std::vector<LevelPlan> plans(1);
-    plan_level(plans[0], in, true, engine, 0);
+    plan_level(plans[0], in, true, engine, 0, true);
     plans[0].bh.ss = make_sset(s_num, s_count, s_den);
     plans[0].bh.rms = split_rms;
     plans[0].bh.is_last = is_last ? 1 : 0;
@@ -705,6 +726,8 @@ int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, c
     bind(ctx, plans[0]);
     hipStream_t s = (hipStream_t)stream;
     st = upload(ctx, plans, s);
+    if (st != FIC_OK) return st;
+    st = run_integ(ctx, plans[0], s);
     if (st != FIC_OK) return st;
     return run_search(ctx, plans[0], s);
 }
@@ -743,7 +766,7 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
                           cl->xy, cl->count, (img->width / B) * (img->height / B), cl,
                           last ? nullptr : codes[i * NL + l + 1].xy, last ? nullptr : codes[i * NL + l + 1].count};
         }
-        plan_level(plans[l], in, true, p->engine, l == 0);
+        plan_level(plans[l], in, true, p->engine, l == 0, l == 0);
         plans[l].bh.ss = make_sset(p->s_num[l], p->s_count[l], p->s_den[l]);
         plans[l].bh.rms = p->split_rms[l];
         plans[l].bh.is_last = last ? 1 : 0;
@@ -755,6 +778,8 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
     st = upload(ctx, plans, s);
     if (st != FIC_OK) return st;
     FIC_TRY(launch_level0_b(plans[0].bh, s));
+    st = run_integ(ctx, plans[0], s);
+    if (st != FIC_OK) return st;
     for (int l = 0; l < NL; ++l) {
         st = run_pool(ctx, plans[l], s);
         if (st != FIC_OK) return st;

@@ -84,7 +84,7 @@ __host__ __device__ inline int iso_inv(int t) { return t == 1 ? 3 : (t == 3 ? 1 
 // Scratch slots owned by a context; each grows on demand.
 enum Slot {
     S_KEYS, S_SEL, S_PBLOCK, S_CBLOCK, S_RINFO, S_AFRAG, S_BFRAG, S_DINFO, S_PARTIAL,
-    S_VF32, S_DF32, S_DEC0, S_TABLES, S_NUM_SLOTS
+    S_VF32, S_DF32, S_DEC0, S_TABLES, S_INTEG, S_ITMP, S_NUM_SLOTS
 };
 
 struct Buf { void *ptr; size_t bytes; };
@@ -161,7 +161,7 @@ enum Engine { E_FP32 = 0, E_I8 = 1, E_F16 = 2 };
 
 enum Kind {
     K_LEVEL0, K_KEYS, K_HIST, K_PCMP, K_MOM, K_RANGE, K_AFRAG, K_BFRAG, K_VIEWS, K_DOMS, K_SEARCH, K_FINAL,
-    K_CCMP, K_NUM
+    K_CCMP, K_IROW, K_ICOL, K_ICSCAN, K_NUM
 };
 
 struct ImgLvl {
@@ -188,6 +188,9 @@ struct ImgLvl {
     int64_t *cerr;
     uint32_t *children;
     int32_t *nchildren;
+    // integral images of this image (shared by every level) and the
+    // column-pass chunk sums
+    uint32_t *integ, *itmp;
     // scratch slices of this image
     int64_t *keys;
     PoolSel *sel;
@@ -204,11 +207,51 @@ struct ImgLvl {
     int nslot;           // partial results per range
 };
 
+// Summed-area tables of one image (built by k_integ.hip): SI and SII over
+// I and I^2, (H+1) x (W+1); then four parity classes q = 2 py + px of Q^2,
+// Q the 2x2 sum at (2i + px, 2j + py), (H/2+1) x (W/2+1) each; uint32 mod 2^32.
+struct IntegGeom {
+    int W, H, ws, hs, wq, hq;   // ws = W+1, hs = H+1, wq = W/2+1, hq = H/2+1
+    __device__ uint32_t *si(uint32_t *base) const { return base; }
+    __device__ uint32_t *sii(uint32_t *base) const { return base + (size_t)hs * ws; }
+    __device__ uint32_t *sq(uint32_t *base, int q) const { return base + 2 * (size_t)hs * ws + (size_t)q * hq * wq; }
+    // table a = 0 (SI), 1 (SII), 2..5 (SQ_{a-2}): pointer, rows, columns
+    __device__ void table(uint32_t *base, int a, uint32_t *&p, int &rows, int &cols) const {
+        if (a < 2) {
+            p = a == 0 ? si(base) : sii(base);
+            rows = hs;
+            cols = ws;
+        } else {
+            p = sq(base, a - 2);
+            rows = hq;
+            cols = wq;
+        }
+    }
+};
+
+// Sum over the w x h box at (x, y) of a summed-area table with row stride s;
+// exact whenever the true sum is below 2^32.
+__device__ inline uint32_t box_sum(const uint32_t *t, int s, int x, int y, int w, int h) {
+    return t[(size_t)(y + h) * s + x + w] - t[(size_t)y * s + x + w] - t[(size_t)(y + h) * s + x] + t[(size_t)y * s + x];
+}
+
 struct BatchDev {
     const ImgLvl *d;     // device table, n entries
     const int *pre;      // device prefixes, K_NUM x (n + 1)
     int n;
 };
+
+struct ImgLvl;
+__device__ inline IntegGeom integ_geom(int W, int H) {
+    IntegGeom g;
+    g.W = W;
+    g.H = H;
+    g.ws = W + 1;
+    g.hs = H + 1;
+    g.wq = W / 2 + 1;
+    g.hq = H / 2 + 1;
+    return g;
+}
 
 __device__ inline int find_img(const int *pre, int n, int b) {
     int lo = 0, hi = n - 1;
@@ -238,6 +281,10 @@ hipError_t launch_range_info_b(const BatchHost &b, hipStream_t st);
 hipError_t launch_finalize_b(const BatchHost &b, hipStream_t st);
 hipError_t launch_children_b(const BatchHost &b, hipStream_t st);
 // MFMA engine
+hipError_t launch_integ_b(const BatchHost &b, hipStream_t st);
+size_t integ_words(int W, int H);
+int integ_col_items(int W, int H);
+int integ_scan_items(int W, int H);
 bool mfma_supported(int B);   // int8 engine
 bool f16_supported(int B);    // f16 engine
 hipError_t launch_f16_prep_b(const BatchHost &b, hipStream_t st);

@@ -28,35 +28,27 @@ hipError_t launch_level0_b(const BatchHost &b, hipStream_t st) {
 // ---------------------------------------------------------------- range moments
 // One wave per range.  The prune margin is n/4 + 4 in units of C'; the float
 // rounding of the prune test is below n/16 in the same units.
+// One thread per range: Sr and sum r^2 from the summed-area tables.
 __global__ __launch_bounds__(256) void k_range_info(BatchDev b) {
     const int *pre = b.pre + K_RANGE * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = (blockIdx.x - pre[im]) * 4 + w;
+    const int r = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
     if (r >= min(*d.nr, d.range_cap)) return;
     const int B = d.B, n = B * B;
     const uint32_t v = d.rxy[r];
     const int x0 = v & 0xffff, y0 = v >> 16;
-    int s = 0, ss = 0;
-    for (int i = lane; i < n; i += 64) {
-        const int y = i / B, x = i - y * B;
-        const int p = d.pix[(size_t)(y0 + y) * d.pitch + x0 + x];
-        s += p;
-        ss += p * p;
-    }
-    s = wave_sum_i32(s);
-    ss = wave_sum_i32(ss);
-    if (lane == 0) {
-        RInfo o;
-        o.cr = (int64_t)n * ss - (int64_t)s * s;
-        o.sr = s;
-        o.bn = (float)(128.0 - (double)s / n);
-        o.an = (float)(512.0 * s - 65536.0 * n + (n / 4 + 4));
-        o.pad = 0.f;
-        o.gbest = INT64_MAX;
-        d.ri[r] = o;
-    }
+    const IntegGeom g = integ_geom(d.W, d.H);
+    const int64_t s = box_sum(g.si(d.integ), g.ws, x0, y0, B, B);
+    const int64_t ss = box_sum(g.sii(d.integ), g.ws, x0, y0, B, B);
+    RInfo o;
+    o.cr = (int64_t)n * ss - s * s;
+    o.sr = (int32_t)s;
+    o.bn = (float)(128.0 - (double)s / n);
+    o.an = (float)(512.0 * s - 65536.0 * n + (n / 4 + 4));
+    o.pad = 0.f;
+    o.gbest = INT64_MAX;
+    d.ri[r] = o;
 }
 
 hipError_t launch_range_info_b(const BatchHost &b, hipStream_t st) {
@@ -105,12 +97,8 @@ __global__ __launch_bounds__(256) void k_finalize(BatchDev b, SSet ss, fic_ratio
     const uint8_t *img = d.pix;
     const uint32_t v = d.rxy[r];
     const int x0 = v & 0xffff, y0 = v >> 16;
-    int64_t sr = 0;
-    for (int i = lane; i < n; i += 64) {
-        const int y = i / B, x = i - y * B;
-        sr += img[(size_t)(y0 + y) * pitch + x0 + x];
-    }
-    sr = wave_sum_i64(sr);
+    const IntegGeom g = integ_geom(d.W, d.H);
+    const int64_t sr = box_sum(g.si(d.integ), g.ws, x0, y0, B, B);
     // every lane's first domain always passes the prune test, so bp is a
     // valid pool index whenever the pool is non-empty; stay in bounds anyway
     const int P = min(*d.pcount, d.pool_cap);

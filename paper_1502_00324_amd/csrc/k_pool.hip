@@ -204,31 +204,22 @@ struct PoolOp {
     __device__ int32_t *total(const ImgLvl &d) const { return d.pcount; }
 };
 
-// Per pool entry: sum of the raw pixels and A = n*sum(D4^2) - (sum D4)^2.
+// Per pool entry: Sd4 = sum of the raw pixels and A = n*sum(D4^2) - (sum D4)^2,
+// each a box of the image's summed-area tables (one thread per entry).
 __global__ __launch_bounds__(256) void k_pool_moments(BatchDev b) {
     const int *pre = b.pre + K_MOM * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int p = (blockIdx.x - pre[im]) * 4 + w;
+    const int p = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
     if (p >= min(*d.pcount, d.pool_cap)) return;
-    const int B = d.B, pitch = d.pitch;
+    const int B = d.B;
     const uint32_t v = d.pxy[p];
     const int x0 = v & 0xffff, y0 = v >> 16;
-    int64_t s = 0, ss = 0;
-    for (int c = lane; c < B * B; c += 64) {
-        const int cy = c / B, cx = c - cy * B;
-        const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
-        const int d4 = q[0] + q[1] + q[pitch] + q[pitch + 1];
-        s += d4;
-        ss += (int64_t)d4 * d4;
-    }
-    s = wave_sum_i64(s);
-    ss = wave_sum_i64(ss);
-    if (lane == 0) {
-        d.psum4[p] = (uint32_t)s;
-        d.pa[p] = (int64_t)B * B * ss - s * s;
-    }
+    const IntegGeom g = integ_geom(d.W, d.H);
+    const int64_t s = box_sum(g.si(d.integ), g.ws, x0, y0, 2 * B, 2 * B);
+    const int64_t ss = box_sum(g.sq(d.integ, 2 * (y0 & 1) + (x0 & 1)), g.wq, x0 >> 1, y0 >> 1, B, B);
+    d.psum4[p] = (uint32_t)s;
+    d.pa[p] = (int64_t)B * B * ss - s * s;
 }
 
 // ---------------------------------------------------------------- launcher

@@ -42,8 +42,8 @@ bool f16_supported(int B) { return B == 4 || B == 8 || B == 16; }
 // compiled one.
 struct F16Shape { int B, rq, dt, wpe; };
 static const F16Shape kF16Shapes[] = {
-    {4, 1, 8, 4}, {4, 2, 8, 2}, {4, 1, 16, 4}, {4, 2, 4, 3},
-    {8, 2, 4, 2}, {8, 1, 4, 3}, {8, 1, 8, 3}, {8, 2, 2, 2},
+    {4, 1, 8, 4}, {4, 2, 8, 2}, {4, 1, 16, 3}, {4, 2, 4, 3},
+    {8, 2, 4, 2}, {8, 1, 4, 3}, {8, 1, 8, 2}, {8, 2, 2, 2},
     {16, 1, 1, 3}, {16, 1, 2, 2},
 };
 static F16Shape f16_shape(int B) {
@@ -384,12 +384,12 @@ hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st) {
     if (B == 4) {
         FIC_F16(1, 1, 8, 4);
         FIC_F16(1, 2, 8, 2);
-        FIC_F16(1, 1, 16, 4);
+        FIC_F16(1, 1, 16, 3);
         FIC_F16(1, 2, 4, 3);
     } else if (B == 8) {
         FIC_F16(4, 2, 4, 2);
         FIC_F16(4, 1, 4, 3);
-        FIC_F16(4, 1, 8, 3);
+        FIC_F16(4, 1, 8, 2);
         FIC_F16(4, 2, 2, 2);
     } else if (B == 16) {
         FIC_F16(16, 1, 1, 3);

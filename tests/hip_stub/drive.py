@@ -20,16 +20,18 @@ sys.path.insert(0, ROOT)
 from paper_1502_00324_amd import fic  # noqa: E402
 from paper_1502_00324_amd.synth import make_image  # noqa: E402
 
-K_LEVEL0, K_KEYS, K_HIST, K_PCMP, K_MOM, K_RANGE, K_AFRAG, K_BFRAG, K_VIEWS, K_DOMS, K_SEARCH, K_FINAL, K_CCMP = \
-    range(13)
+(K_LEVEL0, K_KEYS, K_HIST, K_PCMP, K_MOM, K_RANGE, K_AFRAG, K_BFRAG, K_VIEWS, K_DOMS, K_SEARCH, K_FINAL, K_CCMP,
+ K_IROW, K_ICOL, K_ICSCAN) = range(16)
 KIND_OF = [("k_level0", K_LEVEL0), ("k_pool_keys", K_KEYS), ("k_sel_hist", K_HIST), ("k_pool_moments", K_MOM),
            ("k_range_info", K_RANGE), ("k_mfma_afrag", K_AFRAG), ("k_mfma_bfrag", K_BFRAG),
            ("k_f16_afrag", K_AFRAG), ("k_f16_bfrag", K_BFRAG),
            ("k_fp32_views", K_VIEWS), ("k_fp32_doms", K_DOMS), ("k_mfma_search", K_SEARCH),
-           ("k_f16_search", K_SEARCH), ("k_fp32_search", K_SEARCH), ("k_finalize", K_FINAL)]
+           ("k_f16_search", K_SEARCH), ("k_fp32_search", K_SEARCH), ("k_finalize", K_FINAL),
+           ("k_integ_rows", K_IROW), ("k_integ_colsum", K_ICOL), ("k_integ_coladd", K_ICOL),
+           ("k_integ_colscan", K_ICSCAN)]
 PER_IMAGE = ("k_sel_init", "k_sel_pick", "k_bscan")
 KIND_ARG = ("k_bcount", "k_bscatter")
-NUM_KINDS = 13
+NUM_KINDS = 16
 
 
 class BatchDev(ctypes.Structure):

@@ -63,6 +63,14 @@ def test_one_launch_set_per_level(runs):
     assert per_rep8 < 120
 
 
+def test_integral_images_once_per_encode(runs):
+    # built by the level-0 plan only, reused by the later levels
+    for name, reps in (("mixed_mfma_3lv", 2), ("single_fp32", 2), ("paper_b2_cap", 2)):
+        k = kinds(runs[name])
+        assert k.count("k_integ_rows") == reps and k.count("k_integ_colscan") == reps
+        assert k.count("k_integ_colsum") == reps and k.count("k_integ_coladd") == reps
+
+
 def test_engine_choice(runs):
     m, f = kinds(runs["mixed_mfma_3lv"]), kinds(runs["mixed_fp32_3lv"])
     i8, h = kinds(runs["mixed_i8_3lv"]), kinds(runs["mixed_f16_3lv"])
