@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--workload", default="c3_1024")
     ap.add_argument("--engine", default="mfma", choices=["mfma", "mfma_i8", "mfma_f16"],
                     help="matrix engine of the timed steps (mfma = the faster form per block size)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay each encode as a captured HIP graph (stage times then come from extra eager steps)")
     ap.add_argument("--fp32-steps", type=int, default=2, help="timed steps of the plain FP32 engine (0 skips)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample budget (0 skips)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -137,14 +139,24 @@ def main():
     ENGINE_NAME = {fic.ENGINE_MFMA_F16: "mfma_f16", fic.ENGINE_MFMA_I8: "mfma_i8", fic.ENGINE_FP32: "fp32"}
     p = mk(engine)
     bufs = ctx.alloc_encode([(im.shape[1], im.shape[0]) for im in images], p, dev)
+    if args.graphs:
+        ctx.set_graphs(4)
     for _ in range(args.warmup):
         ctx.encode(imgs, p, bufs)
     torch.cuda.synchronize()
 
-    ctx.set_timing(True)
-    sec = run_steps(ctx, imgs, p, bufs, args.steps, torch)
-    stages = ctx.read_timing()
-    ctx.set_timing(False)
+    if args.graphs:
+        # graph replays are timed as a whole; stage times need eager encodes
+        sec = run_steps(ctx, imgs, p, bufs, args.steps, torch)
+        ctx.set_timing(True)
+        run_steps(ctx, imgs, p, bufs, args.steps, torch)
+        stages = ctx.read_timing()
+        ctx.set_timing(False)
+    else:
+        ctx.set_timing(True)
+        sec = run_steps(ctx, imgs, p, bufs, args.steps, torch)
+        stages = ctx.read_timing()
+        ctx.set_timing(False)
     counts = level_counts(bufs, p)
     triples_by_B = {}
     for per_img in counts:
@@ -226,7 +238,7 @@ def main():
                    "s_set": "k/16, k=0..16" if wl.s_den == 16 else str(wl.s_num), "split_rms": wl.split_rms[0],
                    "engine": args.engine + ": " + ", ".join("B=%d %s" % (B, ENGINE_NAME[fic.level_engine(engine, B)])
                                                             for (B, L) in wl.levels),
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "graph_replay": bool(args.graphs)},
         "comparisons_per_step": triples,
         "levels": [{"B": B, "ranges": R, "pool": P, "comparisons": R * P * 8} for (B, R, P) in counts[0]]
         if len(counts) == 1 else None,

@@ -124,6 +124,21 @@ void fic_ctx_destroy(fic_ctx *ctx);
 int fic_ctx_set_scratch_limit(fic_ctx *ctx, int64_t bytes);
 const char *fic_strerror(int status);
 
+/* Graph replay of fic_encode (launch-bound small images, repeated batches).
+ * With max_graphs > 0, an encode is captured into a HIP graph the first time
+ * its exact arguments (image pointers and sizes, params, every pool and code
+ * buffer) are seen and replayed on later calls with the same arguments: no
+ * host planning, no table upload, one graph launch on the caller's stream.
+ * Image contents may change between replays.  At most max_graphs graphs are
+ * kept (least recently used first out); each holds its own device copy of
+ * the level tables.  All graphs are dropped when the context reallocates
+ * its scratch, and encodes run eagerly while stage timing is on.  0 turns
+ * replay off and frees the graphs.  Graphs contain kernel nodes only. */
+int fic_ctx_set_graphs(fic_ctx *ctx, int32_t max_graphs);
+
+/* Number of graphs currently cached by the context. */
+int fic_ctx_graph_count(fic_ctx *ctx);
+
 /* Stage timing with HIP events recorded on the caller's stream around each
  * stage a call enqueues (measurement aid; off by default).  Stages: pool build,
  * search operand preparation (range moments and operand layouts), the search

@@ -20,6 +20,36 @@ struct Timer {
     int open = -1;
 };
 
+// Captured encodes.  A graph bakes in every pointer of its encode (caller
+// buffers, scratch slots, its own copy of the level tables), so it is keyed by
+// the exact arguments and dropped whenever a scratch slot is reallocated.
+struct GraphEntry {
+    std::vector<uint8_t> key;
+    hipGraphExec_t exec = nullptr;
+    void *tables = nullptr;   // device copy of the level tables the graph reads
+    uint64_t last_use = 0;
+};
+
+struct GraphCache {
+    int max = 0;
+    uint64_t tick = 0;
+    hipStream_t cap = nullptr;   // capture stream (the legacy stream cannot be captured)
+    std::vector<GraphEntry> e;
+};
+
+static void free_graph(GraphEntry &g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.tables) (void)hipFree(g.tables);
+    g.exec = nullptr;
+    g.tables = nullptr;
+}
+
+void drop_graphs(GraphCache *gc) {
+    if (!gc) return;
+    for (auto &g : gc->e) free_graph(g);
+    gc->e.clear();
+}
+
 }  // namespace fic
 
 using namespace fic;
@@ -335,7 +365,7 @@ void rebase(fic_ctx *ctx, T *&p, Slot s) {
     p = (T *)((char *)ctx->slot[s].ptr + (size_t)p);
 }
 
-void bind(fic_ctx *ctx, LevelPlan &pl) {
+void bind(fic_ctx *ctx, LevelPlan &pl, void *tables = nullptr) {
     auto rb = [&](auto &p, Slot s) { rebase(ctx, p, s); };
     for (auto &d : pl.h) {
         rb(d.integ, S_INTEG);
@@ -361,14 +391,14 @@ void bind(fic_ctx *ctx, LevelPlan &pl) {
             d.ri = nullptr;
         }
     }
-    char *base = (char *)ctx->slot[S_TABLES].ptr + pl.table_off;
+    char *base = (char *)(tables ? tables : ctx->slot[S_TABLES].ptr) + pl.table_off;
     pl.bh.dev.d = (const ImgLvl *)base;
     pl.bh.dev.pre = (const int *)(base + al(sizeof(ImgLvl) * pl.h.size()));
 }
 
 // Copies every plan's tables to S_TABLES with one async copy from pinned
 // memory; the staging buffer is reused once the previous copy has finished.
-int upload(fic_ctx *ctx, std::vector<LevelPlan> &plans, hipStream_t st) {
+int upload(fic_ctx *ctx, std::vector<LevelPlan> &plans, hipStream_t st, void *tables = nullptr) {
     size_t total = 0;
     for (auto &pl : plans) total += table_bytes(pl);
     if (ctx->staging_event) {
@@ -388,7 +418,8 @@ int upload(fic_ctx *ctx, std::vector<LevelPlan> &plans, hipStream_t st) {
         memcpy(dst, pl.h.data(), sizeof(ImgLvl) * pl.h.size());
         memcpy(dst + al(sizeof(ImgLvl) * pl.h.size()), pl.pre.data(), sizeof(int) * pl.pre.size());
     }
-    if (hipMemcpyAsync(ctx->slot[S_TABLES].ptr, ctx->staging, total, hipMemcpyHostToDevice, st) != hipSuccess)
+    if (hipMemcpyAsync(tables ? tables : ctx->slot[S_TABLES].ptr, ctx->staging, total, hipMemcpyHostToDevice, st) !=
+        hipSuccess)
         return FIC_E_HIP;
     if (hipEventRecord(ctx->staging_event, st) != hipSuccess) return FIC_E_HIP;
     return FIC_OK;
@@ -441,6 +472,102 @@ int run_search(fic_ctx *ctx, LevelPlan &pl, hipStream_t st) {
     return FIC_OK;
 }
 
+// Every launch of one encode, in order.
+int run_encode(fic_ctx *ctx, std::vector<LevelPlan> &plans, hipStream_t s) {
+    FIC_TRY(launch_level0_b(plans[0].bh, s));
+    int st = run_integ(ctx, plans[0], s);
+    if (st != FIC_OK) return st;
+    for (auto &pl : plans) {
+        st = run_pool(ctx, pl, s);
+        if (st != FIC_OK) return st;
+        st = run_search(ctx, pl, s);
+        if (st != FIC_OK) return st;
+    }
+    return FIC_OK;
+}
+
+template <class T>
+void put(std::vector<uint8_t> &k, const T &v) {
+    const uint8_t *b = (const uint8_t *)&v;
+    k.insert(k.end(), b, b + sizeof(T));
+}
+
+// Every argument of an encode, field by field (no struct padding).
+std::vector<uint8_t> encode_key(const fic_image *imgs, int n, const fic_params *p, const fic_pool *pools,
+                                const fic_level_codes *codes) {
+    std::vector<uint8_t> k;
+    put(k, n);
+    put(k, *p);   // int32 fields only
+    for (int i = 0; i < n; ++i) {
+        put(k, imgs[i].pix);
+        put(k, imgs[i].width);
+        put(k, imgs[i].height);
+        put(k, imgs[i].pitch);
+    }
+    for (int i = 0; i < n * p->levels; ++i) {
+        const fic_pool &q = pools[i];
+        put(k, q.capacity);
+        put(k, q.count);
+        put(k, q.xy);
+        put(k, q.key);
+        put(k, q.sum4);
+        put(k, q.a);
+        const fic_level_codes &c = codes[i];
+        put(k, c.capacity);
+        put(k, c.count);
+        put(k, c.xy);
+        put(k, c.split);
+        put(k, c.domain);
+        put(k, c.iso);
+        put(k, c.s_idx);
+        put(k, c.offset);
+        put(k, c.err);
+    }
+    return k;
+}
+
+// Records the encode's launches into a graph (on the capture stream), keeps
+// it with its own copy of the level tables, and launches it on s.
+int capture_encode(fic_ctx *ctx, std::vector<LevelPlan> &plans, std::vector<uint8_t> key, hipStream_t s) {
+    GraphCache *gc = ctx->graphs;
+    size_t total = 0;
+    for (auto &pl : plans) total += table_bytes(pl);
+    GraphEntry g;
+    g.key = std::move(key);
+    if (hipMalloc(&g.tables, total) != hipSuccess) return FIC_E_NOMEM;
+    for (auto &pl : plans) bind(ctx, pl, g.tables);
+    int st = upload(ctx, plans, s, g.tables);
+    if (st != FIC_OK) {
+        free_graph(g);
+        return st;
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(gc->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        free_graph(g);
+        return FIC_E_HIP;
+    }
+    st = run_encode(ctx, plans, gc->cap);
+    const hipError_t ec = hipStreamEndCapture(gc->cap, &graph);
+    if (st == FIC_OK && ec != hipSuccess) st = FIC_E_HIP;
+    if (st == FIC_OK && hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) st = FIC_E_HIP;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != FIC_OK) {
+        free_graph(g);
+        return st;
+    }
+    if ((int)gc->e.size() >= gc->max) {  // evict the least recently used
+        size_t lru = 0;
+        for (size_t i = 1; i < gc->e.size(); ++i)
+            if (gc->e[i].last_use < gc->e[lru].last_use) lru = i;
+        free_graph(gc->e[lru]);
+        gc->e.erase(gc->e.begin() + lru);
+    }
+    g.last_use = ++gc->tick;
+    gc->e.push_back(g);
+    FIC_TRY(hipGraphLaunch(gc->e.back().exec, s));
+    return FIC_OK;
+}
+
 bool pool_ok(const fic_pool *p) { return p && p->count && p->xy && p->key && p->sum4 && p->a && p->capacity >= 1; }
 
 bool codes_ok(const fic_level_codes *c) {
@@ -468,6 +595,7 @@ int reserve(fic_ctx *ctx, const size_t *bytes) {
             if (!synced) {
                 if (hipDeviceSynchronize() != hipSuccess) return FIC_E_HIP;
                 synced = true;
+                drop_graphs(ctx->graphs);  // they point into the slot being freed
             }
             (void)hipFree(ctx->slot[i].ptr);
             ctx->slot[i].ptr = nullptr;
@@ -628,6 +756,11 @@ void fic_ctx_destroy(fic_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     destroy_timer(ctx->timer);
+    if (ctx->graphs) {
+        drop_graphs(ctx->graphs);
+        if (ctx->graphs->cap) (void)hipStreamDestroy(ctx->graphs->cap);
+        delete ctx->graphs;
+    }
     if (ctx->staging_event) (void)hipEventDestroy(ctx->staging_event);
     if (ctx->staging) (void)hipHostFree(ctx->staging);
     for (int i = 0; i < S_NUM_SLOTS; ++i)
@@ -641,6 +774,27 @@ int fic_ctx_set_scratch_limit(fic_ctx *ctx, int64_t bytes) {
     ctx->limit = bytes;
     return FIC_OK;
 }
+
+int fic_ctx_set_graphs(fic_ctx *ctx, int32_t max_graphs) {
+    if (!ctx || max_graphs < 0 || max_graphs > 1024) return FIC_E_INVALID;
+    int st = enter(ctx);
+    if (st != FIC_OK) return st;
+    if (!ctx->graphs) {
+        if (max_graphs == 0) return FIC_OK;
+        ctx->graphs = new GraphCache;
+        if (hipStreamCreateWithFlags(&ctx->graphs->cap, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx->graphs;
+            ctx->graphs = nullptr;
+            return FIC_E_HIP;
+        }
+    }
+    if (hipDeviceSynchronize() != hipSuccess) return FIC_E_HIP;
+    if (max_graphs < (int)ctx->graphs->e.size()) drop_graphs(ctx->graphs);
+    ctx->graphs->max = max_graphs;
+    return FIC_OK;
+}
+
+int fic_ctx_graph_count(fic_ctx *ctx) { return ctx && ctx->graphs ? (int)ctx->graphs->e.size() : 0; }
 
 int fic_ctx_set_timing(fic_ctx *ctx, int enable) {
     if (!ctx) return FIC_E_INVALID;
@@ -754,6 +908,19 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
     if (n_images == 0) return FIC_OK;
     int st = enter(ctx);
     if (st != FIC_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    GraphCache *gc = ctx->graphs;
+    const bool use_graph = gc && gc->max > 0 && !ctx->timer;
+    std::vector<uint8_t> key;
+    if (use_graph) {
+        key = encode_key(imgs, n_images, p, pools, codes);
+        for (auto &g : gc->e)
+            if (g.key == key) {
+                g.last_use = ++gc->tick;
+                FIC_TRY(hipGraphLaunch(g.exec, s));
+                return FIC_OK;
+            }
+    }
     std::vector<LevelPlan> plans(NL);
     for (int l = 0; l < NL; ++l) {
         const int B = p->block0 >> l;
@@ -773,20 +940,11 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
     }
     st = reserve_plans(ctx, plans, 0);
     if (st != FIC_OK) return st;
+    if (use_graph) return capture_encode(ctx, plans, std::move(key), s);
     for (auto &pl : plans) bind(ctx, pl);
-    hipStream_t s = (hipStream_t)stream;
     st = upload(ctx, plans, s);
     if (st != FIC_OK) return st;
-    FIC_TRY(launch_level0_b(plans[0].bh, s));
-    st = run_integ(ctx, plans[0], s);
-    if (st != FIC_OK) return st;
-    for (int l = 0; l < NL; ++l) {
-        st = run_pool(ctx, plans[l], s);
-        if (st != FIC_OK) return st;
-        st = run_search(ctx, plans[l], s);
-        if (st != FIC_OK) return st;
-    }
-    return FIC_OK;
+    return run_encode(ctx, plans, s);
 }
 
 int fic_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes, int32_t width,

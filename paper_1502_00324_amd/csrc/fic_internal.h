@@ -92,7 +92,8 @@ struct Buf { void *ptr; size_t bytes; };
 }  // namespace fic
 
 namespace fic {
-struct Timer;  // event records of the optional stage timing
+struct Timer;       // event records of the optional stage timing
+struct GraphCache;  // captured encodes for replay
 }
 
 struct fic_ctx {
@@ -101,6 +102,7 @@ struct fic_ctx {
     fic::Buf slot[fic::S_NUM_SLOTS];
     int64_t *table;              // device entropy table
     fic::Timer *timer;           // non-null while stage timing is on
+    fic::GraphCache *graphs;     // non-null once graph replay has been enabled
     void *staging;               // pinned host buffer for the level tables
     size_t staging_bytes;
     hipEvent_t staging_event;    // last copy out of the staging buffer

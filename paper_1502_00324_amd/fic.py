@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
         L.fic_ctx_destroy.restype = None
         L.fic_ctx_set_scratch_limit.argtypes = [vp, i64]
         L.fic_ctx_set_timing.argtypes = [vp, i32]
+        L.fic_ctx_set_graphs.argtypes = [vp, i32]
+        L.fic_ctx_graph_count.argtypes = [vp]
         L.fic_ctx_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
         L.fic_validate_params.argtypes = [ctypes.POINTER(Params), i32, i32]
         L.fic_query_capacity.argtypes = [ctypes.POINTER(Params), i32, i32, vp, vp]
@@ -96,6 +98,7 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ("fic_ctx_create", "fic_ctx_destroy", "fic_ctx_set_scratch_limit", "fic_ctx_set_timing",
+            "fic_ctx_set_graphs", "fic_ctx_graph_count",
             "fic_ctx_read_timing", "fic_strerror",
             "fic_validate_params", "fic_query_capacity", "fic_level_engine", "fic_entropy_table",
             "fic_build_domain_pool",
@@ -260,6 +263,13 @@ class Context:
 
     def set_scratch_limit(self, nbytes: int):
         _check(lib().fic_ctx_set_scratch_limit(self.h, nbytes), "fic_ctx_set_scratch_limit")
+
+    def set_graphs(self, max_graphs: int):
+        """Capture encodes into HIP graphs and replay them for repeated arguments."""
+        _check(lib().fic_ctx_set_graphs(self.h, int(max_graphs)), "fic_ctx_set_graphs")
+
+    def graph_count(self) -> int:
+        return lib().fic_ctx_graph_count(self.h)
 
     def set_timing(self, enable: bool):
         _check(lib().fic_ctx_set_timing(self.h, int(enable)), "fic_ctx_set_timing")

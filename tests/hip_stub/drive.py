@@ -146,6 +146,29 @@ def main():
     scenario("timing_toggle", lambda: encode_case(L, h, mixed[:3], [(16, 2), (8, 2)], M, reps=3,
                                                   timing_toggle=True))
     scenario("empty_batch", lambda: encode_case(L, h, [], [(8, 1), (4, 1)], M))
+    # graph replay: the first encode of a given argument set is captured, the
+    # repeats launch nothing but the graph
+    L.mock_captured.restype = L.mock_replays.restype = ctypes.c_long
+
+    def graphs():
+        L.fic_ctx_set_graphs(h, 2)
+        c0, r0 = L.mock_captured(), L.mock_replays()
+        st = encode_case(L, h, mixed[:3], [(16, 2), (8, 2), (4, 2)], M, reps=3)
+        n1 = L.fic_ctx_graph_count(h)
+        c1, r1, k1 = L.mock_captured(), L.mock_replays(), len(log["launches"])
+        # a second argument set, then a third that evicts the least recently used
+        st += encode_case(L, h, [(64, 64)], [(8, 1), (4, 1)], M, reps=1)
+        st += encode_case(L, h, [(128, 64)], [(8, 1), (4, 1)], M, reps=1)
+        n3 = L.fic_ctx_graph_count(h)
+        L.fic_ctx_set_graphs(h, 0)
+        n0 = L.fic_ctx_graph_count(h)
+        log["graph"] = {"first_launches": k1, "first_captured": c1 - c0, "first_replays": r1 - r0,
+                        "captured": L.mock_captured() - c0, "replays": L.mock_replays() - r0,
+                        "counts": [n1, n3, n0]}
+        return st
+
+    scenario("graphs", graphs)
+    out["graphs"]["graph"] = log["graph"]
     L.fic_ctx_set_scratch_limit(h, 1 << 10)
     scenario("over_limit", lambda: encode_case(L, h, [(1024, 1024)], [(8, 1), (4, 1)], M, reps=1))
     L.fic_ctx_set_scratch_limit(h, 0)

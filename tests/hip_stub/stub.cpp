@@ -20,7 +20,8 @@ static size_t g_shm;
 static hipStream_t g_stream;
 static std::map<const void *, std::string> *g_names;
 static mock_hook_t g_hook;
-static long g_launches;
+static long g_launches, g_captured, g_replays;
+static int g_capturing;
 
 void mock_set_hook(mock_hook_t h) { g_hook = h; }
 long mock_launches() { return g_launches; }
@@ -56,6 +57,7 @@ hipError_t hipLaunchKernel(const void *f, dim3 grid, dim3 block, void **args, si
         abort();
     }
     ++g_launches;
+    if (g_capturing) ++g_captured;
     if (g_hook) g_hook(name, grid.x, block.x, args);
     return hipSuccess;
 }
@@ -115,4 +117,44 @@ hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipSt
     return hipSuccess;
 }
 hipError_t hipSetDevice(int) { return hipSuccess; }
+
+// Streams and graphs: launches during a capture are checked like any other
+// and counted as captured; a graph launch only counts a replay.
+long mock_captured() { return g_captured; }
+long mock_replays() { return g_replays; }
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
+    *s = (hipStream_t)malloc(16);
+    return hipSuccess;
+}
+hipError_t hipStreamDestroy(hipStream_t s) {
+    free(s);
+    return hipSuccess;
+}
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) {
+    if (g_capturing) return hipErrorInvalidValue;
+    g_capturing = 1;
+    return hipSuccess;
+}
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) {
+    if (!g_capturing) return hipErrorInvalidValue;
+    g_capturing = 0;
+    *g = (hipGraph_t)malloc(16);
+    return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t, hipGraphNode_t *, char *, size_t) {
+    *e = (hipGraphExec_t)malloc(16);
+    return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) {
+    ++g_replays;
+    return hipSuccess;
+}
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+    free(e);
+    return hipSuccess;
+}
+hipError_t hipGraphDestroy(hipGraph_t g) {
+    free(g);
+    return hipSuccess;
+}
 }

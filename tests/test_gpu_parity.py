@@ -188,6 +188,57 @@ def test_determinism_and_batch_independence(ctx):
                 np.testing.assert_array_equal(a["codes"][f], c["codes"][f])
 
 
+def test_graph_replay_matches_eager_encodes(ctx):
+    """fic_ctx_set_graphs: the first encode of an argument set is captured,
+    repeats are graph replays.  Each replay (with eager work and a
+    synchronisation between replays, and a new image written in place) is
+    compared with an eager encode of the same image in another context."""
+    shapes = [(128, 64), (64, 64), (96, 96)]
+    p = params([(16, 2), (8, 2), (4, 2)], (3, 10), 0, K16, 16, (6, 1), fic.ENGINE_MFMA)
+    eager = fic.Context(0)
+    g = fic.Context(0)
+    g.set_graphs(4)
+    imgs = [torch.from_numpy(make_image(40 + i, w, h, 8)).cuda() for i, (w, h) in enumerate(shapes)]
+    bufs = g.alloc_encode(shapes, p, imgs[0].device)
+    try:
+        for rep in range(4):
+            if rep == 2:   # new contents at the same addresses
+                for i, (w, h) in enumerate(shapes):
+                    imgs[i].copy_(torch.from_numpy(make_image(60 + i, w, h, 12)).cuda())
+            g.encode(imgs, p, bufs)
+            torch.cuda.synchronize()
+            assert g.graph_count() == 1
+            ref = eager.encode(imgs, p)
+            junk = torch.randn(1 << 16, device=imgs[0].device).sum()   # eager work between replays
+            torch.cuda.synchronize()
+            del junk
+            for (pools, codes), (rp, rc) in zip(bufs, ref):
+                got = fic.levels_numpy(pools, codes, p)
+                want = fic.levels_numpy(rp, rc, p)
+                for a, b in zip(got, want):
+                    for f in ("xy", "split", "domain", "iso", "s_idx", "offset", "err"):
+                        np.testing.assert_array_equal(a["codes"][f], b["codes"][f], err_msg="replay %d %s" % (rep, f))
+                    for f in ("xy", "key", "sum4", "a"):
+                        np.testing.assert_array_equal(a["pool"][f], b["pool"][f], err_msg="replay %d pool %s" % (rep, f))
+        # a second argument set gets its own graph; the first still replays
+        p2 = params([(8, 2), (4, 2)], (3, 10), 0, K16, 16, (8, 1), fic.ENGINE_MFMA)
+        one = [imgs[1]]
+        b2 = g.alloc_encode([shapes[1]], p2, imgs[0].device)
+        g.encode(one, p2, b2)
+        g.encode(imgs, p, bufs)
+        torch.cuda.synchronize()
+        assert g.graph_count() == 2
+        ref2 = eager.encode(one, p2)
+        torch.cuda.synchronize()
+        for a, b in zip(fic.levels_numpy(*b2[0], p2), fic.levels_numpy(*ref2[0], p2)):
+            np.testing.assert_array_equal(a["codes"]["domain"], b["codes"]["domain"])
+            np.testing.assert_array_equal(a["codes"]["err"], b["codes"]["err"])
+    finally:
+        g.set_graphs(0)
+        g.close()
+        eager.close()
+
+
 def test_failure_paths_return_status_without_launch(ctx):
     img = torch.from_numpy(make_image(30, 64, 64, 3)).cuda()
     p = params([(8, 4), (4, 4)], (3, 10), 0, K16, 16, (8, 1), fic.ENGINE_MFMA)

@@ -94,3 +94,16 @@ def test_pool_size_select_runs_only_with_a_cap(runs):
 def test_empty_batch_and_scratch_limit(runs):
     assert runs["empty_batch"]["status"] == [0, 0] and runs["empty_batch"]["launches"] == []
     assert runs["over_limit"]["status"] == [-2] and runs["over_limit"]["launches"] == []
+
+
+def test_graph_capture_and_replay(runs):
+    s = runs["graphs"]
+    assert all(v == 0 for v in s["status"]) and s["errors"] == []
+    g = s["graph"]
+    # three encodes of one argument set: one capture, then graph launches only
+    assert g["first_launches"] == g["first_captured"] > 20 and g["first_replays"] == 3
+    # every kernel launch of the scenario happened inside a capture; two more
+    # argument sets give two more captures and graph launches
+    assert len(s["launches"]) == g["captured"] and g["replays"] == 5
+    # at most two graphs kept; 0 frees them
+    assert g["counts"] == [1, 2, 0]
