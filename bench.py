@@ -193,6 +193,17 @@ def main():
     if traffic:
         roofline["hbm_frac"] = round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
+    # the codec's output size (Sec. 3.3, Fig 7): pack every image once, untimed
+    bits = {"header_bits": 0, "pool_bits": 0, "record_bits": 0, "total_bits": 0}
+    for (pools, codes), im in zip(bufs, images):
+        _, sz = ctx.pack(p, im.shape[1], im.shape[0], pools, codes)
+        for k in bits:
+            bits[k] += sz[k]
+    px = sum(im.size for im in images)
+    bitstream = {"bpp": round(bits["total_bits"] / px, 4), "cr": round(8.0 * px / bits["total_bits"], 3),
+                 "bpp_codes_only": round(bits["record_bits"] / px, 4),
+                 "cr_codes_only": round(8.0 * px / max(1, bits["record_bits"]), 3), **bits}
+
     fp32 = None
     if args.fp32_steps > 0:
         pf = mk(fic.ENGINE_FP32)
@@ -243,7 +254,7 @@ def main():
         "levels": [{"B": B, "ranges": R, "pool": P, "comparisons": R * P * 8} for (B, R, P) in counts[0]]
         if len(counts) == 1 else None,
         "stage_ms_per_step": per_stage,
-        "roofline": roofline, "fp32_baseline": fp32, "cpu_baseline": cpu,
+        "roofline": roofline, "fp32_baseline": fp32, "cpu_baseline": cpu, "bitstream": bitstream,
         "kernel_source_hash": kernel_source_hash(),
     }
     ctx.close()

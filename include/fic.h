@@ -219,6 +219,50 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
 int fic_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes,
                int32_t width, int32_t height, int32_t iterations, uint8_t *out, fic_stream stream);
 
+/* ---- bitstream (Sec. 3.3, Fig 7, Eq 8) -------------------------------- */
+
+/* Stream layout, all fields most significant bit first, zero-padded to a
+ * whole byte:
+ *   header   W (16), H (16), levels-1 (2), log2 block0 (3); per level:
+ *            L-1 (8), |S|-1 (5), den-1 (10), each num (11)
+ *   pools    per level: DN (32), mode (1); mode 0: bitmap over the Nd
+ *            candidates in raster order; mode 1: the DN candidate indices in
+ *            ascending order, ceil(log2 Nd) bits each (used only when
+ *            strictly shorter than the bitmap).  The pool list is the
+ *            decoder's address table (the domain field indexes it).
+ *   records  per accepted range (Fig 7): step (2) = its level, O (8),
+ *            isometry (3), domain (ceil(log2 DN), Eq 8), s index
+ *            (ceil(log2 |S|): none for one value, 1 bit for two).  Order:
+ *            level-0 blocks in raster order, each split block's quarters
+ *            top-left, top-right, bottom-left, bottom-right, depth first;
+ *            range positions are implied and not stored.
+ * Requires every step L <= 256. */
+
+/* Upper bound of the packed size in bytes (a multiple of 4). */
+int fic_pack_capacity(const fic_params *p, int32_t width, int32_t height, int64_t *bytes);
+
+/* Packs one encoded image (its per-level pools and codes, device buffers as
+ * written by fic_encode) into out (device, 4-byte aligned, capacity bytes
+ * from fic_pack_capacity).  sizes (device, 4 x int64) receives the bits of
+ * the header, the pool side information, the records and the total; the
+ * stream is ceil(total / 8) bytes.  Everything runs on the stream. */
+int fic_pack(fic_ctx *ctx, const fic_params *p, int32_t width, int32_t height, const fic_pool *pools,
+             const fic_level_codes *codes, uint8_t *out, int64_t capacity, int64_t *sizes, fic_stream stream);
+
+/* Host-only.  Reads the header of a packed stream (host memory): params
+ * (levels, block0, steps, contrast sets; pool_pct 0, pool_max 0, split_rms
+ * 0/1, engine MFMA) and the image size.  FIC_E_INVALID on a malformed
+ * header. */
+int fic_unpack_header(const uint8_t *data, int64_t nbytes, fic_params *p, int32_t *width, int32_t *height);
+
+/* Host-only.  Unpacks a stream into host buffers (capacities as
+ * fic_query_capacity for the header's params): per level the pool list
+ * (xy; key, sum4 and a are zeroed) and the codes in the encoder's
+ * breadth-first order with split flags (err is 0: the stream does not
+ * carry it).  The result decodes with fic_decode once copied to the device.
+ * FIC_E_INVALID on a malformed or truncated stream. */
+int fic_unpack(const uint8_t *data, int64_t nbytes, fic_pool *pools, fic_level_codes *codes);
+
 #ifdef __cplusplus
 }
 #endif

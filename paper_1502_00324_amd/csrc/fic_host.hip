@@ -195,7 +195,6 @@ SSet make_sset(const int32_t *num, int count, int den) {
     return s;
 }
 
-int hip_status(hipError_t e) { return e == hipSuccess ? FIC_OK : (e == hipErrorOutOfMemory ? FIC_E_NOMEM : FIC_E_HIP); }
 
 #define FIC_TRY(expr)                              \
     do {                                           \
@@ -574,14 +573,17 @@ bool codes_ok(const fic_level_codes *c) {
     return c && c->count && c->xy && c->split && c->domain && c->iso && c->s_idx && c->offset && c->err;
 }
 
-int enter(fic_ctx *ctx) {
-    if (!ctx) return FIC_E_INVALID;
-    return hip_status(hipSetDevice(ctx->device));
-}
 
 }  // namespace
 
 namespace fic {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? FIC_OK : (e == hipErrorOutOfMemory ? FIC_E_NOMEM : FIC_E_HIP); }
+
+int enter(fic_ctx *ctx) {
+    if (!ctx) return FIC_E_INVALID;
+    return hip_status(hipSetDevice(ctx->device));
+}
 
 int reserve(fic_ctx *ctx, const size_t *bytes) {
     int64_t total = 0;

@@ -84,7 +84,7 @@ __host__ __device__ inline int iso_inv(int t) { return t == 1 ? 3 : (t == 3 ? 1 
 // Scratch slots owned by a context; each grows on demand.
 enum Slot {
     S_KEYS, S_SEL, S_PBLOCK, S_CBLOCK, S_RINFO, S_AFRAG, S_BFRAG, S_DINFO, S_PARTIAL,
-    S_VF32, S_DF32, S_DEC0, S_TABLES, S_INTEG, S_ITMP, S_NUM_SLOTS
+    S_VF32, S_DF32, S_DEC0, S_TABLES, S_INTEG, S_ITMP, S_PACK, S_NUM_SLOTS
 };
 
 struct Buf { void *ptr; size_t bytes; };
@@ -111,6 +111,8 @@ struct fic_ctx {
 namespace fic {
 
 int reserve(fic_ctx *ctx, const size_t *bytes);   // bytes[S_NUM_SLOTS], 0 = untouched
+int hip_status(hipError_t e);                      // FIC_OK, FIC_E_NOMEM or FIC_E_HIP
+int enter(fic_ctx *ctx);                           // makes the ctx's device current
 
 // Stage timing: mark(ctx, kind, B, st) opens a stage (closing the previous
 // open one); mark(ctx, -1, 0, st) closes it.  No-ops unless timing is on.

@@ -85,6 +85,11 @@ def lib() -> ctypes.CDLL:
         L.fic_query_capacity.argtypes = [ctypes.POINTER(Params), i32, i32, vp, vp]
         L.fic_entropy_table.argtypes = [vp, i32]
         L.fic_level_engine.argtypes = [i32, i32]
+        L.fic_pack_capacity.argtypes = [ctypes.POINTER(Params), i32, i32, vp]
+        L.fic_pack.argtypes = [vp, ctypes.POINTER(Params), i32, i32, ctypes.POINTER(PoolC), ctypes.POINTER(CodesC),
+                               vp, i64, vp, vp]
+        L.fic_unpack_header.argtypes = [vp, i64, ctypes.POINTER(Params), vp, vp]
+        L.fic_unpack.argtypes = [vp, i64, ctypes.POINTER(PoolC), ctypes.POINTER(CodesC)]
         L.fic_build_domain_pool.argtypes = [vp, ctypes.POINTER(Image), i32, i32, Ratio, i32, ctypes.POINTER(PoolC),
                                             vp]
         L.fic_encode_level.argtypes = [vp, ctypes.POINTER(Image), ctypes.POINTER(PoolC), vp, vp, i32, i32, vp, i32,
@@ -102,7 +107,8 @@ EXPORTED = ("fic_ctx_create", "fic_ctx_destroy", "fic_ctx_set_scratch_limit", "f
             "fic_ctx_read_timing", "fic_strerror",
             "fic_validate_params", "fic_query_capacity", "fic_level_engine", "fic_entropy_table",
             "fic_build_domain_pool",
-            "fic_encode_level", "fic_encode", "fic_decode")
+            "fic_encode_level", "fic_encode", "fic_decode", "fic_pack_capacity", "fic_pack", "fic_unpack_header",
+            "fic_unpack")
 
 
 def strerror(status: int) -> str:
@@ -159,6 +165,66 @@ def query_capacity(p: Params, width: int, height: int):
     _check(lib().fic_query_capacity(ctypes.byref(p), width, height, pc.ctypes.data, rc.ctypes.data),
            "fic_query_capacity")
     return pc[:p.levels].tolist(), rc[:p.levels].tolist()
+
+
+def pack_capacity(p: Params, width: int, height: int) -> int:
+    out = np.zeros(1, np.int64)
+    _check(lib().fic_pack_capacity(ctypes.byref(p), width, height, out.ctypes.data), "fic_pack_capacity")
+    return int(out[0])
+
+
+def unpack(data) -> tuple:
+    """Host-side unpacking of a stream (bytes or uint8 array): (params, W, H,
+    levels) with per level the pool xy and the codes as numpy arrays."""
+    buf = np.frombuffer(bytes(data), np.uint8) if not isinstance(data, np.ndarray) else np.ascontiguousarray(data)
+    p = Params()
+    W, H = np.zeros(1, np.int32), np.zeros(1, np.int32)
+    _check(lib().fic_unpack_header(buf.ctypes.data, buf.size, ctypes.byref(p), W.ctypes.data, H.ctypes.data),
+           "fic_unpack_header")
+    W, H = int(W[0]), int(H[0])
+    pcap, rcap = query_capacity(p, W, H)
+    keep, pools, codes = [], (PoolC * p.levels)(), (CodesC * p.levels)()
+    for l in range(p.levels):
+        arr = lambda n, dt: keep.append(np.zeros(max(n, 1), dt)) or keep[-1]
+        pc, px, pk, ps, pa = arr(1, np.int32), arr(pcap[l], np.uint32), arr(pcap[l], np.int64), \
+            arr(pcap[l], np.uint32), arr(pcap[l], np.int64)
+        pools[l] = PoolC(pcap[l], pc.ctypes.data, px.ctypes.data, pk.ctypes.data, ps.ctypes.data, pa.ctypes.data)
+        cols = [arr(1, np.int32), arr(rcap[l], np.uint32), arr(rcap[l], np.uint8), arr(rcap[l], np.uint32),
+                arr(rcap[l], np.uint8), arr(rcap[l], np.uint8), arr(rcap[l], np.uint8), arr(rcap[l], np.int64)]
+        codes[l] = CodesC(rcap[l], *[c.ctypes.data for c in cols])
+    _check(lib().fic_unpack(buf.ctypes.data, buf.size, pools, codes), "fic_unpack")
+    levels = []
+    for l in range(p.levels):
+        pk = keep[l * 13:(l + 1) * 13]
+        dn, n = int(pk[0][0]), int(pk[5][0])
+        levels.append({"pool_xy": pk[1][:dn].copy(),
+                       "codes": {k: pk[6 + i][:n].copy() for i, k in
+                                 enumerate(("xy", "split", "domain", "iso", "s_idx", "offset", "err"))}})
+    return p, W, H, levels
+
+
+def to_device(p: Params, W: int, H: int, levels: list, device):
+    """Unpacked host levels -> device Pool / Codes lists for Context.decode."""
+    t = _torch()
+    pcap, rcap = query_capacity(p, W, H)
+    pools, codes = [], []
+    for l, lv in enumerate(levels):
+        pl = Pool.alloc(pcap[l], device)
+        n = len(lv["pool_xy"])
+        pl.count.fill_(n)
+        pl.xy[:n] = t.from_numpy(lv["pool_xy"].view(np.int32)).to(device)
+        cd = Codes.alloc(rcap[l], device)
+        c = lv["codes"]
+        m = len(c["xy"])
+        cd.count.fill_(m)
+        for k in ("xy", "domain"):
+            getattr(cd, k)[:m] = t.from_numpy(c[k].view(np.int32)).to(device)
+        for k in ("split", "iso", "s_idx", "offset"):
+            getattr(cd, k)[:m] = t.from_numpy(c[k]).to(device)
+        cd.err[:m] = 0
+        pools.append(pl)
+        codes.append(cd)
+    return pools, codes
 
 
 def entropy_table() -> np.ndarray:
@@ -263,6 +329,22 @@ class Context:
 
     def set_scratch_limit(self, nbytes: int):
         _check(lib().fic_ctx_set_scratch_limit(self.h, nbytes), "fic_ctx_set_scratch_limit")
+
+    def pack(self, p: Params, width: int, height: int, pools, codes):
+        """Packs one encoded image on the device; returns (stream bytes as a
+        numpy uint8 array, {header, pool, records, total} bits)."""
+        t = _torch()
+        dev = codes[0].xy.device
+        cap = pack_capacity(p, width, height)
+        out = t.empty(cap, dtype=t.uint8, device=dev)
+        sizes = t.zeros(4, dtype=t.int64, device=dev)
+        pc = (PoolC * p.levels)(*[pl.c() for pl in pools])
+        cc = (CodesC * p.levels)(*[cd.c() for cd in codes])
+        _check(lib().fic_pack(self.h, ctypes.byref(p), width, height, pc, cc, out.data_ptr(), cap,
+                              sizes.data_ptr(), _stream()), "fic_pack")
+        sz = sizes.cpu().tolist()
+        nbytes = (sz[3] + 7) // 8
+        return out[:nbytes].cpu().numpy(), dict(zip(("header_bits", "pool_bits", "record_bits", "total_bits"), sz))
 
     def set_graphs(self, max_graphs: int):
         """Capture encodes into HIP graphs and replay them for repeated arguments."""
