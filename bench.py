@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--workload", default="c3_1024")
     ap.add_argument("--engine", default="mfma", choices=["mfma", "mfma_i8", "mfma_f16"],
                     help="matrix engine of the timed steps (mfma = the faster form per block size)")
+    ap.add_argument("--decode-iters", type=int, default=None,
+                    help="decode each image after the timed encodes and report PSNR (default: the workload's)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay each encode as a captured HIP graph (stage times then come from extra eager steps)")
     ap.add_argument("--fp32-steps", type=int, default=2, help="timed steps of the plain FP32 engine (0 skips)")
@@ -204,6 +206,21 @@ def main():
                  "bpp_codes_only": round(bits["record_bits"] / px, 4),
                  "cr_codes_only": round(8.0 * px / max(1, bits["record_bits"]), 3), **bits}
 
+    # decode (Sec. 1-2) and PSNR (Eq 4), untimed by the step clock
+    decode = None
+    iters = wl.decode_iters if args.decode_iters is None else args.decode_iters
+    if iters > 0:
+        import numpy as np
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = [ctx.decode(p, pools, codes, im.shape[1], im.shape[0], iters) for (pools, codes), im in zip(bufs, images)]
+        torch.cuda.synchronize()
+        dec_ms = (time.perf_counter() - t0) * 1e3
+        sse = sum(int(((o.cpu().numpy().astype(np.int64) - im.astype(np.int64)) ** 2).sum())
+                  for o, im in zip(outs, images))
+        decode = {"iterations": iters, "ms": round(dec_ms, 3),
+                  "psnr_db": round(10 * np.log10(65025.0 * px / sse), 3) if sse else float("inf")}
+
     fp32 = None
     if args.fp32_steps > 0:
         pf = mk(fic.ENGINE_FP32)
@@ -246,7 +263,8 @@ def main():
         "config": {"workload": wl.name + ": " + wl.notes, "images": len(images),
                    "levels": [{"B": B, "L": L} for (B, L) in wl.levels],
                    "pool": "drop ceil(%d/%d * Nd) lowest-entropy candidates" % wl.pct,
-                   "s_set": "k/16, k=0..16" if wl.s_den == 16 else str(wl.s_num), "split_rms": wl.split_rms[0],
+                   "s_set": "k/16, k=0..16" if wl.s_den == 16 else "%s / %s" % (wl.s_num, wl.s_den),
+                   "pool_max": wl.pool_max, "split_rms": wl.split_rms[0],
                    "engine": args.engine + ": " + ", ".join("B=%d %s" % (B, ENGINE_NAME[fic.level_engine(engine, B)])
                                                             for (B, L) in wl.levels),
                    "parallelism": "single GPU", "graph_replay": bool(args.graphs)},
@@ -254,7 +272,7 @@ def main():
         "levels": [{"B": B, "ranges": R, "pool": P, "comparisons": R * P * 8} for (B, R, P) in counts[0]]
         if len(counts) == 1 else None,
         "stage_ms_per_step": per_stage,
-        "roofline": roofline, "fp32_baseline": fp32, "cpu_baseline": cpu, "bitstream": bitstream,
+        "roofline": roofline, "fp32_baseline": fp32, "cpu_baseline": cpu, "bitstream": bitstream, "decode": decode,
         "kernel_source_hash": kernel_source_hash(),
     }
     ctx.close()

@@ -56,12 +56,13 @@ enum {
 
 /* Search engines; all give identical codes.
  *   MFMA:     matrix cores, the faster form per block size: MFMA_F16 at
- *             B = 4, MFMA_I8 at B = 8 and 16; FP32 for B = 2 and B = 32.
+ *             B = 2 and 4, MFMA_I8 at B = 8 and 16; FP32 for B = 32.
  *   FP32:     plain vector FP32 with the same exact epilogue (baseline).
  *   MFMA_I8:  int8 matrix cores for B = 4, 8, 16 (raw pixels at B = 4,
  *             decimated hi/lo planes above); FP32 elsewhere.
  *   MFMA_F16: f16 matrix cores with exact f32 accumulation over the B^2
- *             decimated positions for B = 4, 8, 16; FP32 elsewhere. */
+ *             decimated positions for B = 2 (zero-padded to 16), 4, 8, 16;
+ *             FP32 at B = 32. */
 enum { FIC_ENGINE_MFMA = 0, FIC_ENGINE_FP32 = 1, FIC_ENGINE_MFMA_I8 = 2, FIC_ENGINE_MFMA_F16 = 3 };
 enum { FIC_MAX_LEVELS = 4, FIC_MAX_S = 32 };
 

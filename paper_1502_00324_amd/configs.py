@@ -49,6 +49,6 @@ WORKLOADS = {
     # S = {0.1}, {0.2, 0.4}, {0.3, 0.8}, {0.5, 0.9}
     "paper_dn64": Workload("paper_dn64", [(0, 512, 512, 40)], [(16, 4), (8, 4), (4, 4), (2, 4)],
                            pct=(0, 1), pool_max=64,
-                           s_num=((1,), (2, 4), (3, 8), (5, 9)), s_den=10, split_rms=(8, 1),
+                           s_num=((1,), (2, 4), (3, 8), (5, 9)), s_den=10, split_rms=(8, 1), decode_iters=8,
                            notes="paper schedule, DN = 64"),
 }

@@ -154,11 +154,11 @@ bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 bool engine_ok(int e) { return e >= FIC_ENGINE_MFMA && e <= FIC_ENGINE_MFMA_F16; }
 
 // The engine that searches a level of block size B: the matrix engine
-// measured fastest per block size for MFMA (f16 at B = 4, where it needs no
-// replicated operands; int8 hi/lo planes at B = 8 and 16), FP32 where the
-// requested matrix engine has no form.
+// measured fastest per block size for MFMA (f16 at B = 2 and 4, where it
+// needs no replicated operands; int8 hi/lo planes at B = 8 and 16), FP32
+// where the requested matrix engine has no form.
 int engine_for(int engine, int B) {
-    if (engine == FIC_ENGINE_MFMA) return B == 4 ? E_F16 : mfma_supported(B) ? E_I8 : E_FP32;
+    if (engine == FIC_ENGINE_MFMA) return (B == 2 || B == 4) ? E_F16 : mfma_supported(B) ? E_I8 : E_FP32;
     if (engine == FIC_ENGINE_MFMA_I8) return mfma_supported(B) ? E_I8 : E_FP32;
     if (engine == FIC_ENGINE_MFMA_F16) return f16_supported(B) ? E_F16 : E_FP32;
     return E_FP32;

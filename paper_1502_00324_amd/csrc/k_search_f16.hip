@@ -34,7 +34,7 @@ namespace fic {
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f16x __attribute__((ext_vector_type(16)));
 
-bool f16_supported(int B) { return B == 4 || B == 8 || B == 16; }
+bool f16_supported(int B) { return B == 2 || B == 4 || B == 8 || B == 16; }
 
 // Range quads per wave (RQ), domain tiles per LDS stage (DT) and the
 // occupancy the register allocation aims at (waves per SIMD); the first entry
@@ -42,6 +42,7 @@ bool f16_supported(int B) { return B == 4 || B == 8 || B == 16; }
 // compiled one.
 struct F16Shape { int B, rq, dt, wpe; };
 static const F16Shape kF16Shapes[] = {
+    {2, 1, 8, 4},
     {4, 1, 8, 4}, {4, 2, 8, 2}, {4, 1, 16, 3}, {4, 2, 4, 3},
     {8, 2, 4, 2}, {8, 1, 4, 3}, {8, 1, 8, 2}, {8, 2, 2, 2},
     {16, 1, 1, 3}, {16, 1, 2, 2},
@@ -61,7 +62,7 @@ MfmaGeom f16_geometry(int B, int range_cap, int pool_cap) {
     const F16Shape sh = f16_shape(B);
     MfmaGeom g;
     g.pl = 0;
-    g.ka = B * B / 16;
+    g.ka = (B * B + 15) / 16;   // B = 2: the 4 positions zero-padded to one step
     g.kt = g.ka;
     g.rpw = 16 * sh.rq;
     const int ntiles = (pool_cap + kDomTile32 - 1) / kDomTile32;
@@ -93,6 +94,10 @@ __global__ __launch_bounds__(256) void k_f16_afrag(BatchDev b) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = 16 * s + 8 * kb + e;
+            if (k >= B * B) {   // padding of the last step (B = 2)
+                w[e] = (_Float16)0;
+                continue;
+            }
             const int cy = k / B, cx = k - cy * B;
             int sy, sx;
             iso_src(ti, B, cy, cx, sy, sx);
@@ -126,6 +131,10 @@ __global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = 16 * s + 8 * kb + e;
+            if (k >= B * B) {   // padding of the last step (B = 2)
+                w[e] = (_Float16)0;
+                continue;
+            }
             const int cy = k / B, cx = k - cy * B;
             const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
             w[e] = (_Float16)(q[0] + q[1] + q[pitch] + q[pitch + 1] - 512);
@@ -381,7 +390,9 @@ hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st) {
     const F16Shape sh = f16_shape(B);
 #define FIC_F16(KS, RQ, DT, WPE) \
     if (sh.rq == RQ && sh.dt == DT && sh.wpe == WPE) return launch_f16_t<KS, RQ, DT, WPE>(b, st)
-    if (B == 4) {
+    if (B == 2) {
+        FIC_F16(1, 1, 8, 4);
+    } else if (B == 4) {
         FIC_F16(1, 1, 8, 4);
         FIC_F16(1, 2, 8, 2);
         FIC_F16(1, 1, 16, 3);

@@ -127,9 +127,9 @@ def test_ctx_create_reports_missing_device():
 
 def test_level_engine_resolution():
     M, F, I8, H = fic.ENGINE_MFMA, fic.ENGINE_FP32, fic.ENGINE_MFMA_I8, fic.ENGINE_MFMA_F16
-    assert [fic.level_engine(M, B) for B in (2, 4, 8, 16, 32)] == [F, H, I8, I8, F]
+    assert [fic.level_engine(M, B) for B in (2, 4, 8, 16, 32)] == [H, H, I8, I8, F]
     assert [fic.level_engine(I8, B) for B in (2, 4, 8, 16, 32)] == [F, I8, I8, I8, F]
-    assert [fic.level_engine(H, B) for B in (2, 4, 8, 16, 32)] == [F, H, H, H, F]
+    assert [fic.level_engine(H, B) for B in (2, 4, 8, 16, 32)] == [H, H, H, H, F]
     assert all(fic.level_engine(F, B) == F for B in (2, 4, 8, 16, 32))
     assert fic.lib().fic_level_engine(4, 8) == fic.FIC_E_INVALID
     assert fic.lib().fic_level_engine(M, 12) == fic.FIC_E_INVALID

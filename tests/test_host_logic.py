@@ -79,10 +79,10 @@ def test_engine_choice(runs):
     assert "k_mfma_search" not in f and "k_f16_search" not in f
     assert i8.count("k_mfma_search") == 2 * 3 and "k_f16_search" not in i8
     assert h.count("k_f16_search") == 2 * 3 and "k_mfma_search" not in h
-    # B=32 and B=2 levels take the FP32 engine even when MFMA is asked for
+    # B=32 levels take the FP32 engine even when MFMA is asked for
     assert "k_fp32_search" in kinds(runs["mixed_b32_4lv"]) and "k_f16_search" in kinds(runs["mixed_b32_4lv"])
     assert "k_mfma_search" in kinds(runs["mixed_b32_4lv"])
-    assert "k_fp32_search" in kinds(runs["paper_b2_cap"])
+    assert "k_fp32_search" not in kinds(runs["paper_b2_cap"])   # B = 2 runs on the f16 engine
 
 
 def test_pool_size_select_runs_only_with_a_cap(runs):
