@@ -220,6 +220,18 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
 int fic_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes,
                int32_t width, int32_t height, int32_t iterations, uint8_t *out, fic_stream stream);
 
+/* ---- contrast diagnostic (Sec. 3.2, Fig 5; Sec. 3.2.1, Fig 6) ---------- */
+
+/* Histograms over the ranges accepted at each level of one encoded image
+ * (its image, pools and codes, device buffers as written by fic_encode):
+ * the least-squares contrast of the chosen match (Eq 2 with d = D4 / 4),
+ * s* = 4 Bx / A, binned exactly over [0, 1) into nbins (1..4096) bins, and
+ * the chosen contrast index.  out (device, int64) receives per level
+ * nbins + 3 + 32 counts: [s* < 0, nbins bins, s* >= 1, A = 0 (s* undefined),
+ * then one count per contrast index 0..31].  Runs on the stream. */
+int fic_s_histogram(fic_ctx *ctx, const fic_image *img, const fic_params *p, const fic_pool *pools,
+                    const fic_level_codes *codes, int32_t nbins, int64_t *out, fic_stream stream);
+
 /* ---- bitstream (Sec. 3.3, Fig 7, Eq 8) -------------------------------- */
 
 /* Stream layout, all fields most significant bit first, zero-padded to a

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfic.so")
-SOURCES = ["fic_host.hip", "k_pool.hip", "k_level.hip", "k_search_mfma.hip", "k_search_f16.hip", "k_search_fp32.hip", "k_decode.hip", "k_integ.hip", "k_pack.hip"]
+SOURCES = ["fic_host.hip", "k_pool.hip", "k_level.hip", "k_search_mfma.hip", "k_search_f16.hip", "k_search_fp32.hip", "k_decode.hip", "k_integ.hip", "k_pack.hip", "k_shist.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          # packed FP32 instructions are kept out of every kernel

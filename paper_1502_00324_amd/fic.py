@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
                                vp, i64, vp, vp]
         L.fic_unpack_header.argtypes = [vp, i64, ctypes.POINTER(Params), vp, vp]
         L.fic_unpack.argtypes = [vp, i64, ctypes.POINTER(PoolC), ctypes.POINTER(CodesC)]
+        L.fic_s_histogram.argtypes = [vp, ctypes.POINTER(Image), ctypes.POINTER(Params), ctypes.POINTER(PoolC),
+                                      ctypes.POINTER(CodesC), i32, vp, vp]
         L.fic_build_domain_pool.argtypes = [vp, ctypes.POINTER(Image), i32, i32, Ratio, i32, ctypes.POINTER(PoolC),
                                             vp]
         L.fic_encode_level.argtypes = [vp, ctypes.POINTER(Image), ctypes.POINTER(PoolC), vp, vp, i32, i32, vp, i32,
@@ -108,7 +110,7 @@ EXPORTED = ("fic_ctx_create", "fic_ctx_destroy", "fic_ctx_set_scratch_limit", "f
             "fic_validate_params", "fic_query_capacity", "fic_level_engine", "fic_entropy_table",
             "fic_build_domain_pool",
             "fic_encode_level", "fic_encode", "fic_decode", "fic_pack_capacity", "fic_pack", "fic_unpack_header",
-            "fic_unpack")
+            "fic_unpack", "fic_s_histogram")
 
 
 def strerror(status: int) -> str:
@@ -345,6 +347,23 @@ class Context:
         sz = sizes.cpu().tolist()
         nbytes = (sz[3] + 7) // 8
         return out[:nbytes].cpu().numpy(), dict(zip(("header_bits", "pool_bits", "record_bits", "total_bits"), sz))
+
+    def s_histogram(self, image, p: Params, pools, codes, nbins: int = 20) -> list:
+        """Per level: {'s_star': counts of the nbins bins of the chosen match's
+        least-squares contrast over [0, 1), 'under', 'over', 'flat',
+        's_index': counts per contrast index} over the accepted ranges."""
+        t = _torch()
+        per = nbins + 3 + MAX_S
+        out = t.zeros(per * p.levels, dtype=t.int64, device=image.device)
+        pc = (PoolC * p.levels)(*[pl.c() for pl in pools])
+        cc = (CodesC * p.levels)(*[cd.c() for cd in codes])
+        im = _image(image)
+        _check(lib().fic_s_histogram(self.h, ctypes.byref(im), ctypes.byref(p), pc, cc, nbins, out.data_ptr(),
+                                     _stream()), "fic_s_histogram")
+        h = out.cpu().numpy().reshape(p.levels, per)
+        return [{"under": int(r[0]), "s_star": r[1:nbins + 1].copy(), "over": int(r[nbins + 1]),
+                 "flat": int(r[nbins + 2]), "s_index": r[nbins + 3:nbins + 3 + p.s_count[l]].copy()}
+                for l, r in enumerate(h)]
 
     def set_graphs(self, max_graphs: int):
         """Capture encodes into HIP graphs and replay them for repeated arguments."""
