@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--workload", default="c3_1024")
     ap.add_argument("--engine", default="mfma", choices=["mfma", "mfma_i8", "mfma_f16"],
                     help="matrix engine of the timed steps (mfma = the faster form per block size)")
+    ap.add_argument("--pool-key", default="entropy", choices=["entropy", "variance"],
+                    help="domain pool key: entropy (the paper's) or variance (the cited alternative)")
     ap.add_argument("--decode-iters", type=int, default=None,
                     help="decode each image after the timed encodes and report PSNR (default: the workload's)")
     ap.add_argument("--graphs", action="store_true",
@@ -135,8 +137,9 @@ def main():
     dev = torch.device("cuda:0")
     imgs = [torch.from_numpy(im).to(dev) for im in images]
     ctx = fic.Context(0)
+    pool_key = fic.POOL_VARIANCE if args.pool_key == "variance" else fic.POOL_ENTROPY
     mk = lambda engine: fic.make_params(wl.levels, pct=wl.pct, pool_max=wl.pool_max, s_num=wl.s_num,
-                                        s_den=wl.s_den, split_rms=wl.split_rms, engine=engine)
+                                        s_den=wl.s_den, split_rms=wl.split_rms, engine=engine, pool_key=pool_key)
     engine = {"mfma": fic.ENGINE_MFMA, "mfma_i8": fic.ENGINE_MFMA_I8, "mfma_f16": fic.ENGINE_MFMA_F16}[args.engine]
     ENGINE_NAME = {fic.ENGINE_MFMA_F16: "mfma_f16", fic.ENGINE_MFMA_I8: "mfma_i8", fic.ENGINE_FP32: "fp32"}
     p = mk(engine)
@@ -262,7 +265,7 @@ def main():
         "data": "synthetic (seeded 1/f^2 noise + rectangles)",
         "config": {"workload": wl.name + ": " + wl.notes, "images": len(images),
                    "levels": [{"B": B, "L": L} for (B, L) in wl.levels],
-                   "pool": "drop ceil(%d/%d * Nd) lowest-entropy candidates" % wl.pct,
+                   "pool": "drop ceil(%d/%d * Nd) lowest-%s candidates" % (wl.pct + (args.pool_key,)),
                    "s_set": "k/16, k=0..16" if wl.s_den == 16 else "%s / %s" % (wl.s_num, wl.s_den),
                    "pool_max": wl.pool_max, "split_rms": wl.split_rms[0],
                    "engine": args.engine + ": " + ", ".join("B=%d %s" % (B, ENGINE_NAME[fic.level_engine(engine, B)])

@@ -65,6 +65,12 @@ enum {
  *             FP32 at B = 32. */
 enum { FIC_ENGINE_MFMA = 0, FIC_ENGINE_FP32 = 1, FIC_ENGINE_MFMA_I8 = 2, FIC_ENGINE_MFMA_F16 = 3 };
 enum { FIC_MAX_LEVELS = 4, FIC_MAX_S = 32 };
+/* Pool keys.  Entropy (Sec. 3, Eq 5-6): G = sum over gray levels of
+ * T[count], larger G = lower entropy.  Variance (the alternative the paper
+ * cites in Sec. 1, low-variance domains deleted): 2^47 - (M sum p^2 -
+ * (sum p)^2) over the M = 4B^2 raw pixels, larger key = lower variance.  Both
+ * go through the same rule: drop the largest keys, cap to the smallest. */
+enum { FIC_POOL_ENTROPY = 0, FIC_POOL_VARIANCE = 1 };
 
 typedef struct fic_ctx fic_ctx;
 typedef void *fic_stream;            /* hipStream_t */
@@ -86,6 +92,7 @@ typedef struct {
     int32_t s_num[FIC_MAX_LEVELS][FIC_MAX_S]; /* strictly ascending, 0 <= num <= den */
     fic_ratio split_rms[FIC_MAX_LEVELS]; /* split iff RMS error > num/den; den 1..16; unused at the last level */
     int32_t engine;                  /* FIC_ENGINE_MFMA (default), _FP32, _MFMA_I8 or _MFMA_F16 */
+    int32_t pool_key;                /* FIC_POOL_ENTROPY (default, Sec. 3) or FIC_POOL_VARIANCE */
 } fic_params;
 
 /* Domain pool of one level (Sec. 3.3: the domain address is the list index).
@@ -186,11 +193,12 @@ int fic_entropy_table(int64_t *out, int32_t n);
 /* Sec. 3, Eq 5-6 and Sec. 3.2.1: the domain pool for range size B at step L.
  * Candidates are all 2B x 2B blocks at multiples of L, raster order.  With
  * c = ceil(pct*Nd) > 0, the c-th largest key is the threshold t and the pool
- * keeps keys < t (entropy strictly greater); if none, it keeps the keys equal
- * to the minimum.  pool_max > 0 then keeps the pool_max smallest (key, index)
- * pairs.  out->capacity must be >= Nd. */
+ * keeps keys < t (entropy, or variance, strictly greater); if none, it keeps
+ * the keys equal to the minimum.  pool_max > 0 then keeps the pool_max
+ * smallest (key, index) pairs.  pool_key: FIC_POOL_ENTROPY or
+ * FIC_POOL_VARIANCE.  out->capacity must be >= the pool size bound. */
 int fic_build_domain_pool(fic_ctx *ctx, const fic_image *img, int32_t B, int32_t L,
-                          fic_ratio pct, int32_t pool_max, fic_pool *out, fic_stream stream);
+                          fic_ratio pct, int32_t pool_max, int32_t pool_key, fic_pool *out, fic_stream stream);
 
 /* One quadtree step (Sec. 2): searches the *n_ranges (device) ranges
  * ranges_xy against every pool domain, 8 isometries and s_count contrasts,

@@ -50,7 +50,9 @@ def lib():
         L.orc_entropy_key.argtypes = [P, i32, i32, i32, i32]
         L.orc_entropy_key.restype = i64
         L.orc_candidates.argtypes = [i32, i32, i32, i32, P, i32]
-        L.orc_build_pool.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, i32, P, P, P, P, i32]
+        L.orc_build_pool.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, i32, i32, P, P, P, P, i32]
+        L.orc_variance_key.argtypes = [P, i32, i32, i32, i32]
+        L.orc_variance_key.restype = i64
         L.orc_iso_source.argtypes = [i32, i32, i32, i32, P, P]
         L.orc_encode_level.argtypes = [P, i32, i32, i32, P, i32, P, i32, i32, P, i32, i32, i32, i32, i32,
                                        P, P, P, P, P, P]
@@ -89,7 +91,17 @@ def iso_source(t: int, B: int, y: int, x: int):
     return sy.value, sx.value
 
 
-def build_pool(img: np.ndarray, B: int, L: int, pct=(0, 1), pool_max: int = 0) -> dict:
+POOL_KEYS = {"entropy": 0, "variance": 1}
+
+
+def variance_key(img: np.ndarray, x: int, y: int, size: int) -> int:
+    img = np.ascontiguousarray(img, np.uint8)
+    return lib().orc_variance_key(_p(img), img.shape[1], x, y, size)
+
+
+def build_pool(img: np.ndarray, B: int, L: int, pct=(0, 1), pool_max: int = 0, pool_key: str = "entropy") -> dict:
+    """Sec. 3 Eq 5-6 (entropy key) or the variance key of the cited
+    alternative; the same percentile and DN rules for both."""
     img = np.ascontiguousarray(img, np.uint8)
     H, W = img.shape
     nd = lib().orc_candidates(W, H, B, L, None, 0)
@@ -99,7 +111,7 @@ def build_pool(img: np.ndarray, B: int, L: int, pct=(0, 1), pool_max: int = 0) -
     key = np.zeros(nd, np.int64)
     sum4 = np.zeros(nd, np.uint32)
     a = np.zeros(nd, np.int64)
-    cnt = lib().orc_build_pool(_p(img), W, H, W, B, L, pct[0], pct[1], pool_max,
+    cnt = lib().orc_build_pool(_p(img), W, H, W, B, L, pct[0], pct[1], pool_max, POOL_KEYS[pool_key],
                                _p(xy), _p(key), _p(sum4), _p(a), nd)
     if cnt < 0:
         raise ValueError("orc_build_pool failed: %d" % cnt)
@@ -156,7 +168,7 @@ def encode_level(img: np.ndarray, pool_xy: np.ndarray, ranges_xy: np.ndarray, B:
 
 
 def encode(img: np.ndarray, levels, pct=(3, 10), pool_max: int = 0, s_num=None, s_den: int = 16,
-           split_rms=None, workers: int = 1) -> list:
+           split_rms=None, workers: int = 1, pool_key: str = "entropy") -> list:
     """Whole quadtree.  levels: list of (B, L) per step.  s_num / s_den /
     split_rms may be per-level lists or single values.  Returns one dict
     per level with the pool, the ranges and the codes."""
@@ -168,7 +180,7 @@ def encode(img: np.ndarray, levels, pct=(3, 10), pool_max: int = 0, s_num=None, 
     out = []
     ranges = level0_ranges(W, H, levels[0][0])
     for li, (B, L) in enumerate(levels):
-        pool = build_pool(img, B, L, pct, pool_max)
+        pool = build_pool(img, B, L, pct, pool_max, pool_key)
         is_last = li == nl - 1
         codes = encode_level(img, pool["xy"], ranges, B, s_num_l[li], s_den_l[li],
                              rms_l[li] if rms_l[li] is not None else (0, 1), is_last, workers)

@@ -74,6 +74,24 @@ int64_t orc_entropy_key(const uint8_t *img, int pitch, int x, int y, int size)
     return g;
 }
 
+/* Variance pool (the alternative the paper cites in Sec. 1: domains of
+ * small variance are deleted): key = 2^47 - (M sum p^2 - (sum p)^2) over the
+ * M raw pixels of the block, so a smaller key means a larger variance and
+ * the entropy pool's drop-the-largest-keys rule applies unchanged.
+ * M sum p^2 - (sum p)^2 = M^2 var <= 4096^2 * 255^2 / 4 < 2^47. */
+int64_t orc_variance_key(const uint8_t *img, int pitch, int x, int y, int size)
+{
+    int64_t s = 0, ss = 0;
+    for (int dy = 0; dy < size; ++dy)
+        for (int dx = 0; dx < size; ++dx) {
+            const int64_t v = img[(size_t)(y + dy) * pitch + x + dx];
+            s += v;
+            ss += v * v;
+        }
+    const int64_t m = (int64_t)size * size;
+    return ((int64_t)1 << 47) - (m * ss - s * s);
+}
+
 /* Sec. 2: all 2B x 2B blocks at integer step L, raster order. */
 int orc_candidates(int W, int H, int B, int L, uint32_t *xy, int cap)
 {
@@ -122,10 +140,11 @@ static void decimate(const uint8_t *img, int pitch, int x, int y, int B, int32_t
  * Returns the pool size, or a negative status.
  */
 int orc_build_pool(const uint8_t *img, int W, int H, int pitch, int B, int L,
-                   int p_num, int p_den, int pool_max,
+                   int p_num, int p_den, int pool_max, int key_kind,
                    uint32_t *xy, int64_t *key, uint32_t *sum4, int64_t *a, int cap)
 {
-    if (p_den < 1 || p_num < 0 || p_num >= p_den || pool_max < 0) return ORC_EINVAL;
+    if (p_den < 1 || p_num < 0 || p_num >= p_den || pool_max < 0 || key_kind < 0 || key_kind > 1)
+        return ORC_EINVAL;
     int nd = orc_candidates(W, H, B, L, NULL, 0);
     if (nd < 0) return nd;
     uint32_t *cxy = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nd);
@@ -141,7 +160,8 @@ int orc_build_pool(const uint8_t *img, int W, int H, int pitch, int B, int L,
     orc_candidates(W, H, B, L, cxy, nd);
     int64_t gmin = INT64_MAX;
     for (int i = 0; i < nd; ++i) {
-        g[i] = orc_entropy_key(img, pitch, (int)(cxy[i] & 0xffff), (int)(cxy[i] >> 16), 2 * B);
+        g[i] = key_kind == 0 ? orc_entropy_key(img, pitch, (int)(cxy[i] & 0xffff), (int)(cxy[i] >> 16), 2 * B)
+                             : orc_variance_key(img, pitch, (int)(cxy[i] & 0xffff), (int)(cxy[i] >> 16), 2 * B);
         if (g[i] < gmin) gmin = g[i];
     }
     /* c = ceil(p * Nd) lowest-entropy candidates (largest G) set the threshold */

@@ -233,7 +233,7 @@ struct LevelPlan {
 // build_integ: this plan computes the images' summed-area tables (every plan
 // of one encode lays them out identically, so later levels reuse them).
 void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int engine, int level0,
-                bool build_integ) {
+                bool build_integ, int pool_key) {
     const int n = (int)in.size();
     pl.h.assign(n, ImgLvl());
     pl.pre.assign((size_t)K_NUM * (n + 1), 0);
@@ -244,6 +244,7 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
     const int eng = do_search ? engine_for(engine, B) : E_FP32;
     pl.bh.B = B;
     pl.bh.eng = eng;
+    pl.bh.pool_key = pool_key;
     pl.bh.L = in[0].L;
     pl.bh.KS = KS;
     size_t off[S_NUM_SLOTS] = {0};
@@ -288,7 +289,8 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
         // block counts
         int blk[K_NUM] = {0};
         if (level0) blk[K_LEVEL0] = cdiv((long)(d.W / d.B) * (d.H / d.B), 256);
-        blk[K_KEYS] = cdiv(d.nx, 64) * cdiv(d.ny, 16);
+        // entropy: one wave per strip of candidates; variance: one thread per candidate
+        blk[K_KEYS] = pool_key == FIC_POOL_VARIANCE ? cdiv(d.nd, 256) : cdiv(d.nx, 64) * cdiv(d.ny, 16);
         blk[K_HIST] = max(1, min(256, cdiv(d.nd, 256)));
         blk[K_PCMP] = cdiv(d.nd, kScanBlock);
         blk[K_MOM] = cdiv(d.pool_cap, 256);
@@ -696,6 +698,7 @@ int fic_validate_params(const fic_params *p, int32_t width, int32_t height) {
     if (width < 2 * p->block0 || height < 2 * p->block0 || width % p->block0 || height % p->block0) return FIC_E_INVALID;
     if (width > 65535 || height > 65535 || (int64_t)width * height > (1 << 28)) return FIC_E_INVALID;
     if (check_pct(p->pool_pct) != FIC_OK || p->pool_max < 0) return FIC_E_INVALID;
+    if (p->pool_key != FIC_POOL_ENTROPY && p->pool_key != FIC_POOL_VARIANCE) return FIC_E_INVALID;
     if (!engine_ok(p->engine)) return FIC_E_INVALID;
     for (int l = 0; l < p->levels; ++l) {
         if (p->step[l] < 1) return FIC_E_INVALID;
@@ -832,9 +835,9 @@ int fic_ctx_read_timing(fic_ctx *ctx, fic_timing *out) {
 }
 
 int fic_build_domain_pool(fic_ctx *ctx, const fic_image *img, int32_t B, int32_t L, fic_ratio pct,
-                          int32_t pool_max, fic_pool *out, fic_stream stream) {
+                          int32_t pool_max, int32_t pool_key, fic_pool *out, fic_stream stream) {
     if (!ctx || B < 2 || B > 32 || L < 1 || !image_ok(img, B) || check_pct(pct) != FIC_OK || pool_max < 0 ||
-        !pool_ok(out))
+        !pool_ok(out) || (pool_key != FIC_POOL_ENTROPY && pool_key != FIC_POOL_VARIANCE))
         return FIC_E_INVALID;
     const int64_t nd = n_candidates(img->width, img->height, B, L);
     const int64_t need = (pool_max > 0 && pool_max < nd) ? pool_max : nd;
@@ -844,7 +847,7 @@ int fic_build_domain_pool(fic_ctx *ctx, const fic_image *img, int32_t B, int32_t
     std::vector<ImgIn> in(1);
     in[0] = ImgIn{img, B, L, pct.num, pct.den, pool_max, out, nullptr, nullptr, 0, nullptr, nullptr, nullptr};
     std::vector<LevelPlan> plans(1);
-    plan_level(plans[0], in, false, FIC_ENGINE_MFMA, 0, true);
+    plan_level(plans[0], in, false, FIC_ENGINE_MFMA, 0, true, pool_key);
     st = reserve_plans(ctx, plans, 0);
     if (st != FIC_OK) return st;
     bind(ctx, plans[0]);
@@ -873,7 +876,7 @@ int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, c
     in[0] = ImgIn{img, B, B, 0, 1, 0, const_cast<fic_pool *>(pool), ranges_xy, n_ranges, range_capacity, out,
                   children_xy, n_children};
     std::vector<LevelPlan> plans(1);
-    plan_level(plans[0], in, true, engine, 0, true);
+    plan_level(plans[0], in, true, engine, 0, true, FIC_POOL_ENTROPY);
     plans[0].bh.ss = make_sset(s_num, s_count, s_den);
     plans[0].bh.rms = split_rms;
     plans[0].bh.is_last = is_last ? 1 : 0;
@@ -935,7 +938,7 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
                           cl->xy, cl->count, (img->width / B) * (img->height / B), cl,
                           last ? nullptr : codes[i * NL + l + 1].xy, last ? nullptr : codes[i * NL + l + 1].count};
         }
-        plan_level(plans[l], in, true, p->engine, l == 0, l == 0);
+        plan_level(plans[l], in, true, p->engine, l == 0, l == 0, p->pool_key);
         plans[l].bh.ss = make_sset(p->s_num[l], p->s_count[l], p->s_den[l]);
         plans[l].bh.rms = p->split_rms[l];
         plans[l].bh.is_last = last ? 1 : 0;

@@ -271,7 +271,7 @@ __device__ inline int find_img(const int *pre, int n, int b) {
 struct BatchHost {
     BatchDev dev;
     int blocks[K_NUM];   // total workgroups per kind
-    int B, L, KS, any_cap, eng;
+    int B, L, KS, any_cap, eng, pool_key;
     SSet ss;
     fic_ratio rms;
     int is_last;

@@ -86,6 +86,31 @@ __global__ __launch_bounds__(64) void k_pool_keys(BatchDev b, const int64_t *__r
     if (lane == 0) atomicMin(&d.sel->gmin, (unsigned long long)gm);
 }
 
+// Variance key (the alternative pool cited in Sec. 1): one thread per
+// candidate, from the summed-area tables; 2^47 - (M sum p^2 - (sum p)^2), so a
+// smaller key means a larger variance and the selection below is unchanged.
+__global__ __launch_bounds__(256) void k_pool_keys_var(BatchDev b) {
+    const int *pre = b.pre + K_KEYS * (b.n + 1);
+    const int im = find_img(pre, b.n, blockIdx.x);
+    const ImgLvl &d = b.d[im];
+    const int i = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int64_t key = INT64_MAX;
+    if (i < d.nd) {
+        const int cy = i / d.nx, cx = i - cy * d.nx;
+        const int x = cx * d.L, y = cy * d.L, size = 2 * d.B;
+        const IntegGeom g = integ_geom(d.W, d.H);
+        const int64_t s = box_sum(g.si(d.integ), g.ws, x, y, size, size);
+        const int64_t ss = box_sum(g.sii(d.integ), g.ws, x, y, size, size);
+        key = ((int64_t)1 << 47) - ((int64_t)size * size * ss - s * s);
+        d.keys[i] = key;
+    }
+    // wave minimum, then one atomic per wave
+    int64_t gm = key;
+    for (int off = 32; off > 0; off >>= 1) gm = min(gm, (int64_t)__shfl_xor(gm, off, 64));
+    if (lane == 0 && gm != INT64_MAX) atomicMin(&d.sel->gmin, (unsigned long long)gm);
+}
+
 // ---------------------------------------------------------------- radix select
 // Passes 0..5 pick the key 8 bits at a time (keys < 2^48); passes 6..9 pick
 // the candidate index (< 2^32).  The percentile select finds the c-th largest
@@ -226,7 +251,10 @@ __global__ __launch_bounds__(256) void k_pool_moments(BatchDev b) {
 hipError_t launch_pool_b(const BatchHost &b, const int64_t *table, hipStream_t st) {
     const BatchDev &dv = b.dev;
     k_sel_init<<<dv.n, 256, 0, st>>>(dv);
-    if (b.blocks[K_KEYS] > 0) k_pool_keys<<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table);
+    if (b.blocks[K_KEYS] > 0) {
+        if (b.pool_key == FIC_POOL_VARIANCE) k_pool_keys_var<<<b.blocks[K_KEYS], 256, 0, st>>>(dv);
+        else k_pool_keys<<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table);
+    }
     for (int pass = 0; pass < 6; ++pass) {
         k_sel_hist<<<b.blocks[K_HIST], 256, 0, st>>>(dv, pass, 0);
         k_sel_pick<<<dv.n, 256, 0, st>>>(dv, pass, 0);

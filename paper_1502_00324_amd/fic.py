@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfic.so")
 
 FIC_OK, FIC_E_INVALID, FIC_E_NOMEM, FIC_E_HIP, FIC_E_CAPACITY, FIC_E_ARCH = 0, -1, -2, -3, -4, -5
 ENGINE_MFMA, ENGINE_FP32, ENGINE_MFMA_I8, ENGINE_MFMA_F16 = 0, 1, 2, 3
+POOL_ENTROPY, POOL_VARIANCE = 0, 1
 MAX_LEVELS, MAX_S = 4, 32
 
 i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
@@ -40,7 +41,8 @@ class Image(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("levels", i32), ("block0", i32), ("step", i32 * MAX_LEVELS), ("pool_pct", Ratio),
                 ("pool_max", i32), ("s_count", i32 * MAX_LEVELS), ("s_den", i32 * MAX_LEVELS),
-                ("s_num", (i32 * MAX_S) * MAX_LEVELS), ("split_rms", Ratio * MAX_LEVELS), ("engine", i32)]
+                ("s_num", (i32 * MAX_S) * MAX_LEVELS), ("split_rms", Ratio * MAX_LEVELS), ("engine", i32),
+                ("pool_key", i32)]
 
 
 T_POOL, T_PREP, T_SEARCH, T_FINAL, T_DECODE, T_KINDS = 0, 1, 2, 3, 4, 5
@@ -92,7 +94,7 @@ def lib() -> ctypes.CDLL:
         L.fic_unpack.argtypes = [vp, i64, ctypes.POINTER(PoolC), ctypes.POINTER(CodesC)]
         L.fic_s_histogram.argtypes = [vp, ctypes.POINTER(Image), ctypes.POINTER(Params), ctypes.POINTER(PoolC),
                                       ctypes.POINTER(CodesC), i32, vp, vp]
-        L.fic_build_domain_pool.argtypes = [vp, ctypes.POINTER(Image), i32, i32, Ratio, i32, ctypes.POINTER(PoolC),
+        L.fic_build_domain_pool.argtypes = [vp, ctypes.POINTER(Image), i32, i32, Ratio, i32, i32, ctypes.POINTER(PoolC),
                                             vp]
         L.fic_encode_level.argtypes = [vp, ctypes.POINTER(Image), ctypes.POINTER(PoolC), vp, vp, i32, i32, vp, i32,
                                        i32, Ratio, i32, i32, ctypes.POINTER(CodesC), vp, vp, vp]
@@ -124,7 +126,7 @@ def _check(status: int, where: str):
 
 # ---------------------------------------------------------------- parameters
 def make_params(levels, block0=None, pct=(3, 10), pool_max=0, s_num=tuple(range(17)), s_den=16,
-                split_rms=(8, 1), engine=ENGINE_MFMA) -> Params:
+                split_rms=(8, 1), engine=ENGINE_MFMA, pool_key=POOL_ENTROPY) -> Params:
     """levels: list of (B, L).  s_num / s_den / split_rms: one value for all
     levels or one per level."""
     p = Params()
@@ -147,6 +149,7 @@ def make_params(levels, block0=None, pct=(3, 10), pool_max=0, s_num=tuple(range(
     p.pool_pct = Ratio(int(pct[0]), int(pct[1]))
     p.pool_max = pool_max
     p.engine = engine
+    p.pool_key = pool_key
     return p
 
 
@@ -387,13 +390,14 @@ class Context:
         return out
 
     # -------------------------------------------------------------- entry points
-    def build_domain_pool(self, img, B: int, L: int, pct=(3, 10), pool_max: int = 0, pool: Pool | None = None) -> Pool:
+    def build_domain_pool(self, img, B: int, L: int, pct=(3, 10), pool_max: int = 0, pool: Pool | None = None,
+                          pool_key: int = POOL_ENTROPY) -> Pool:
         H, W = img.shape
         nd = ((W - 2 * B) // L + 1) * ((H - 2 * B) // L + 1)
         cap = min(nd, pool_max) if pool_max > 0 else nd
         pool = pool or Pool.alloc(cap, img.device)
         pc = pool.c()
-        _check(lib().fic_build_domain_pool(self.h, ctypes.byref(_image(img)), B, L, Ratio(*pct), pool_max,
+        _check(lib().fic_build_domain_pool(self.h, ctypes.byref(_image(img)), B, L, Ratio(*pct), pool_max, pool_key,
                                            ctypes.byref(pc), _stream()), "fic_build_domain_pool")
         return pool
 

@@ -74,6 +74,8 @@ BAD = [
     ("rms_den17", lambda p: p.split_rms.__setitem__(0, fic.Ratio(8, 17))),
     ("rms_neg", lambda p: p.split_rms.__setitem__(0, fic.Ratio(-1, 1))),
     ("engine4", lambda p: setattr(p, "engine", 4)),
+    ("pool_key2", lambda p: setattr(p, "pool_key", 2)),
+    ("pool_key_neg", lambda p: setattr(p, "pool_key", -1)),
     ("engine_neg", lambda p: setattr(p, "engine", -1)),
 ]
 
@@ -109,7 +111,7 @@ def test_null_context_is_rejected_before_any_device_work():
     codes = fic.CodesC()
     assert L.fic_encode(None, ctypes.byref(img), 1, ctypes.byref(p), ctypes.byref(pool), ctypes.byref(codes),
                         None) == fic.FIC_E_INVALID
-    assert L.fic_build_domain_pool(None, ctypes.byref(img), 8, 4, fic.Ratio(3, 10), 0, ctypes.byref(pool),
+    assert L.fic_build_domain_pool(None, ctypes.byref(img), 8, 4, fic.Ratio(3, 10), 0, 0, ctypes.byref(pool),
                                    None) == fic.FIC_E_INVALID
     assert L.fic_decode(None, ctypes.byref(p), ctypes.byref(pool), ctypes.byref(codes), 64, 64, 1, None,
                         None) == fic.FIC_E_INVALID

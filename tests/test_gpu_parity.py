@@ -188,6 +188,29 @@ def test_determinism_and_batch_independence(ctx):
                 np.testing.assert_array_equal(a["codes"][f], c["codes"][f])
 
 
+VARIANCE_CASES = [
+    ("var_two_levels", 31, 96, 64, 8, [(8, 2), (4, 2)], (3, 10), 0, K16, 16, (6, 1)),
+    ("var_paper_dn32", 32, 128, 128, 12, [(16, 4), (8, 4), (4, 4), (2, 4)], (0, 1), 32,
+     ((1,), (2, 4), (3, 8), (5, 9)), 10, (8, 1)),
+    ("var_b32", 33, 128, 128, 10, [(32, 4), (16, 4)], (1, 2), 0, K16, 16, (8, 1)),
+]
+
+
+@pytest.mark.parametrize("engine", [fic.ENGINE_MFMA, fic.ENGINE_FP32], ids=["mfma", "fp32"])
+@pytest.mark.parametrize("case", VARIANCE_CASES, ids=lambda c: c[0])
+def test_variance_pool_parity(ctx, case, engine):
+    """The variance-keyed pool (the alternative cited in Sec. 1) through the
+    whole encode: pools (xy, key, sum4, A) and codes equal the oracle's."""
+    name, seed, W, H, nr, levels, pct, dn, s_num, s_den, rms = case
+    img = make_image(seed, W, H, nr)
+    p = fic.make_params(levels, pct=pct, pool_max=dn, s_num=s_num, s_den=s_den, split_rms=rms, engine=engine,
+                        pool_key=fic.POOL_VARIANCE)
+    got, _ = gpu_run(ctx, img, p)
+    ref = oracle.encode(img, levels, pct=pct, pool_max=dn, s_num=s_num, s_den=s_den, split_rms=rms,
+                        workers=WORKERS, pool_key="variance")
+    assert_levels_equal(got, ref, name)
+
+
 def test_graph_replay_matches_eager_encodes(ctx):
     """fic_ctx_set_graphs: the first encode of an argument set is captured,
     repeats are graph replays.  Each replay (with eager work and a
