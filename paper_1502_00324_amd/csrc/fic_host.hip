@@ -248,6 +248,15 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
     pl.bh.L = in[0].L;
     pl.bh.KS = KS;
     size_t off[S_NUM_SLOTS] = {0};
+    // entropy-key strip length, one per level: strips of candidate rows as long
+    // as possible (sliding windows reuse work) while the whole batch still
+    // gives ~1024 waves
+    long strip_rows = 0;
+    for (const ImgIn &x : in) {
+        const int nx = (x.img->width - 2 * x.B) / x.L + 1, ny = (x.img->height - 2 * x.B) / x.L + 1;
+        strip_rows += (long)cdiv(nx, 64) * ny;
+    }
+    const int strip = (int)max(1L, min(16L, strip_rows / 1024));
     for (int i = 0; i < n; ++i) {
         const ImgIn &x = in[i];
         ImgLvl &d = pl.h[i];
@@ -289,8 +298,11 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
         // block counts
         int blk[K_NUM] = {0};
         if (level0) blk[K_LEVEL0] = cdiv((long)(d.W / d.B) * (d.H / d.B), 256);
-        // entropy: one wave per strip of candidates; variance: one thread per candidate
-        blk[K_KEYS] = pool_key == FIC_POOL_VARIANCE ? cdiv(d.nd, 256) : cdiv(d.nx, 64) * cdiv(d.ny, 16);
+        // entropy: one wave per strip of candidate rows, the strip as long as
+        // possible (sliding windows reuse work) while still giving ~1024 waves;
+        // variance: one thread per candidate
+        d.strip = strip;
+        blk[K_KEYS] = pool_key == FIC_POOL_VARIANCE ? cdiv(d.nd, 256) : cdiv(d.nx, 64) * cdiv(d.ny, d.strip);
         blk[K_HIST] = max(1, min(256, cdiv(d.nd, 256)));
         blk[K_PCMP] = cdiv(d.nd, kScanBlock);
         blk[K_MOM] = cdiv(d.pool_cap, 256);

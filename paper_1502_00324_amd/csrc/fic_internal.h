@@ -174,6 +174,7 @@ struct ImgLvl {
     int W, H, pitch;
     // level geometry: candidates nx * ny = nd at step L, c = ceil(p nd)
     int B, L, nx, ny, nd, pool_max, pool_cap, range_cap;
+    int strip;           // candidate rows per wave of the entropy key kernel
     long long c;
     // pool (caller buffers)
     int32_t *pcount;

@@ -9,10 +9,10 @@ namespace fic {
 // ---------------------------------------------------------------- keys
 // G = sum over gray levels of T[count]; a larger G means a lower entropy.
 // One wave per strip: lane l owns candidate column cx = 64 gx + l and slides
-// its window down over kStripRows candidate rows.  Each lane keeps a private
+// its window down over d.strip candidate rows (1..16, chosen per image so
+// small images still give the GPU enough waves).  Each lane keeps a private
 // 256-bin histogram in LDS (layout [bin][lane], no atomics) and updates G
 // incrementally: adding a pixel whose bin held c adds T[c+1] - T[c].
-constexpr int kStripRows = 16;
 
 __global__ __launch_bounds__(64) void k_pool_keys(BatchDev b, const int64_t *__restrict__ T) {
     __shared__ uint16_t hist[256][64];
@@ -31,8 +31,8 @@ __global__ __launch_bounds__(64) void k_pool_keys(BatchDev b, const int64_t *__r
     for (int v = 0; v < 256; ++v) hist[v][lane] = 0;
     __syncthreads();
     const int cx = gx * 64 + lane;
-    const int cy0 = gy * kStripRows;
-    const int cy1 = min(d.ny, cy0 + kStripRows);
+    const int cy0 = gy * d.strip;
+    const int cy1 = min(d.ny, cy0 + d.strip);
     // inactive lanes stay for the wave reduction below
     const bool active = cx < nx && cy0 < d.ny;
     const uint8_t *col = d.pix + (size_t)(active ? cx : 0) * L;
