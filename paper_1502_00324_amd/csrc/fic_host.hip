@@ -257,6 +257,9 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
         strip_rows += (long)cdiv(nx, 64) * ny;
     }
     const int strip = (int)max(1L, min(16L, strip_rows / 1024));
+    pl.bh.fused_sel = 1;
+    for (const ImgIn &x : in)
+        if (n_candidates(x.img->width, x.img->height, x.B, x.L) > kFusedSelMax) pl.bh.fused_sel = 0;
     for (int i = 0; i < n; ++i) {
         const ImgIn &x = in[i];
         ImgLvl &d = pl.h[i];

@@ -16,6 +16,7 @@ constexpr int kTableSize = 4097;       // entropy table entries, q = 0..4096
 constexpr int kScanBlock = 1024;       // items per block in stable compaction
 constexpr int kDomTile = 16;           // domains per column tile of the int8 engine
 constexpr int kDomTile32 = 32;         // domains per column tile of the f16 engine
+constexpr int kFusedSelMax = 131072;   // candidates per image for the one-workgroup selection
 
 // ---------------------------------------------------------------- small PODs
 // Contrast set of one level, passed by value to kernels.
@@ -273,6 +274,7 @@ struct BatchHost {
     BatchDev dev;
     int blocks[K_NUM];   // total workgroups per kind
     int B, L, KS, any_cap, eng, pool_key;
+    int fused_sel;       // every image has <= kFusedSelMax candidates: one-workgroup selection
     SSet ss;
     fic_ratio rms;
     int is_last;

@@ -207,6 +207,99 @@ __global__ __launch_bounds__(256) void k_sel_pick(BatchDev b, int pass, int whic
     }
 }
 
+// All select passes of one image in one 1024-thread workgroup (levels whose
+// images have few candidates): the same digit-by-digit selection as
+// k_sel_hist / k_sel_pick, with the histogram and the selection state in LDS,
+// so a level's selection is one launch instead of 12 (or 32 with a cap).
+__global__ __launch_bounds__(1024) void k_sel_fused(BatchDev b) {
+    __shared__ uint32_t h[256], cum[256];
+    __shared__ unsigned long long kpre[2];
+    __shared__ uint32_t ipre[2];
+    __shared__ int32_t rem[2], all[2];
+    const ImgLvl &d = b.d[blockIdx.x];
+    const int t = threadIdx.x;
+    const unsigned long long gmin = d.sel->gmin;
+    if (t == 0) {
+        kpre[0] = kpre[1] = 0;
+        ipre[0] = ipre[1] = 0;
+        rem[0] = (int32_t)d.c;
+        all[0] = d.c == 0 ? 1 : 0;
+        rem[1] = d.pool_max;
+        all[1] = d.pool_max == 0 ? 1 : 0;
+    }
+    __syncthreads();
+    for (int which = 0; which < 2; ++which) {
+        const int largest = which ? 0 : 1;
+        for (int pass = 0; pass < (which ? 10 : 6); ++pass) {
+            if (all[which]) break;  // uniform: read after a barrier
+            if (t < 256) h[t] = 0;
+            const unsigned long long kp = kpre[which];
+            const uint32_t ip = ipre[which];
+            __syncthreads();
+            for (int i = t; i < d.nd; i += 1024) {
+                const int64_t key = d.keys[i];
+                if (which) {   // the percentile step's survivors only
+                    const unsigned long long tk = kpre[0];
+                    const bool keep = d.c == 0 || (unsigned long long)key < tk ||
+                                      (tk == gmin && (unsigned long long)key == gmin);
+                    if (!keep) continue;
+                }
+                uint32_t dg;
+                if (pass < 6) {
+                    const int sh = 40 - 8 * pass;
+                    if (((unsigned long long)key >> (sh + 8)) != (kp >> (sh + 8))) continue;
+                    dg = (uint32_t)(((unsigned long long)key >> sh) & 255u);
+                } else {
+                    const int sh = 24 - 8 * (pass - 6);
+                    if ((unsigned long long)key != kp) continue;
+                    if (sh < 24 && ((uint32_t)i >> (sh + 8)) != (ip >> (sh + 8))) continue;
+                    dg = ((uint32_t)i >> sh) & 255u;
+                }
+                atomicAdd(&h[dg], 1u);
+            }
+            __syncthreads();
+            // scan in the order of the wanted digits (descending for the largest)
+            int dgt = 0;
+            uint32_t cnt = 0;
+            if (t < 256) {
+                dgt = largest ? 255 - t : t;
+                cnt = h[dgt];
+                cum[t] = cnt;
+            }
+            __syncthreads();
+            for (int off = 1; off < 256; off <<= 1) {
+                const uint32_t v = (t < 256 && t >= off) ? cum[t - off] : 0u;
+                __syncthreads();
+                if (t < 256) cum[t] += v;
+                __syncthreads();
+            }
+            const int32_t r = rem[which];
+            const uint32_t total = cum[255];
+            __syncthreads();  // every thread has read rem before it changes
+            if (t < 256) {
+                const uint32_t incl = cum[t], excl = incl - cnt;
+                if (pass == 0 && total < (uint32_t)r) {
+                    if (t == 0) all[which] = 1;
+                } else if (excl < (uint32_t)r && (uint32_t)r <= incl) {
+                    rem[which] = r - (int32_t)excl;
+                    if (pass < 6) kpre[which] |= (unsigned long long)dgt << (40 - 8 * pass);
+                    else ipre[which] |= (uint32_t)dgt << (24 - 8 * (pass - 6));
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (t == 0) {
+        SelState *st[2] = {&d.sel->pct, &d.sel->cap};
+        for (int w = 0; w < 2; ++w) {
+            st[w]->key_prefix = kpre[w];
+            st[w]->idx_prefix = ipre[w];
+            st[w]->remaining = rem[w];
+            st[w]->all = all[w];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- compaction
 struct PoolOp {
     int mult = 1;
@@ -255,15 +348,19 @@ hipError_t launch_pool_b(const BatchHost &b, const int64_t *table, hipStream_t s
         if (b.pool_key == FIC_POOL_VARIANCE) k_pool_keys_var<<<b.blocks[K_KEYS], 256, 0, st>>>(dv);
         else k_pool_keys<<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table);
     }
-    for (int pass = 0; pass < 6; ++pass) {
-        k_sel_hist<<<b.blocks[K_HIST], 256, 0, st>>>(dv, pass, 0);
-        k_sel_pick<<<dv.n, 256, 0, st>>>(dv, pass, 0);
-    }
-    if (b.any_cap)
-        for (int pass = 0; pass < 10; ++pass) {
-            k_sel_hist<<<b.blocks[K_HIST], 256, 0, st>>>(dv, pass, 1);
-            k_sel_pick<<<dv.n, 256, 0, st>>>(dv, pass, 1);
+    if (b.fused_sel) {
+        k_sel_fused<<<dv.n, 1024, 0, st>>>(dv);
+    } else {
+        for (int pass = 0; pass < 6; ++pass) {
+            k_sel_hist<<<b.blocks[K_HIST], 256, 0, st>>>(dv, pass, 0);
+            k_sel_pick<<<dv.n, 256, 0, st>>>(dv, pass, 0);
         }
+        if (b.any_cap)
+            for (int pass = 0; pass < 10; ++pass) {
+                k_sel_hist<<<b.blocks[K_HIST], 256, 0, st>>>(dv, pass, 1);
+                k_sel_pick<<<dv.n, 256, 0, st>>>(dv, pass, 1);
+            }
+    }
     hipError_t e = compact_b(dv, K_PCMP, b.blocks[K_PCMP], PoolOp{}, st);
     if (e != hipSuccess) return e;
     if (b.blocks[K_MOM] > 0) k_pool_moments<<<b.blocks[K_MOM], 256, 0, st>>>(dv);

@@ -29,7 +29,7 @@ KIND_OF = [("k_level0", K_LEVEL0), ("k_pool_keys", K_KEYS), ("k_sel_hist", K_HIS
            ("k_f16_search", K_SEARCH), ("k_fp32_search", K_SEARCH), ("k_finalize", K_FINAL),
            ("k_integ_rows", K_IROW), ("k_integ_colsum", K_ICOL), ("k_integ_coladd", K_ICOL),
            ("k_integ_colscan", K_ICSCAN)]
-PER_IMAGE = ("k_sel_init", "k_sel_pick", "k_bscan")
+PER_IMAGE = ("k_sel_init", "k_sel_pick", "k_bscan", "k_sel_fused")
 KIND_ARG = ("k_bcount", "k_bscatter")
 NUM_KINDS = 16
 
@@ -143,6 +143,9 @@ def main():
     scenario("paper_b2_cap", lambda: encode_case(L, h, [(64, 64), (32, 48)], [(16, 4), (8, 4), (4, 4), (2, 4)], M,
                                                  pool_max=64))
     scenario("min_images", lambda: encode_case(L, h, [(8, 8), (16, 8)], [(4, 1)], M))
+    # more candidates than the one-workgroup selection takes: multi-block passes
+    scenario("large_uncapped", lambda: encode_case(L, h, [(512, 512)], [(4, 1)], M, reps=1))
+    scenario("large_capped", lambda: encode_case(L, h, [(512, 512)], [(4, 1)], M, pool_max=100, reps=1))
     scenario("timing_toggle", lambda: encode_case(L, h, mixed[:3], [(16, 2), (8, 2)], M, reps=3,
                                                   timing_toggle=True))
     scenario("empty_batch", lambda: encode_case(L, h, [], [(8, 1), (4, 1)], M))

@@ -36,7 +36,7 @@ def runs(tmp_path_factory):
 
 
 SCENARIOS = ["single_mfma", "single_fp32", "mixed_mfma_3lv", "mixed_fp32_3lv", "mixed_i8_3lv", "mixed_f16_3lv",
-             "mixed_b32_4lv",
+             "mixed_b32_4lv", "large_uncapped", "large_capped",
              "paper_b2_cap", "min_images", "timing_toggle"]
 
 
@@ -85,10 +85,16 @@ def test_engine_choice(runs):
     assert "k_fp32_search" not in kinds(runs["paper_b2_cap"])   # B = 2 runs on the f16 engine
 
 
-def test_pool_size_select_runs_only_with_a_cap(runs):
-    per_level_uncapped = kinds(runs["single_mfma"]).count("k_sel_hist") // (2 * 2)
-    per_level_capped = kinds(runs["paper_b2_cap"]).count("k_sel_hist") // (2 * 4)
-    assert per_level_uncapped == 6 and per_level_capped == 16
+def test_selection_paths(runs):
+    # small levels: one fused selection launch per level, no pass launches
+    for name, levels in (("single_mfma", 2), ("paper_b2_cap", 4), ("mixed_mfma_3lv", 3)):
+        k = kinds(runs[name])
+        assert k.count("k_sel_fused") == 2 * levels and k.count("k_sel_hist") == 0
+    # large levels: 6 digit passes, 10 more with a pool-size cap
+    for name, passes in (("large_uncapped", 6), ("large_capped", 16)):
+        k = kinds(runs[name])
+        assert k.count("k_sel_fused") == 0
+        assert k.count("k_sel_hist") == passes and k.count("k_sel_pick") == passes
 
 
 def test_empty_batch_and_scratch_limit(runs):
