@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X published dense peaks per engine dtype (TFLOP/s, int8 in TOPS)
-PEAK = {"mfma_f16": 2500.0, "mfma_i8": 5000.0, "fp32": 157.3}
+PEAK = {"mfma_f16": 2500.0, "mfma_f16_16x16": 2500.0, "mfma_i8": 5000.0, "fp32": 157.3}
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1502_00324_amd/csrc/k_search_mfma.hip", "paper_1502_00324_amd/csrc/k_search_f16.hip",
                   "paper_1502_00324_amd/csrc/search_common.h", "paper_1502_00324_amd/csrc/fic_internal.h"]
@@ -33,7 +33,7 @@ def traffic_file(workload):
 
 def issued_ops(engine_name, B):
     """MFMA ops the engine issues per comparison (the algorithmic count is 2 B^2)."""
-    if engine_name == "mfma_f16":
+    if engine_name in ("mfma_f16", "mfma_f16_16x16"):
         return 2 * B * B                       # K = B^2 decimated positions
     if engine_name == "mfma_i8":
         return 8 * B * B if B == 4 else 4 * B * B   # raw pixels at B=4, hi/lo planes above
@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3_1024")
-    ap.add_argument("--engine", default="mfma", choices=["mfma", "mfma_i8", "mfma_f16"],
+    ap.add_argument("--engine", default="mfma", choices=["mfma", "mfma_i8", "mfma_f16", "mfma_f16_16x16"],
                     help="matrix engine of the timed steps (mfma = the faster form per block size)")
     ap.add_argument("--pool-key", default="entropy", choices=["entropy", "variance"],
                     help="domain pool key: entropy (the paper's) or variance (the cited alternative)")
@@ -140,8 +140,10 @@ def main():
     pool_key = fic.POOL_VARIANCE if args.pool_key == "variance" else fic.POOL_ENTROPY
     mk = lambda engine: fic.make_params(wl.levels, pct=wl.pct, pool_max=wl.pool_max, s_num=wl.s_num,
                                         s_den=wl.s_den, split_rms=wl.split_rms, engine=engine, pool_key=pool_key)
-    engine = {"mfma": fic.ENGINE_MFMA, "mfma_i8": fic.ENGINE_MFMA_I8, "mfma_f16": fic.ENGINE_MFMA_F16}[args.engine]
-    ENGINE_NAME = {fic.ENGINE_MFMA_F16: "mfma_f16", fic.ENGINE_MFMA_I8: "mfma_i8", fic.ENGINE_FP32: "fp32"}
+    engine = {"mfma": fic.ENGINE_MFMA, "mfma_i8": fic.ENGINE_MFMA_I8, "mfma_f16": fic.ENGINE_MFMA_F16,
+              "mfma_f16_16x16": fic.ENGINE_MFMA_F16_16X16}[args.engine]
+    ENGINE_NAME = {fic.ENGINE_MFMA_F16: "mfma_f16", fic.ENGINE_MFMA_I8: "mfma_i8", fic.ENGINE_FP32: "fp32",
+                   fic.ENGINE_MFMA_F16_16X16: "mfma_f16_16x16"}
     p = mk(engine)
     bufs = ctx.alloc_encode([(im.shape[1], im.shape[0]) for im in images], p, dev)
     if args.graphs:

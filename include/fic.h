@@ -56,14 +56,23 @@ enum {
 
 /* Search engines; all give identical codes.
  *   MFMA:     matrix cores, the faster form per block size: MFMA_F16 at
- *             B = 2 and 4, MFMA_I8 at B = 8 and 16; FP32 for B = 32.
+ *             B = 2 and 4, MFMA_F16_16X16 at B = 8, MFMA_I8 at B = 16;
+ *             FP32 for B = 32.
  *   FP32:     plain vector FP32 with the same exact epilogue (baseline).
  *   MFMA_I8:  int8 matrix cores for B = 4, 8, 16 (raw pixels at B = 4,
  *             decimated hi/lo planes above); FP32 elsewhere.
  *   MFMA_F16: f16 matrix cores with exact f32 accumulation over the B^2
  *             decimated positions for B = 2 (zero-padded to 16), 4, 8, 16;
- *             FP32 at B = 32. */
-enum { FIC_ENGINE_MFMA = 0, FIC_ENGINE_FP32 = 1, FIC_ENGINE_MFMA_I8 = 2, FIC_ENGINE_MFMA_F16 = 3 };
+ *             FP32 at B = 32 (32 x 32 result tiles).
+ *   MFMA_F16_16X16: f16 matrix cores in the 16 x 16 result tiles of the
+ *             int8 engine, for B = 8 and 16; FP32 elsewhere. */
+enum {
+    FIC_ENGINE_MFMA = 0,
+    FIC_ENGINE_FP32 = 1,
+    FIC_ENGINE_MFMA_I8 = 2,
+    FIC_ENGINE_MFMA_F16 = 3,
+    FIC_ENGINE_MFMA_F16_16X16 = 4
+};
 enum { FIC_MAX_LEVELS = 4, FIC_MAX_S = 32 };
 /* Pool keys.  Entropy (Sec. 3, Eq 5-6): G = sum over gray levels of
  * T[count], larger G = lower entropy.  Variance (the alternative the paper
@@ -91,7 +100,7 @@ typedef struct {
     int32_t s_den[FIC_MAX_LEVELS];   /* 1..1024 */
     int32_t s_num[FIC_MAX_LEVELS][FIC_MAX_S]; /* strictly ascending, 0 <= num <= den */
     fic_ratio split_rms[FIC_MAX_LEVELS]; /* split iff RMS error > num/den; den 1..16; unused at the last level */
-    int32_t engine;                  /* FIC_ENGINE_MFMA (default), _FP32, _MFMA_I8 or _MFMA_F16 */
+    int32_t engine;                  /* FIC_ENGINE_MFMA (default), _FP32, _MFMA_I8, _MFMA_F16, _MFMA_F16_16X16 */
     int32_t pool_key;                /* FIC_POOL_ENTROPY (default, Sec. 3) or FIC_POOL_VARIANCE */
 } fic_params;
 
@@ -178,7 +187,8 @@ int fic_query_capacity(const fic_params *p, int32_t width, int32_t height,
                        int64_t *pool_cap, int64_t *range_cap);
 
 /* The engine that runs the search of a level with block size B when engine
- * is requested: FIC_ENGINE_MFMA resolves to MFMA_F16, MFMA_I8 or FP32 per B,
+ * is requested: FIC_ENGINE_MFMA resolves to MFMA_F16, MFMA_F16_16X16,
+ * MFMA_I8 or FP32 per B,
  * and the matrix engines fall back to FP32 where they have no form.
  * Returns FIC_E_INVALID for an unknown engine or B outside 2..32. */
 int fic_level_engine(int32_t engine, int32_t B);

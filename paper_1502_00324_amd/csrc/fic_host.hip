@@ -151,16 +151,18 @@ void build_table() {
 // ---------------------------------------------------------------- validation
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-bool engine_ok(int e) { return e >= FIC_ENGINE_MFMA && e <= FIC_ENGINE_MFMA_F16; }
+bool engine_ok(int e) { return e >= FIC_ENGINE_MFMA && e <= FIC_ENGINE_MFMA_F16_16X16; }
 
 // The engine that searches a level of block size B: the matrix engine
-// measured fastest per block size for MFMA (f16 at B = 2 and 4, where it
-// needs no replicated operands; int8 hi/lo planes at B = 8 and 16), FP32
-// where the requested matrix engine has no form.
+// measured fastest per block size for MFMA (f16 32x32 tiles at B = 2 and 4,
+// where it needs no replicated operands; f16 16x16 tiles at B = 8; int8 hi/lo
+// planes at B = 16), FP32 where the requested matrix engine has no form.
 int engine_for(int engine, int B) {
-    if (engine == FIC_ENGINE_MFMA) return (B == 2 || B == 4) ? E_F16 : mfma_supported(B) ? E_I8 : E_FP32;
+    if (engine == FIC_ENGINE_MFMA)
+        return (B == 2 || B == 4) ? E_F16 : B == 8 ? E_H16 : mfma_supported(B) ? E_I8 : E_FP32;
     if (engine == FIC_ENGINE_MFMA_I8) return mfma_supported(B) ? E_I8 : E_FP32;
     if (engine == FIC_ENGINE_MFMA_F16) return f16_supported(B) ? E_F16 : E_FP32;
+    if (engine == FIC_ENGINE_MFMA_F16_16X16) return (B == 8 || B == 16) ? E_H16 : E_FP32;
     return E_FP32;
 }
 
@@ -337,7 +339,8 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
             if (eng != E_FP32) {
                 // int8: A fragments per quad and half; f16: per quad (32 rows)
                 const bool f16 = eng == E_F16;
-                d.geo = f16 ? f16_geometry(d.B, d.range_cap, d.pool_cap) : mfma_geometry(d.B, d.range_cap, d.pool_cap);
+                d.geo = f16 ? f16_geometry(d.B, d.range_cap, d.pool_cap)
+                            : mfma_geometry(d.B, d.range_cap, d.pool_cap, eng == E_H16);
                 const int nquads = d.geo.nrg * (d.geo.rpw / 4);
                 const int tile = f16 ? kDomTile32 : kDomTile;
                 const int ntiles = cdiv(d.pool_cap, tile);
@@ -475,11 +478,11 @@ int run_search(fic_ctx *ctx, LevelPlan &pl, hipStream_t st) {
     mark(ctx, FIC_T_PREP, b.B, st);
     FIC_TRY(launch_range_info_b(b, st));
     if (b.eng == E_F16) FIC_TRY(launch_f16_prep_b(b, st));
-    else if (b.eng == E_I8) FIC_TRY(launch_mfma_prep_b(b, st));
+    else if (b.eng == E_I8 || b.eng == E_H16) FIC_TRY(launch_mfma_prep_b(b, st));
     else FIC_TRY(launch_fp32_prep_b(b, st));
     mark(ctx, FIC_T_SEARCH, b.B, st);
     if (b.eng == E_F16) FIC_TRY(launch_f16_search_b(b, st));
-    else if (b.eng == E_I8) FIC_TRY(launch_mfma_search_b(b, st));
+    else if (b.eng == E_I8 || b.eng == E_H16) FIC_TRY(launch_mfma_search_b(b, st));
     else FIC_TRY(launch_fp32_search_b(b, st));
     mark(ctx, FIC_T_FINAL, b.B, st);
     FIC_TRY(launch_finalize_b(b, st));
@@ -726,7 +729,8 @@ int fic_validate_params(const fic_params *p, int32_t width, int32_t height) {
 int fic_level_engine(int32_t engine, int32_t B) {
     if (!engine_ok(engine) || B < 2 || B > 32 || !pow2(B)) return FIC_E_INVALID;
     const int e = engine_for(engine, B);
-    return e == E_F16 ? FIC_ENGINE_MFMA_F16 : e == E_I8 ? FIC_ENGINE_MFMA_I8 : FIC_ENGINE_FP32;
+    return e == E_F16 ? FIC_ENGINE_MFMA_F16 : e == E_I8 ? FIC_ENGINE_MFMA_I8
+         : e == E_H16 ? FIC_ENGINE_MFMA_F16_16X16 : FIC_ENGINE_FP32;
 }
 
 int fic_query_capacity(const fic_params *p, int32_t width, int32_t height, int64_t *pool_cap, int64_t *range_cap) {

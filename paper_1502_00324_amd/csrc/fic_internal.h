@@ -134,7 +134,7 @@ struct MfmaGeom {
     int nslot;    // partial results per range
     int nwg;      // workgroups
 };
-MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap);   // int8 engine
+MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, bool f16);   // 16-row engine (int8 or f16 form)
 MfmaGeom f16_geometry(int B, int range_cap, int pool_cap);    // f16 engine
 void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt);
 
@@ -162,7 +162,7 @@ __device__ inline void chunk_walk(const MfmaGeom &geo, int lb, int &rg, int &cfi
 // state below, and a launch of kind k gives image i the workgroups
 // [pre[k][i], pre[k][i+1]) (found by binary search on the prefix table).
 // Search engine of a level: every image of a level uses the same one.
-enum Engine { E_FP32 = 0, E_I8 = 1, E_F16 = 2 };
+enum Engine { E_FP32 = 0, E_I8 = 1, E_F16 = 2, E_H16 = 3 };
 
 enum Kind {
     K_LEVEL0, K_KEYS, K_HIST, K_PCMP, K_MOM, K_RANGE, K_AFRAG, K_BFRAG, K_VIEWS, K_DOMS, K_SEARCH, K_FINAL,

@@ -10,8 +10,13 @@
 //   planes (pl = 2, K = 2B^2): D4 - 512 = 4 hi + lo with hi = floor(D4/4) - 128
 //       and lo = D4 mod 4; rows hold the range once per decimated position,
 //       the hi and lo planes are contracted separately and C' = 4 C_hi + C_lo.
-// The planes form does half the MFMA work and moves half the domain bytes;
-// it needs B^2 >= 64, so B = 4 keeps the raw form.
+//   f16 (pl = 3, K = B^2, v_mfma_f32_16x16x32_f16): the range minus 128 and
+//       D4 - 512 as f16 (exact: integers below 2^11), f32 accumulation exact
+//       (every partial sum an integer of magnitude <= B^2 2^16 <= 2^24); the
+//       accumulators are floats, so the epilogue needs no conversion or
+//       combination.  Same 16-row layout as the int8 forms.
+// The planes form does half the MFMA work of the raw form and moves half the
+// domain bytes; planes and f16 need B^2 >= 64, so B = 4 keeps the raw form.
 //
 // Fragment layouts (16 bytes per lane, 64 lanes per 1 KiB fragment, verified
 // for this instruction: lane L feeds A row L%16 and B column L%16 with the
@@ -22,7 +27,9 @@
 //   B: tile of 16 domains, K-step s < kt:         bfrag[(tile*kt + s)*64 + L]
 //      planes form: steps [0, ka) hold hi, [ka, 2 ka) hold lo
 //   K index k = 64 s + 16 (L/16) + byte -> raw pixel (k / 2B, k % 2B), or
-//   decimated position (k / B, k % B) in the planes form.
+//   decimated position (k / B, k % B) in the planes form; f16 form: 8 halves
+//   per lane, k = 32 s + 8 (L/16) + e -> decimated position (k / B, k % B)
+//   (the same row/column/result layout, checked for this instruction).
 // With rows arranged this way the two halves give each lane all 8 isometries
 // of one (range, domain) pair, so the isometry max stays in registers.
 #include <stdio.h>
@@ -34,27 +41,38 @@
 namespace fic {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ h8v as_h8(const v4i &x) {
+    h8v h;
+    __builtin_memcpy(&h, &x, sizeof(h));
+    return h;
+}
 
 bool mfma_supported(int B) { return B == 4 || B == 8 || B == 16; }
 
 // Operand form (pl), range quads per wave (RQ), domain tiles per LDS stage
 // (DT) and the occupancy the register allocation aims at (waves per SIMD).
-// Each range size has a measured default (its first entry);
-// FIC_MFMA_SHAPE="pl,rq,dt,wpe" selects another compiled shape (used to tune).
+// Each range size and form class (int8: pl 1 or 2; f16: pl 3) has a measured
+// default (its first entry); FIC_MFMA_SHAPE="pl,rq,dt,wpe" selects another
+// compiled shape of the same class (used to tune).
 struct Shape { int B, pl, rq, dt, wpe; };
 static const Shape kShapes[] = {
     {4, 1, 2, 16, 3}, {4, 1, 1, 16, 3}, {4, 1, 4, 16, 2},
     {8, 2, 2, 8, 3}, {8, 2, 2, 16, 2}, {8, 2, 1, 8, 4}, {8, 2, 3, 8, 2}, {8, 2, 4, 8, 2}, {8, 1, 2, 8, 2},
     {16, 2, 2, 1, 3}, {16, 2, 2, 1, 2}, {16, 2, 1, 2, 3}, {16, 2, 2, 2, 2}, {16, 2, 1, 1, 4}, {16, 1, 1, 1, 2},
+    {8, 3, 2, 8, 3}, {8, 3, 1, 8, 4}, {8, 3, 2, 16, 2}, {8, 3, 3, 8, 2}, {8, 3, 4, 8, 2},
+    {16, 3, 1, 2, 3}, {16, 3, 2, 1, 2}, {16, 3, 1, 1, 4}, {16, 3, 2, 2, 2},
 };
-static Shape mfma_shape(int B) {
+static Shape mfma_shape(int B, bool f16) {
     const char *e = getenv("FIC_MFMA_SHAPE");
     int pl = 0, rq = 0, dt = 0, wpe = 0;
     if (e && sscanf(e, "%d,%d,%d,%d", &pl, &rq, &dt, &wpe) == 4)
         for (const Shape &s : kShapes)
-            if (s.B == B && s.pl == pl && s.rq == rq && s.dt == dt && s.wpe == wpe) return s;
+            if (s.B == B && (s.pl == 3) == f16 && s.pl == pl && s.rq == rq && s.dt == dt && s.wpe == wpe) return s;
     for (const Shape &s : kShapes)
-        if (s.B == B) return s;
+        if (s.B == B && (s.pl == 3) == f16) return s;
     return Shape{B, 1, 1, 1, 1};
 }
 
@@ -109,12 +127,12 @@ void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt) 
     g.nwg = g.nrg * g.nslot;
 }
 
-MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap) {
+MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, bool f16) {
     MfmaGeom g;
-    const Shape sh = mfma_shape(B);
+    const Shape sh = mfma_shape(B, f16);
     g.pl = sh.pl;
-    g.ka = sh.pl == 2 ? B * B / 64 : B * B / 16;
-    g.kt = g.ka * sh.pl;
+    g.ka = sh.pl == 2 ? B * B / 64 : sh.pl == 3 ? B * B / 32 : B * B / 16;
+    g.kt = sh.pl == 2 ? 2 * g.ka : g.ka;
     g.rpw = 16 * sh.rq;
     const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
     split_chunks(g, range_cap, ntiles, g.kt, sh.dt);
@@ -126,7 +144,7 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
     const int *pre = b.pre + K_AFRAG * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int B = d.B, KA = d.geo.ka, planes = d.geo.pl == 2;
+    const int B = d.B, KA = d.geo.ka, planes = d.geo.pl == 2, f16 = d.geo.pl == 3;
     const int nquads = d.geo.nrg * (d.geo.rpw / 4);
     const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
     if (slot >= nquads * 2 * KA * 64) return;
@@ -139,7 +157,21 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
     const int t = 4 * h + (i & 3);
     const int r = q * 4 + (i >> 2);
     uint32_t w[4] = {0u, 0u, 0u, 0u};
-    if (r < min(*d.nr, d.range_cap)) {
+    if (f16 && r < min(*d.nr, d.range_cap)) {
+        const uint32_t v = d.rxy[r];
+        const int x0 = v & 0xffff, y0 = v >> 16;
+        const int ti = iso_inv(t);
+        h8v hv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 32 * s + 8 * kg + e;
+            const int cy = k / B, cx = k - cy * B;
+            int sy, sx;
+            iso_src(ti, B, cy, cx, sy, sx);
+            hv[e] = (_Float16)((int)d.pix[(size_t)(y0 + sy) * d.pitch + x0 + sx] - 128);
+        }
+        __builtin_memcpy(w, &hv, sizeof(w));
+    } else if (r < min(*d.nr, d.range_cap)) {
         const uint32_t v = d.rxy[r];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int ti = iso_inv(t), D = 2 * B;
@@ -167,7 +199,7 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     const int *pre = b.pre + K_BFRAG * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int B = d.B, KA = d.geo.ka, KT = d.geo.kt, planes = d.geo.pl == 2;
+    const int B = d.B, KA = d.geo.ka, KT = d.geo.kt, planes = d.geo.pl == 2, f16 = d.geo.pl == 3;
     const int ntiles = (d.pool_cap + kDomTile - 1) / kDomTile;
     const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
     if (slot >= ntiles * KT * 64) return;
@@ -178,7 +210,19 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     const int p = tile * kDomTile + j;
     const bool valid = p < min(*d.pcount, d.pool_cap);
     uint32_t w[4] = {0u, 0u, 0u, 0u};
-    if (valid) {
+    if (valid && f16) {
+        const uint32_t v = d.pxy[p];
+        const int x0 = v & 0xffff, y0 = v >> 16, pitch = d.pitch;
+        h8v hv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 32 * s + 8 * kg + e;
+            const int cy = k / B, cx = k - cy * B;
+            const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
+            hv[e] = (_Float16)(q[0] + q[1] + q[pitch] + q[pitch + 1] - 512);
+        }
+        __builtin_memcpy(w, &hv, sizeof(w));
+    } else if (valid) {
         const uint32_t v = d.pxy[p];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int D = 2 * B, pitch = d.pitch;
@@ -211,9 +255,14 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
 // of domain tiles.  Domain fragments go global -> registers -> LDS in stages
 // of DT tiles, double-buffered: the loads for stage s+1 are issued before the
 // MFMAs of stage s and written to the other LDS buffer after them.
+template <int PL> struct AccOf { typedef v4i type; };   // int32 accumulators
+template <> struct AccOf<3> { typedef v4f type; };      // f16 form: f32 accumulators
+
 template <int KA, int PL, int RQ, int DT, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_mfma_search(BatchDev bt, SSet ss) {
-    constexpr int KB = KA * PL;                  // K-steps of a domain tile
+    typedef typename AccOf<PL>::type Acc;
+    constexpr int NP = PL == 2 ? 2 : 1;          // accumulator planes
+    constexpr int KB = KA * NP;                  // K-steps of a domain tile
     // share range bests across workgroups only when a stage is long enough
     // (>= 4 tiles) to hide the coherent load of the shared values
     constexpr bool SHARE = DT >= 4;
@@ -307,7 +356,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     };
     // acc[qi][h][plane]: the planes are combined (4 hi + lo) at the test,
     // one tile later, so no MFMA result is waited for at issue time
-    auto mfma_tile = [&](v4i (&acc)[RQ][2][PL], int buf, int dt) {
+    auto mfma_tile = [&](Acc (&acc)[RQ][2][NP], int buf, int dt) {
         v4i Bf[KB];
 #pragma unroll
         for (int s = 0; s < KB; ++s) {
@@ -317,21 +366,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
         for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
-            for (int pl = 0; pl < PL; ++pl) acc[qi][0][pl] = acc[qi][1][pl] = v4i{0, 0, 0, 0};
+            for (int pl = 0; pl < NP; ++pl) acc[qi][0][pl] = acc[qi][1][pl] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KA; ++s)
 #pragma unroll
-            for (int pl = 0; pl < PL; ++pl)
+            for (int pl = 0; pl < NP; ++pl)
 #pragma unroll
                 for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
-                    for (int h = 0; h < 2; ++h)
-                        acc[qi][h][pl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][h][s], Bf[pl * KA + s],
-                                                                               acc[qi][h][pl], 0, 0, 0);
+                    for (int h = 0; h < 2; ++h) {
+                        if constexpr (PL == 3)
+                            acc[qi][h][pl] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(A[qi][h][s]), as_h8(Bf[s]),
+                                                                                    acc[qi][h][pl], 0, 0, 0);
+                        else
+                            acc[qi][h][pl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][h][s], Bf[pl * KA + s],
+                                                                                   acc[qi][h][pl], 0, 0, 0);
+                    }
     };
-    auto cprime = [&](const v4i (&a)[PL]) -> v4i {
+    auto cprime = [&](const v4i (&a)[NP]) -> v4i {
         if constexpr (PL == 2) return (a[0] << 2) + a[1];
         else return a[0];
+    };
+    // the largest C' over the 8 isometries of each lane's pair; in the f16
+    // form the f32 accumulators hold exact integers
+    auto cmax = [&](const Acc (&x)[NP], const Acc (&y)[NP]) -> int {
+        if constexpr (PL == 3) {
+            return (int)max8f(x[0].x, x[0].y, x[0].z, x[0].w, y[0].x, y[0].y, y[0].z, y[0].w);
+        } else {
+            const v4i cx = cprime(x), cy = cprime(y);
+            return max8(cx.x, cx.y, cx.z, cx.w, cy.x, cy.y, cy.z, cy.w);
+        }
     };
   for (int cj = 0; cj < ncs; ++cj) {
     const int chunk = cfirst + cj * cstep;
@@ -355,7 +419,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             const int tbase = t0 + stg * DT;
             // software pipeline: the MFMAs of tile dt+1 are issued before the
             // prune test of tile dt, in the same basic block
-            v4i acc[2][RQ][2][PL];
+            Acc acc[2][RQ][2][NP];
             mfma_tile(acc[0], buf, 0);
 #pragma unroll
             for (int dt = 0; dt < DT; ++dt) {
@@ -367,8 +431,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 int mx[RQ];
 #pragma unroll
                 for (int qi = 0; qi < RQ; ++qi) {
-                    const v4i cx = cprime(acc[cur][qi][0]), cy = cprime(acc[cur][qi][1]);
-                    mx[qi] = max8(cx.x, cx.y, cx.z, cx.w, cy.x, cy.y, cy.z, cy.w);
+                    mx[qi] = cmax(acc[cur][qi][0], acc[cur][qi][1]);
                     const float rhs = fmaf(tn[qi], di.y, fmaf(-bn[qi], di.x, -an[qi]));
                     // false on NaN: rows past the ranges, domains past the
                     // pool or the chunk, and ranges already at val 0
@@ -441,7 +504,7 @@ static hipError_t launch_search_t(const BatchHost &b, hipStream_t st) {
 hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
     if (b.blocks[K_SEARCH] == 0) return hipSuccess;
     const int B = b.B;
-    const Shape sh = mfma_shape(B);
+    const Shape sh = mfma_shape(B, b.eng == E_H16);
 #define FIC_SEARCH(KA, PL, RQ, DT, WPE) \
     if (sh.pl == PL && sh.rq == RQ && sh.dt == DT && sh.wpe == WPE) return launch_search_t<KA, PL, RQ, DT, WPE>(b, st)
     if (B == 4) {
@@ -455,6 +518,11 @@ hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
         FIC_SEARCH(1, 2, 3, 8, 2);
         FIC_SEARCH(1, 2, 4, 8, 2);
         FIC_SEARCH(4, 1, 2, 8, 2);
+        FIC_SEARCH(2, 3, 2, 8, 3);
+        FIC_SEARCH(2, 3, 1, 8, 4);
+        FIC_SEARCH(2, 3, 2, 16, 2);
+        FIC_SEARCH(2, 3, 3, 8, 2);
+        FIC_SEARCH(2, 3, 4, 8, 2);
     } else if (B == 16) {
         FIC_SEARCH(4, 2, 2, 1, 3);
         FIC_SEARCH(4, 2, 2, 1, 2);
@@ -462,6 +530,10 @@ hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
         FIC_SEARCH(4, 2, 2, 2, 2);
         FIC_SEARCH(4, 2, 1, 1, 4);
         FIC_SEARCH(16, 1, 1, 1, 2);
+        FIC_SEARCH(8, 3, 1, 2, 3);
+        FIC_SEARCH(8, 3, 2, 1, 2);
+        FIC_SEARCH(8, 3, 1, 1, 4);
+        FIC_SEARCH(8, 3, 2, 2, 2);
     }
 #undef FIC_SEARCH
     return hipErrorInvalidValue;

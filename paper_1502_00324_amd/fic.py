@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfic.so")
 
 FIC_OK, FIC_E_INVALID, FIC_E_NOMEM, FIC_E_HIP, FIC_E_CAPACITY, FIC_E_ARCH = 0, -1, -2, -3, -4, -5
-ENGINE_MFMA, ENGINE_FP32, ENGINE_MFMA_I8, ENGINE_MFMA_F16 = 0, 1, 2, 3
+ENGINE_MFMA, ENGINE_FP32, ENGINE_MFMA_I8, ENGINE_MFMA_F16, ENGINE_MFMA_F16_16X16 = 0, 1, 2, 3, 4
 POOL_ENTROPY, POOL_VARIANCE = 0, 1
 MAX_LEVELS, MAX_S = 4, 32
 

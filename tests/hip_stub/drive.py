@@ -10,6 +10,7 @@ relies on it).  Prints one JSON object with the results of each scenario.
 import ctypes
 import json
 import os
+import re
 import sys
 
 import numpy as np
@@ -39,7 +40,7 @@ class BatchDev(ctypes.Structure):
 
 
 HOOK = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_uint, ctypes.c_uint, ctypes.POINTER(ctypes.c_void_p))
-log = {"launches": [], "errors": []}
+log = {"launches": [], "errors": [], "forms": []}
 
 
 def on_launch(name, grid, block, args):
@@ -64,6 +65,10 @@ def on_launch(name, grid, block, args):
         want = pre[kind, n]
         if short == "k_finalize":
             want = max(1, want)
+        if short == "k_mfma_search":
+            # operand form: the second template argument of the mangled name
+            m = re.search(r"k_mfma_searchILi(\d+)ELi(\d+)E", name)
+            log["forms"].append(int(m.group(2)) if m else -1)
         if short in ("k_mfma_search", "k_f16_search") and (pre[kind] % 8 != 0).any():
             log["errors"].append("%s: an image's workgroups do not start on a multiple of 8" % short)
     if grid != want:
@@ -126,11 +131,13 @@ def main():
     out = {}
 
     def scenario(name, fn):
-        log["launches"], log["errors"] = [], []
+        log["launches"], log["errors"], log["forms"] = [], [], []
         st = fn()
-        out[name] = {"status": st, "errors": list(log["errors"]), "launches": list(log["launches"])}
+        out[name] = {"status": st, "errors": list(log["errors"]), "launches": list(log["launches"]),
+                     "forms": list(log["forms"])}
 
     M, F, I8, H = fic.ENGINE_MFMA, fic.ENGINE_FP32, fic.ENGINE_MFMA_I8, fic.ENGINE_MFMA_F16
+    X = fic.ENGINE_MFMA_F16_16X16
     mixed = [(128, 128), (256, 128), (64, 128), (1024, 512), (96, 96), (512, 512), (32, 32), (208, 144)]
     scenario("single_mfma", lambda: encode_case(L, h, [(64, 64)], [(8, 1), (4, 1)], M))
     scenario("single_fp32", lambda: encode_case(L, h, [(64, 64)], [(8, 1), (4, 1)], F))
@@ -138,6 +145,7 @@ def main():
     scenario("mixed_fp32_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], F))
     scenario("mixed_i8_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], I8))
     scenario("mixed_f16_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], H))
+    scenario("mixed_f16x_3lv", lambda: encode_case(L, h, mixed, [(16, 2), (8, 2), (4, 2)], X))
     scenario("mixed_b32_4lv", lambda: encode_case(L, h, [(256, 256), (128, 64), (64, 64)],
                                                   [(32, 4), (16, 4), (8, 4), (4, 4)], M))
     scenario("paper_b2_cap", lambda: encode_case(L, h, [(64, 64), (32, 48)], [(16, 4), (8, 4), (4, 4), (2, 4)], M,

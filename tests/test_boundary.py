@@ -73,7 +73,7 @@ BAD = [
     ("rms_den0", lambda p: p.split_rms.__setitem__(0, fic.Ratio(8, 0))),
     ("rms_den17", lambda p: p.split_rms.__setitem__(0, fic.Ratio(8, 17))),
     ("rms_neg", lambda p: p.split_rms.__setitem__(0, fic.Ratio(-1, 1))),
-    ("engine4", lambda p: setattr(p, "engine", 4)),
+    ("engine5", lambda p: setattr(p, "engine", 5)),
     ("pool_key2", lambda p: setattr(p, "pool_key", 2)),
     ("pool_key_neg", lambda p: setattr(p, "pool_key", -1)),
     ("engine_neg", lambda p: setattr(p, "engine", -1)),
@@ -129,10 +129,12 @@ def test_ctx_create_reports_missing_device():
 
 def test_level_engine_resolution():
     M, F, I8, H = fic.ENGINE_MFMA, fic.ENGINE_FP32, fic.ENGINE_MFMA_I8, fic.ENGINE_MFMA_F16
-    assert [fic.level_engine(M, B) for B in (2, 4, 8, 16, 32)] == [H, H, I8, I8, F]
+    X = fic.ENGINE_MFMA_F16_16X16
+    assert [fic.level_engine(M, B) for B in (2, 4, 8, 16, 32)] == [H, H, X, I8, F]
     assert [fic.level_engine(I8, B) for B in (2, 4, 8, 16, 32)] == [F, I8, I8, I8, F]
     assert [fic.level_engine(H, B) for B in (2, 4, 8, 16, 32)] == [H, H, H, H, F]
+    assert [fic.level_engine(X, B) for B in (2, 4, 8, 16, 32)] == [F, F, X, X, F]
     assert all(fic.level_engine(F, B) == F for B in (2, 4, 8, 16, 32))
-    assert fic.lib().fic_level_engine(4, 8) == fic.FIC_E_INVALID
+    assert fic.lib().fic_level_engine(5, 8) == fic.FIC_E_INVALID
     assert fic.lib().fic_level_engine(M, 12) == fic.FIC_E_INVALID
     assert fic.lib().fic_level_engine(M, 64) == fic.FIC_E_INVALID

@@ -16,8 +16,8 @@ from paper_1502_00324_amd.synth import make_image
 
 pytestmark = pytest.mark.gpu
 WORKERS = max(1, min(16, os.cpu_count() or 1))
-ENGINES = [fic.ENGINE_MFMA, fic.ENGINE_FP32, fic.ENGINE_MFMA_I8, fic.ENGINE_MFMA_F16]
-ENGINE_IDS = ["mfma", "fp32", "mfma_i8", "mfma_f16"]
+ENGINES = [fic.ENGINE_MFMA, fic.ENGINE_FP32, fic.ENGINE_MFMA_I8, fic.ENGINE_MFMA_F16, fic.ENGINE_MFMA_F16_16X16]
+ENGINE_IDS = ["mfma", "fp32", "mfma_i8", "mfma_f16", "mfma_f16_16x16"]
 
 
 @pytest.fixture(scope="module")

@@ -36,6 +36,7 @@ def runs(tmp_path_factory):
 
 
 SCENARIOS = ["single_mfma", "single_fp32", "mixed_mfma_3lv", "mixed_fp32_3lv", "mixed_i8_3lv", "mixed_f16_3lv",
+             "mixed_f16x_3lv",
              "mixed_b32_4lv", "large_uncapped", "large_capped",
              "paper_b2_cap", "min_images", "timing_toggle"]
 
@@ -74,11 +75,18 @@ def test_integral_images_once_per_encode(runs):
 def test_engine_choice(runs):
     m, f = kinds(runs["mixed_mfma_3lv"]), kinds(runs["mixed_fp32_3lv"])
     i8, h = kinds(runs["mixed_i8_3lv"]), kinds(runs["mixed_f16_3lv"])
-    # default: f16 at B=4, int8 at B=8 and 16
+    # default: f16 32x32 tiles at B=4, f16 16x16 tiles at B=8, int8 planes at B=16
     assert "k_fp32_search" not in m and m.count("k_f16_search") == 2 and m.count("k_mfma_search") == 4
+    assert runs["mixed_mfma_3lv"]["forms"] == [2, 3] * 2
     assert "k_mfma_search" not in f and "k_f16_search" not in f
     assert i8.count("k_mfma_search") == 2 * 3 and "k_f16_search" not in i8
     assert h.count("k_f16_search") == 2 * 3 and "k_mfma_search" not in h
+    # the int8 engine: raw form at B=4, hi/lo planes at 8 and 16; the f16
+    # 16x16 form at B=8 and 16 only (B=4 falls back to FP32)
+    assert runs["mixed_i8_3lv"]["forms"] == [2, 2, 1] * 2
+    x = kinds(runs["mixed_f16x_3lv"])
+    assert x.count("k_mfma_search") == 2 * 2 and x.count("k_fp32_search") == 2 and "k_f16_search" not in x
+    assert runs["mixed_f16x_3lv"]["forms"] == [3, 3] * 2
     # B=32 levels take the FP32 engine even when MFMA is asked for
     assert "k_fp32_search" in kinds(runs["mixed_b32_4lv"]) and "k_f16_search" in kinds(runs["mixed_b32_4lv"])
     assert "k_mfma_search" in kinds(runs["mixed_b32_4lv"])
