@@ -16,7 +16,6 @@ import ctypes
 import math
 import os
 import subprocess
-from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -29,7 +28,7 @@ def build(force: bool = False) -> str:
     """Compile fic_oracle.c with gcc into liboracle.so (in place)."""
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
         tmp = LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-Wall", "-Wextra",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-pthread", "-Wall", "-Wextra",
                                "-o", tmp, SRC_PATH], cwd=HERE)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -50,12 +49,12 @@ def lib():
         L.orc_entropy_key.argtypes = [P, i32, i32, i32, i32]
         L.orc_entropy_key.restype = i64
         L.orc_candidates.argtypes = [i32, i32, i32, i32, P, i32]
-        L.orc_build_pool.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, i32, i32, P, P, P, P, i32]
+        L.orc_build_pool.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, i32, i32, P, P, P, P, i32, i32]
         L.orc_variance_key.argtypes = [P, i32, i32, i32, i32]
         L.orc_variance_key.restype = i64
         L.orc_iso_source.argtypes = [i32, i32, i32, i32, P, P]
         L.orc_encode_level.argtypes = [P, i32, i32, i32, P, i32, P, i32, i32, P, i32, i32, i32, i32, i32,
-                                       P, P, P, P, P, P]
+                                       P, P, P, P, P, P, i32]
         L.orc_decode.argtypes = [i32, i32, i32] + [P] * 9 + [i32, P, P]
         _lib = L
     return _lib
@@ -99,9 +98,11 @@ def variance_key(img: np.ndarray, x: int, y: int, size: int) -> int:
     return lib().orc_variance_key(_p(img), img.shape[1], x, y, size)
 
 
-def build_pool(img: np.ndarray, B: int, L: int, pct=(0, 1), pool_max: int = 0, pool_key: str = "entropy") -> dict:
+def build_pool(img: np.ndarray, B: int, L: int, pct=(0, 1), pool_max: int = 0, pool_key: str = "entropy",
+               threads: int = 1) -> dict:
     """Sec. 3 Eq 5-6 (entropy key) or the variance key of the cited
-    alternative; the same percentile and DN rules for both."""
+    alternative; the same percentile and DN rules for both.  threads: the
+    candidate keys are split over that many threads (same values)."""
     img = np.ascontiguousarray(img, np.uint8)
     H, W = img.shape
     nd = lib().orc_candidates(W, H, B, L, None, 0)
@@ -112,7 +113,7 @@ def build_pool(img: np.ndarray, B: int, L: int, pct=(0, 1), pool_max: int = 0, p
     sum4 = np.zeros(nd, np.uint32)
     a = np.zeros(nd, np.int64)
     cnt = lib().orc_build_pool(_p(img), W, H, W, B, L, pct[0], pct[1], pool_max, POOL_KEYS[pool_key],
-                               _p(xy), _p(key), _p(sum4), _p(a), nd)
+                               _p(xy), _p(key), _p(sum4), _p(a), nd, max(1, min(64, int(threads))))
     if cnt < 0:
         raise ValueError("orc_build_pool failed: %d" % cnt)
     return {"xy": xy[:cnt].copy(), "key": key[:cnt].copy(), "sum4": sum4[:cnt].copy(), "a": a[:cnt].copy(),
@@ -148,22 +149,13 @@ def encode_level(img: np.ndarray, pool_xy: np.ndarray, ranges_xy: np.ndarray, B:
     if R == 0:
         return out
 
-    def run(lo, hi):
-        rs = ranges_xy[lo:hi]
-        o = {k: v[lo:hi] for k, v in out.items()}
-        st = lib().orc_encode_level(_p(img), W, H, W, _p(pool_xy), len(pool_xy), _p(rs), hi - lo, B,
-                                    _p(s_num), len(s_num), s_den, split_rms[0], split_rms[1], int(is_last),
-                                    *(_p(o[k]) for k in ("split", "domain", "iso", "s_idx", "offset", "err")))
-        if st != 0:
-            raise ValueError("orc_encode_level failed: %d" % st)
-
-    if workers <= 1 or R < 2 * workers:
-        run(0, R)
-    else:
-        # slices are views into out's arrays, so each shard writes its part in place
-        bounds = np.linspace(0, R, min(R, workers * 4) + 1).astype(int)
-        with ThreadPoolExecutor(workers) as ex:
-            list(ex.map(lambda i: run(bounds[i], bounds[i + 1]), range(len(bounds) - 1)))
+    # workers: threads in the C search, each over a slice of the ranges
+    st = lib().orc_encode_level(_p(img), W, H, W, _p(pool_xy), len(pool_xy), _p(ranges_xy), R, B,
+                                _p(s_num), len(s_num), s_den, split_rms[0], split_rms[1], int(is_last),
+                                *(_p(out[k]) for k in ("split", "domain", "iso", "s_idx", "offset", "err")),
+                                max(1, min(64, int(workers))))
+    if st != 0:
+        raise ValueError("orc_encode_level failed: %d" % st)
     return out
 
 
@@ -180,7 +172,7 @@ def encode(img: np.ndarray, levels, pct=(3, 10), pool_max: int = 0, s_num=None, 
     out = []
     ranges = level0_ranges(W, H, levels[0][0])
     for li, (B, L) in enumerate(levels):
-        pool = build_pool(img, B, L, pct, pool_max, pool_key)
+        pool = build_pool(img, B, L, pct, pool_max, pool_key, threads=workers)
         is_last = li == nl - 1
         codes = encode_level(img, pool["xy"], ranges, B, s_num_l[li], s_den_l[li],
                              rms_l[li] if rms_l[li] is not None else (0, 1), is_last, workers)

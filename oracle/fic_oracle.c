@@ -42,6 +42,7 @@
  * Eq 1 with the Eq 3 offset.  For den <= 1024 and B <= 32 every |term| is
  * below 1.2e18, so int64 holds val exactly.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -132,18 +133,40 @@ static void decimate(const uint8_t *img, int pitch, int x, int y, int B, int32_t
         }
 }
 
+/* Keys of candidates [lo, hi): independent per candidate, so the range may be
+ * split over threads without changing any value. */
+typedef struct {
+    const uint8_t *img;
+    int pitch, size, kind, lo, hi;
+    const uint32_t *cxy;
+    int64_t *g;
+} key_job;
+
+static void *key_range(void *arg)
+{
+    key_job *j = (key_job *)arg;
+    for (int i = j->lo; i < j->hi; ++i) {
+        int x = (int)(j->cxy[i] & 0xffff), y = (int)(j->cxy[i] >> 16);
+        j->g[i] = j->kind == 0 ? orc_entropy_key(j->img, j->pitch, x, y, j->size)
+                               : orc_variance_key(j->img, j->pitch, x, y, j->size);
+    }
+    return NULL;
+}
+
 /*
  * Domain pool for range size B (domains 2B x 2B) at step L.
  * drop fraction p = p_num/p_den of the candidates (lowest entropy first,
  * rank by nearest rank ceil(p*Nd)); pool_max > 0 caps the pool size.
  * Writes xy, key G, sum4 = sum of the raw pixels, a = n*sum(D4^2) - sum4^2.
+ * threads (1..64): the candidate keys are computed by that many threads.
  * Returns the pool size, or a negative status.
  */
 int orc_build_pool(const uint8_t *img, int W, int H, int pitch, int B, int L,
                    int p_num, int p_den, int pool_max, int key_kind,
-                   uint32_t *xy, int64_t *key, uint32_t *sum4, int64_t *a, int cap)
+                   uint32_t *xy, int64_t *key, uint32_t *sum4, int64_t *a, int cap, int threads)
 {
-    if (p_den < 1 || p_num < 0 || p_num >= p_den || pool_max < 0 || key_kind < 0 || key_kind > 1)
+    if (p_den < 1 || p_num < 0 || p_num >= p_den || pool_max < 0 || key_kind < 0 || key_kind > 1 ||
+        threads < 1 || threads > 64)
         return ORC_EINVAL;
     int nd = orc_candidates(W, H, B, L, NULL, 0);
     if (nd < 0) return nd;
@@ -158,12 +181,20 @@ int orc_build_pool(const uint8_t *img, int W, int H, int pitch, int B, int L,
         return ORC_ENOMEM;
     }
     orc_candidates(W, H, B, L, cxy, nd);
-    int64_t gmin = INT64_MAX;
-    for (int i = 0; i < nd; ++i) {
-        g[i] = key_kind == 0 ? orc_entropy_key(img, pitch, (int)(cxy[i] & 0xffff), (int)(cxy[i] >> 16), 2 * B)
-                             : orc_variance_key(img, pitch, (int)(cxy[i] & 0xffff), (int)(cxy[i] >> 16), 2 * B);
-        if (g[i] < gmin) gmin = g[i];
+    key_job jobs[64];
+    pthread_t tid[64];
+    int started[64] = {0};
+    for (int t = 0; t < threads; ++t) {
+        jobs[t] = (key_job){img, pitch, 2 * B, key_kind, (int)((int64_t)nd * t / threads),
+                            (int)((int64_t)nd * (t + 1) / threads), cxy, g};
+        if (t + 1 < threads) started[t] = pthread_create(&tid[t], NULL, key_range, &jobs[t]) == 0;
+        if (!started[t]) key_range(&jobs[t]);   /* the last part, or a thread that could not start */
     }
+    for (int t = 0; t + 1 < threads; ++t)
+        if (started[t]) pthread_join(tid[t], NULL);
+    int64_t gmin = INT64_MAX;
+    for (int i = 0; i < nd; ++i)
+        if (g[i] < gmin) gmin = g[i];
     /* c = ceil(p * Nd) lowest-entropy candidates (largest G) set the threshold */
     int64_t c = ((int64_t)p_num * nd + p_den - 1) / p_den;
     int count = 0;
@@ -229,12 +260,82 @@ void orc_iso_source(int t, int B, int y, int x, int *sy, int *sx)
     *sy = yy; *sx = xx;
 }
 
+/* Shared, read-only state of one quadtree step, and the slice of ranges
+ * [lo, hi) one thread searches (ranges are independent of each other). */
+typedef struct {
+    const uint8_t *img;
+    int pitch, P, B, S, tn, td, is_last, lo, hi, status;
+    const int32_t *dec, *perm, *s_num;
+    const int64_t *dsum, *da;
+    int64_t den;
+    const uint32_t *ranges_xy;
+    uint8_t *split, *iso, *s_idx, *offset;
+    uint32_t *domain;
+    int64_t *err;
+} level_job;
+
+static void *search_ranges(void *arg)
+{
+    level_job *j = (level_job *)arg;
+    const int B = j->B, n = B * B, P = j->P, S = j->S, pitch = j->pitch;
+    const int64_t den = j->den;
+    int32_t *r = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!r) { j->status = ORC_ENOMEM; return NULL; }
+    for (int ri = j->lo; ri < j->hi; ++ri) {
+        int rx = (int)(j->ranges_xy[ri] & 0xffff), ry = (int)(j->ranges_xy[ri] >> 16);
+        int64_t sr = 0, srr = 0;
+        for (int y = 0; y < B; ++y)
+            for (int x = 0; x < B; ++x) {
+                int v = j->img[(size_t)(ry + y) * pitch + rx + x];
+                r[y * B + x] = v;
+                sr += v;
+                srr += (int64_t)v * v;
+            }
+        int64_t cr = (int64_t)n * srr - sr * sr;
+        int64_t o = (2 * sr + n) / (2 * n);
+        int64_t best = INT64_MAX;
+        int bp = 0, bt = 0, bk = 0;
+        for (int p = 0; p < P; ++p) {
+            const int32_t *d = j->dec + (size_t)p * n;
+            for (int t = 0; t < 8; ++t) {
+                const int32_t *pm = j->perm + t * n;
+                int64_t x4 = 0;
+                for (int i = 0; i < n; ++i) x4 += (int64_t)r[i] * d[pm[i]];
+                int64_t bx = (int64_t)n * x4 - sr * j->dsum[p];
+                for (int k = 0; k < S; ++k) {
+                    int64_t num = j->s_num[k];
+                    int64_t val = num * num * j->da[p] - 8 * num * den * bx + 16 * den * den * cr;
+                    if (val < best) { best = val; bp = p; bt = t; bk = k; }
+                }
+            }
+        }
+        int64_t dq = (int64_t)n * o - sr;
+        int64_t valq = best + 16 * den * den * dq * dq;
+        int sp = 0;
+        if (!j->is_last) {
+            __int128 lhs = (__int128)valq * j->td * j->td;
+            __int128 rhs = (__int128)16 * den * den * n * n * j->tn * j->tn;
+            sp = lhs > rhs;
+        }
+        j->split[ri] = (uint8_t)sp;
+        j->domain[ri] = (uint32_t)bp;
+        j->iso[ri] = (uint8_t)bt;
+        j->s_idx[ri] = (uint8_t)bk;
+        j->offset[ri] = (uint8_t)o;
+        j->err[ri] = valq;
+    }
+    free(r);
+    return NULL;
+}
+
 /*
  * One quadtree step: search every range of ranges_xy (B x B, top-left xy)
  * against every pool domain (2B x 2B at pool_xy), all 8 isometries and all
  * s = s_num[k]/s_den.  Outputs per range: best domain index, isometry,
  * s index, stored offset O, val_q = 16*den^2*n*E_q (error with the stored
  * O) and the split flag.  Split iff !is_last and RMS(E_q) > tn/td.
+ * threads (1..64): the ranges are split over that many threads, which share
+ * the decimated pool.
  */
 int orc_encode_level(const uint8_t *img, int W, int H, int pitch,
                      const uint32_t *pool_xy, int P,
@@ -242,10 +343,10 @@ int orc_encode_level(const uint8_t *img, int W, int H, int pitch,
                      const int32_t *s_num, int S, int s_den,
                      int tn, int td, int is_last,
                      uint8_t *split, uint32_t *domain, uint8_t *iso, uint8_t *s_idx,
-                     uint8_t *offset, int64_t *err)
+                     uint8_t *offset, int64_t *err, int threads)
 {
     if (B < 1 || B > 32 || P < 1 || R < 0 || S < 1 || S > 32 || s_den < 1 || s_den > 1024 ||
-        td < 1 || tn < 0)
+        td < 1 || tn < 0 || threads < 1 || threads > 64)
         return ORC_EINVAL;
     for (int k = 0; k < S; ++k)
         if (s_num[k] < 0 || s_num[k] > s_den || (k > 0 && s_num[k] <= s_num[k - 1])) return ORC_EINVAL;
@@ -255,9 +356,8 @@ int orc_encode_level(const uint8_t *img, int W, int H, int pitch,
     int64_t *dsum = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);
     int64_t *da = (int64_t *)malloc(sizeof(int64_t) * (size_t)P);
     int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * 8 * (size_t)n);
-    int32_t *r = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    if (!dec || !dsum || !da || !perm || !r) {
-        free(dec); free(dsum); free(da); free(perm); free(r);
+    if (!dec || !dsum || !da || !perm) {
+        free(dec); free(dsum); free(da); free(perm);
         return ORC_ENOMEM;
     }
     for (int p = 0; p < P; ++p) {
@@ -275,52 +375,24 @@ int orc_encode_level(const uint8_t *img, int W, int H, int pitch,
                 orc_iso_source(t, B, y, x, &sy, &sx);
                 perm[t * n + y * B + x] = sy * B + sx;
             }
-    const int64_t den = s_den;
-    for (int ri = 0; ri < R; ++ri) {
-        int rx = (int)(ranges_xy[ri] & 0xffff), ry = (int)(ranges_xy[ri] >> 16);
-        int64_t sr = 0, srr = 0;
-        for (int y = 0; y < B; ++y)
-            for (int x = 0; x < B; ++x) {
-                int v = img[(size_t)(ry + y) * pitch + rx + x];
-                r[y * B + x] = v;
-                sr += v;
-                srr += (int64_t)v * v;
-            }
-        int64_t cr = (int64_t)n * srr - sr * sr;
-        int64_t o = (2 * sr + n) / (2 * n);
-        int64_t best = INT64_MAX;
-        int bp = 0, bt = 0, bk = 0;
-        for (int p = 0; p < P; ++p) {
-            const int32_t *d = dec + (size_t)p * n;
-            for (int t = 0; t < 8; ++t) {
-                const int32_t *pm = perm + t * n;
-                int64_t x4 = 0;
-                for (int i = 0; i < n; ++i) x4 += (int64_t)r[i] * d[pm[i]];
-                int64_t bx = (int64_t)n * x4 - sr * dsum[p];
-                for (int k = 0; k < S; ++k) {
-                    int64_t num = s_num[k];
-                    int64_t val = num * num * da[p] - 8 * num * den * bx + 16 * den * den * cr;
-                    if (val < best) { best = val; bp = p; bt = t; bk = k; }
-                }
-            }
-        }
-        int64_t dq = (int64_t)n * o - sr;
-        int64_t valq = best + 16 * den * den * dq * dq;
-        int sp = 0;
-        if (!is_last) {
-            __int128 lhs = (__int128)valq * td * td;
-            __int128 rhs = (__int128)16 * den * den * n * n * tn * tn;
-            sp = lhs > rhs;
-        }
-        split[ri] = (uint8_t)sp;
-        domain[ri] = (uint32_t)bp;
-        iso[ri] = (uint8_t)bt;
-        s_idx[ri] = (uint8_t)bk;
-        offset[ri] = (uint8_t)o;
-        err[ri] = valq;
+    if (threads > R) threads = R > 0 ? R : 1;
+    level_job jobs[64];
+    pthread_t tid[64];
+    int started[64] = {0};
+    for (int t = 0; t < threads; ++t) {
+        jobs[t] = (level_job){img, pitch, P, B, S, tn, td, is_last, (int)((int64_t)R * t / threads),
+                              (int)((int64_t)R * (t + 1) / threads), ORC_OK, dec, perm, s_num, dsum, da,
+                              (int64_t)s_den, ranges_xy, split, iso, s_idx, offset, domain, err};
+        if (t + 1 < threads) started[t] = pthread_create(&tid[t], NULL, search_ranges, &jobs[t]) == 0;
+        if (!started[t]) search_ranges(&jobs[t]);
     }
-    free(dec); free(dsum); free(da); free(perm); free(r);
-    return ORC_OK;
+    int status = ORC_OK;
+    for (int t = 0; t < threads; ++t) {
+        if (t + 1 < threads && started[t]) pthread_join(tid[t], NULL);
+        if (jobs[t].status != ORC_OK) status = jobs[t].status;
+    }
+    free(dec); free(dsum); free(da); free(perm);
+    return status;
 }
 
 static int64_t floor_div(int64_t a, int64_t b) /* b > 0 */
