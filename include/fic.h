@@ -48,7 +48,8 @@ extern "C" {
 enum {
     FIC_OK = 0,
     FIC_E_INVALID = -1,   /* bad argument (see fic_validate_params) */
-    FIC_E_NOMEM = -2,     /* scratch allocation failed or exceeds the ctx limit */
+    FIC_E_NOMEM = -2,     /* scratch allocation failed or exceeds the ctx limit, or a
+                             launch would need 2^31 or more workgroups */
     FIC_E_HIP = -3,       /* a HIP runtime call failed (no device, launch error) */
     FIC_E_CAPACITY = -4,  /* a caller buffer is smaller than the worst case */
     FIC_E_ARCH = -5       /* the device is not gfx950 */
@@ -56,11 +57,11 @@ enum {
 
 /* Search engines; all give identical codes.
  *   MFMA:     matrix cores, the faster form per block size: MFMA_F16 at
- *             B = 2 and 4, MFMA_F16_16X16 at B = 8, MFMA_I8 at B = 16;
- *             FP32 for B = 32.
+ *             B = 2 and 4, MFMA_F16_16X16 at B = 8, MFMA_I8 at B = 16
+ *             and 32.
  *   FP32:     plain vector FP32 with the same exact epilogue (baseline).
- *   MFMA_I8:  int8 matrix cores for B = 4, 8, 16 (raw pixels at B = 4,
- *             decimated hi/lo planes above); FP32 elsewhere.
+ *   MFMA_I8:  int8 matrix cores for B = 4, 8, 16, 32 (raw pixels at B = 4,
+ *             decimated hi/lo planes above); FP32 at B = 2.
  *   MFMA_F16: f16 matrix cores with exact f32 accumulation over the B^2
  *             decimated positions for B = 2 (zero-padded to 16), 4, 8, 16;
  *             FP32 at B = 32 (32 x 32 result tiles).

@@ -156,7 +156,9 @@ bool engine_ok(int e) { return e >= FIC_ENGINE_MFMA && e <= FIC_ENGINE_MFMA_F16_
 // The engine that searches a level of block size B: the matrix engine
 // measured fastest per block size for MFMA (f16 32x32 tiles at B = 2 and 4,
 // where it needs no replicated operands; f16 16x16 tiles at B = 8; int8 hi/lo
-// planes at B = 16), FP32 where the requested matrix engine has no form.
+// planes at B = 16 and 32, where f32 accumulation of f16 products would no
+// longer be exact above B = 16), FP32 where the requested matrix engine has
+// no form.
 int engine_for(int engine, int B) {
     if (engine == FIC_ENGINE_MFMA)
         return (B == 2 || B == 4) ? E_F16 : B == 8 ? E_H16 : mfma_supported(B) ? E_I8 : E_FP32;
@@ -207,7 +209,7 @@ SSet make_sset(const int32_t *num, int count, int den) {
 // ---------------------------------------------------------------- batched level plans
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
-int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+long cdiv(long a, long b) { return (a + b - 1) / b; }
 
 // One image's share of one level: what the caller hands over.
 struct ImgIn {
@@ -234,8 +236,10 @@ struct LevelPlan {
 // pointers; bind() rebases them once the slots are allocated).
 // build_integ: this plan computes the images' summed-area tables (every plan
 // of one encode lays them out identically, so later levels reuse them).
-void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int engine, int level0,
+// Returns false when a launch of the batch would need 2^31 or more workgroups.
+bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int engine, int level0,
                 bool build_integ, int pool_key) {
+    bool fits = true;
     const int n = (int)in.size();
     pl.h.assign(n, ImgLvl());
     pl.pre.assign((size_t)K_NUM * (n + 1), 0);
@@ -301,7 +305,7 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
         d.eng = eng;
         pl.bh.any_cap |= x.pool_max > 0;
         // block counts
-        int blk[K_NUM] = {0};
+        long blk[K_NUM] = {0};
         if (level0) blk[K_LEVEL0] = cdiv((long)(d.W / d.B) * (d.H / d.B), 256);
         // entropy: one wave per strip of candidate rows, the strip as long as
         // possible (sliding windows reuse work) while still giving ~1024 waves;
@@ -343,7 +347,7 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
                             : mfma_geometry(d.B, d.range_cap, d.pool_cap, eng == E_H16);
                 const int nquads = d.geo.nrg * (d.geo.rpw / 4);
                 const int tile = f16 ? kDomTile32 : kDomTile;
-                const int ntiles = cdiv(d.pool_cap, tile);
+                const int ntiles = (int)cdiv(d.pool_cap, tile);
                 const long afr = (long)nquads * (f16 ? 1 : 2) * d.geo.ka;   // 1 KiB fragments
                 blk[K_AFRAG] = cdiv(afr * 64, 256);
                 blk[K_BFRAG] = cdiv((long)ntiles * d.geo.kt * 64, 256);
@@ -366,11 +370,16 @@ void plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
             }
             d.part = (Partial *)take(S_PARTIAL, sizeof(Partial) * (size_t)d.range_cap * d.nslot);
         }
-        for (int k = 0; k < K_NUM; ++k) pl.pre[(size_t)k * (n + 1) + i + 1] = pl.pre[(size_t)k * (n + 1) + i] + blk[k];
+        for (int k = 0; k < K_NUM; ++k) {
+            const long v = (long)pl.pre[(size_t)k * (n + 1) + i] + blk[k];
+            if (v > INT32_MAX) fits = false;
+            pl.pre[(size_t)k * (n + 1) + i + 1] = (int)std::min(v, (long)INT32_MAX);
+        }
     }
     for (int k = 0; k < K_NUM; ++k) pl.bh.blocks[k] = pl.pre[(size_t)k * (n + 1) + n];
     for (int s = 0; s < S_NUM_SLOTS; ++s) pl.slot_bytes[s] = off[s];
     pl.bh.dev.n = n;
+    return fits;
 }
 
 size_t table_bytes(const LevelPlan &pl) {
@@ -866,7 +875,7 @@ int fic_build_domain_pool(fic_ctx *ctx, const fic_image *img, int32_t B, int32_t
     std::vector<ImgIn> in(1);
     in[0] = ImgIn{img, B, L, pct.num, pct.den, pool_max, out, nullptr, nullptr, 0, nullptr, nullptr, nullptr};
     std::vector<LevelPlan> plans(1);
-    plan_level(plans[0], in, false, FIC_ENGINE_MFMA, 0, true, pool_key);
+    if (!plan_level(plans[0], in, false, FIC_ENGINE_MFMA, 0, true, pool_key)) return FIC_E_NOMEM;
     st = reserve_plans(ctx, plans, 0);
     if (st != FIC_OK) return st;
     bind(ctx, plans[0]);
@@ -895,7 +904,7 @@ int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, c
     in[0] = ImgIn{img, B, B, 0, 1, 0, const_cast<fic_pool *>(pool), ranges_xy, n_ranges, range_capacity, out,
                   children_xy, n_children};
     std::vector<LevelPlan> plans(1);
-    plan_level(plans[0], in, true, engine, 0, true, FIC_POOL_ENTROPY);
+    if (!plan_level(plans[0], in, true, engine, 0, true, FIC_POOL_ENTROPY)) return FIC_E_NOMEM;
     plans[0].bh.ss = make_sset(s_num, s_count, s_den);
     plans[0].bh.rms = split_rms;
     plans[0].bh.is_last = is_last ? 1 : 0;
@@ -957,7 +966,7 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
                           cl->xy, cl->count, (img->width / B) * (img->height / B), cl,
                           last ? nullptr : codes[i * NL + l + 1].xy, last ? nullptr : codes[i * NL + l + 1].count};
         }
-        plan_level(plans[l], in, true, p->engine, l == 0, l == 0, p->pool_key);
+        if (!plan_level(plans[l], in, true, p->engine, l == 0, l == 0, p->pool_key)) return FIC_E_NOMEM;
         plans[l].bh.ss = make_sset(p->s_num[l], p->s_count[l], p->s_den[l]);
         plans[l].bh.rms = p->split_rms[l];
         plans[l].bh.is_last = last ? 1 : 0;

@@ -77,10 +77,10 @@ __global__ __launch_bounds__(256) void k_f16_afrag(BatchDev b) {
     const ImgLvl &d = b.d[im];
     const int B = d.B, KS = d.geo.ka;
     const int nquads = d.geo.nrg * (d.geo.rpw / 4);
-    const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
-    if (slot >= nquads * KS * 64) return;
-    const int lane = slot & 63;
-    const int rest = slot >> 6;
+    const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    if (slot >= (int64_t)nquads * KS * 64) return;
+    const int lane = (int)(slot & 63);
+    const int rest = (int)(slot >> 6);
     const int s = rest % KS, q = rest / KS;
     const int m = lane & 31, kb = lane >> 5;
     const int j = m >> 3, h = (m >> 2) & 1, i = m & 3;
@@ -116,10 +116,10 @@ __global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
     const ImgLvl &d = b.d[im];
     const int B = d.B, KS = d.geo.kt;
     const int ntiles = (d.pool_cap + kDomTile32 - 1) / kDomTile32;
-    const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
-    if (slot >= ntiles * KS * 64) return;
-    const int lane = slot & 63;
-    const int rest = slot >> 6;
+    const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;   // can pass 2^31
+    if (slot >= (int64_t)ntiles * KS * 64) return;
+    const int lane = (int)(slot & 63);
+    const int rest = (int)(slot >> 6);
     const int s = rest % KS, tile = rest / KS;
     const int col = lane & 31, kb = lane >> 5;
     const int p = tile * kDomTile32 + col;

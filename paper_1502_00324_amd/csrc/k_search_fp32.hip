@@ -1,6 +1,6 @@
-// Plain per-pixel FP32 search engine: the baseline the MFMA engine is
-// measured against, and the engine for range sizes the MFMA tiling does not
-// cover (B = 2, B = 32).
+// Plain per-pixel FP32 search engine: the baseline the MFMA engines are
+// measured against, and the engine for range sizes a requested matrix engine
+// has no form for.
 //
 // Per (range, isometry, domain) it sums (view_j - 128)(D4_j - 512) over the
 // B^2 decimated cells in FP32 -- the same integer C' as the MFMA engine.
@@ -43,10 +43,11 @@ __global__ __launch_bounds__(256) void k_fp32_views(BatchDev b) {
     const int *pre = b.pre + K_VIEWS * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int e = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    // 64-bit element index: B^2 x padded count passes 2^31 for large images
+    const int64_t e = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;
     const int B = d.B, n = B * B, Rpad = d.rpad;
-    if (e >= n * Rpad) return;
-    const int j = e / Rpad, r = e - j * Rpad;
+    if (e >= (int64_t)n * Rpad) return;
+    const int j = (int)(e / Rpad), r = (int)(e - (int64_t)j * Rpad);
     const int cy = j / B, cx = j - cy * B;
     const bool valid = r < min(*d.nr, d.range_cap);
     int x0 = 0, y0 = 0;
@@ -71,10 +72,12 @@ __global__ __launch_bounds__(256) void k_fp32_doms(BatchDev b) {
     const int *pre = b.pre + K_DOMS * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int e = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    // 64-bit element index: B^2 x padded pool passes 2^31 at B = 32 on a
+    // 4096^2 image (1024 x 4.07 M candidates)
+    const int64_t e = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;
     const int B = d.B, n = B * B, Ppad = d.ppad, pitch = d.pitch;
-    if (e >= n * Ppad) return;
-    const int j = e / Ppad, p = e - j * Ppad;
+    if (e >= (int64_t)n * Ppad) return;
+    const int j = (int)(e / Ppad), p = (int)(e - (int64_t)j * Ppad);
     const bool valid = p < min(*d.pcount, d.pool_cap);
     float val = 0.f;
     if (valid) {

@@ -17,6 +17,8 @@
 //       combination.  Same 16-row layout as the int8 forms.
 // The planes form does half the MFMA work of the raw form and moves half the
 // domain bytes; planes and f16 need B^2 >= 64, so B = 4 keeps the raw form.
+// Up to B = 32 the int32 planes are exact (|C_hi| <= B^2 2^14 <= 2^24); the
+// f16 form is exact up to B = 16 only.
 //
 // Fragment layouts (16 bytes per lane, 64 lanes per 1 KiB fragment, verified
 // for this instruction: lane L feeds A row L%16 and B column L%16 with the
@@ -50,7 +52,7 @@ __device__ __forceinline__ h8v as_h8(const v4i &x) {
     return h;
 }
 
-bool mfma_supported(int B) { return B == 4 || B == 8 || B == 16; }
+bool mfma_supported(int B) { return B == 4 || B == 8 || B == 16 || B == 32; }
 
 // Operand form (pl), range quads per wave (RQ), domain tiles per LDS stage
 // (DT) and the occupancy the register allocation aims at (waves per SIMD).
@@ -64,6 +66,7 @@ static const Shape kShapes[] = {
     {16, 2, 2, 1, 3}, {16, 2, 2, 1, 2}, {16, 2, 1, 2, 3}, {16, 2, 2, 2, 2}, {16, 2, 1, 1, 4}, {16, 1, 1, 1, 2},
     {8, 3, 2, 8, 3}, {8, 3, 1, 8, 4}, {8, 3, 2, 16, 2}, {8, 3, 3, 8, 2}, {8, 3, 4, 8, 2},
     {16, 3, 1, 2, 3}, {16, 3, 2, 1, 2}, {16, 3, 1, 1, 4}, {16, 3, 2, 2, 2},
+    {32, 2, 1, 1, 2}, {32, 2, 2, 1, 1}, {32, 2, 1, 2, 1},
 };
 static Shape mfma_shape(int B, bool f16) {
     const char *e = getenv("FIC_MFMA_SHAPE");
@@ -146,10 +149,10 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
     const ImgLvl &d = b.d[im];
     const int B = d.B, KA = d.geo.ka, planes = d.geo.pl == 2, f16 = d.geo.pl == 3;
     const int nquads = d.geo.nrg * (d.geo.rpw / 4);
-    const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
-    if (slot >= nquads * 2 * KA * 64) return;
-    const int lane = slot & 63;
-    int rest = slot >> 6;
+    const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    if (slot >= (int64_t)nquads * 2 * KA * 64) return;
+    const int lane = (int)(slot & 63);
+    int rest = (int)(slot >> 6);
     const int s = rest % KA;
     rest /= KA;
     const int h = rest & 1, q = rest >> 1;
@@ -201,10 +204,10 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     const ImgLvl &d = b.d[im];
     const int B = d.B, KA = d.geo.ka, KT = d.geo.kt, planes = d.geo.pl == 2, f16 = d.geo.pl == 3;
     const int ntiles = (d.pool_cap + kDomTile - 1) / kDomTile;
-    const int slot = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
-    if (slot >= ntiles * KT * 64) return;
-    const int lane = slot & 63;
-    const int rest = slot >> 6;
+    const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;   // can pass 2^31
+    if (slot >= (int64_t)ntiles * KT * 64) return;
+    const int lane = (int)(slot & 63);
+    const int rest = (int)(slot >> 6);
     const int s = rest % KT, tile = rest / KT;
     const int j = lane & 15, kg = lane >> 4;
     const int p = tile * kDomTile + j;
@@ -264,8 +267,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     constexpr int NP = PL == 2 ? 2 : 1;          // accumulator planes
     constexpr int KB = KA * NP;                  // K-steps of a domain tile
     // share range bests across workgroups only when a stage is long enough
-    // (>= 4 tiles) to hide the coherent load of the shared values
-    constexpr bool SHARE = DT >= 4;
+    // (>= 4 tiles, or one tile of >= 32 K-steps) to hide the coherent load of
+    // the shared values
+    constexpr bool SHARE = DT >= 4 || KB >= 32;
     constexpr int STAGE = DT * KB * 64;          // uint4 per stage
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
@@ -356,32 +360,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     };
     // acc[qi][h][plane]: the planes are combined (4 hi + lo) at the test,
     // one tile later, so no MFMA result is waited for at issue time
+    // (up to 8 K-steps the tile's fragments are read up front; longer tiles
+    // read each K-step's fragments just before its MFMAs, to bound registers)
     auto mfma_tile = [&](Acc (&acc)[RQ][2][NP], int buf, int dt) {
-        v4i Bf[KB];
-#pragma unroll
-        for (int s = 0; s < KB; ++s) {
+        constexpr int KR = KB <= 8 ? KB : NP;   // fragments read per batch
+        v4i Bf[KR];
+        auto rd = [&](int s) {
             const uint4 u = bl[buf][(dt * KB + s) * 64 + lane];
-            Bf[s] = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+            return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+        };
+        if constexpr (KB <= 8) {
+#pragma unroll
+            for (int s = 0; s < KB; ++s) Bf[s] = rd(s);
         }
 #pragma unroll
         for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl) acc[qi][0][pl] = acc[qi][1][pl] = Acc{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < KA; ++s)
+        for (int s = 0; s < KA; ++s) {
+            if constexpr (KB > 8) {
 #pragma unroll
-            for (int pl = 0; pl < NP; ++pl)
+                for (int pl = 0; pl < NP; ++pl) Bf[pl] = rd(pl * KA + s);
+            }
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) {
+                const v4i &b = KB <= 8 ? Bf[pl * KA + s] : Bf[pl];
 #pragma unroll
                 for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         if constexpr (PL == 3)
-                            acc[qi][h][pl] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(A[qi][h][s]), as_h8(Bf[s]),
+                            acc[qi][h][pl] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(A[qi][h][s]), as_h8(b),
                                                                                     acc[qi][h][pl], 0, 0, 0);
                         else
-                            acc[qi][h][pl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][h][s], Bf[pl * KA + s],
+                            acc[qi][h][pl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qi][h][s], b,
                                                                                    acc[qi][h][pl], 0, 0, 0);
                     }
+            }
+        }
     };
     auto cprime = [&](const v4i (&a)[NP]) -> v4i {
         if constexpr (PL == 2) return (a[0] << 2) + a[1];
@@ -534,6 +551,10 @@ hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
         FIC_SEARCH(8, 3, 2, 1, 2);
         FIC_SEARCH(8, 3, 1, 1, 4);
         FIC_SEARCH(8, 3, 2, 2, 2);
+    } else if (B == 32) {
+        FIC_SEARCH(16, 2, 1, 1, 2);
+        FIC_SEARCH(16, 2, 2, 1, 1);
+        FIC_SEARCH(16, 2, 1, 2, 1);
     }
 #undef FIC_SEARCH
     return hipErrorInvalidValue;

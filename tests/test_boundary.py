@@ -130,8 +130,8 @@ def test_ctx_create_reports_missing_device():
 def test_level_engine_resolution():
     M, F, I8, H = fic.ENGINE_MFMA, fic.ENGINE_FP32, fic.ENGINE_MFMA_I8, fic.ENGINE_MFMA_F16
     X = fic.ENGINE_MFMA_F16_16X16
-    assert [fic.level_engine(M, B) for B in (2, 4, 8, 16, 32)] == [H, H, X, I8, F]
-    assert [fic.level_engine(I8, B) for B in (2, 4, 8, 16, 32)] == [F, I8, I8, I8, F]
+    assert [fic.level_engine(M, B) for B in (2, 4, 8, 16, 32)] == [H, H, X, I8, I8]
+    assert [fic.level_engine(I8, B) for B in (2, 4, 8, 16, 32)] == [F, I8, I8, I8, I8]
     assert [fic.level_engine(H, B) for B in (2, 4, 8, 16, 32)] == [H, H, H, H, F]
     assert [fic.level_engine(X, B) for B in (2, 4, 8, 16, 32)] == [F, F, X, X, F]
     assert all(fic.level_engine(F, B) == F for B in (2, 4, 8, 16, 32))

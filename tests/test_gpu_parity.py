@@ -73,6 +73,8 @@ CASES = [
     ("pct0_full_pool", 8, 64, 64, 5, [(8, 2), (4, 2)], (0, 1), 0, K16, 16, (5, 1)),
     ("odd_s_set", 9, 64, 64, 5, [(8, 4), (4, 4)], (3, 10), 0, (0, 3, 7, 10), 10, (7, 2)),
     ("b32_to_b16", 10, 128, 128, 10, [(32, 4), (16, 4)], (1, 2), 0, K16, 16, (8, 1)),
+    # B = 32 over ~200 domain tiles with a ragged last tile, 3 range groups
+    ("b32_multi_tile", 13, 256, 192, 12, [(32, 2), (16, 2)], (1, 2), 0, K16, 16, (8, 1)),
     ("pool_max_ties", 11, 96, 64, 30, [(8, 2), (4, 2)], (1, 10), 100, K16, 16, (6, 1)),
 ]
 
@@ -89,6 +91,31 @@ def test_encode_decode_parity(ctx, case, engine):
     ref_dec = oracle.decode(W, H, ref, 6)
     np.testing.assert_array_equal(dec, ref_dec)
     assert oracle.psnr(img, dec) == oracle.psnr(img, ref_dec)
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+def test_b32_extreme_magnitudes(ctx, engine):
+    """Pixels 0 or 255 only: range and domain operands at their extremes, so
+    the B = 32 cross term reaches the largest magnitudes the int32 planes
+    hold (|C_hi| up to 2^24)."""
+    rng = np.random.default_rng(5)
+    img = (rng.integers(0, 2, (128, 160)) * 255).astype(np.uint8)
+    levels = [(32, 2), (16, 2)]
+    got, dec = gpu_run(ctx, img, params(levels, (1, 2), 0, K16, 16, (8, 1), engine), iters=4)
+    ref = oracle_run(img, levels, (1, 2), 0, K16, 16, (8, 1))
+    assert_levels_equal(got, ref, "b32_extreme")
+    np.testing.assert_array_equal(dec, oracle.decode(160, 128, ref, 4))
+
+
+@pytest.mark.parametrize("engine", [fic.ENGINE_MFMA, fic.ENGINE_FP32], ids=["mfma", "fp32"])
+def test_b32_xcd_chunks(ctx, engine):
+    """512 x 512 at B = 32, L = 2: ~25 k domains in ~40 chunks, enough for the
+    XCD-aware chunk walk and the cross-workgroup best sharing."""
+    img = make_image(14, 512, 512, 40)
+    levels = [(32, 2)]
+    got, _ = gpu_run(ctx, img, params(levels, (1, 2), 0, K16, 16, (8, 1), engine))
+    ref = oracle_run(img, levels, (1, 2), 0, K16, 16, (8, 1))
+    assert_levels_equal(got, ref, "b32_xcd")
 
 
 @pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
@@ -149,6 +176,57 @@ def test_config3_1024_sampled_parity(ctx):
             ranges = oracle.children(ranges, ref["split"], B)
             if len(ranges) == 0:
                 break
+
+
+@pytest.fixture(scope="module")
+def c5_reference():
+    """Full-size c5 (4096^2, B 32 -> 16 -> 8 -> 4): the oracle's four pools in
+    full (4.07 M to 16.7 M candidates) and the codes of 12 level-0 ranges with
+    their whole quadtree subtrees.  Few level-0 ranges of this image split, so
+    the sample is the 12 with the largest gradient energy (sum of squared
+    neighbour differences), the ones most likely to reach the lower levels."""
+    wl = WORKLOADS["c5_4096"]
+    seed, W, H, nrect = wl.images[0]
+    img = make_image(seed, W, H, nrect)
+    pools = [oracle.build_pool(img, B, L, wl.pct, wl.pool_max, threads=WORKERS) for (B, L) in wl.levels]
+    B0 = wl.levels[0][0]
+    f = img.astype(np.int64)
+    ge = np.zeros_like(f)
+    ge[:, :-1] += (f[:, 1:] - f[:, :-1]) ** 2
+    ge[:-1, :] += (f[1:, :] - f[:-1, :]) ** 2
+    energy = ge.reshape(H // B0, B0, W // B0, B0).sum(axis=(1, 3)).ravel()
+    all0 = oracle.level0_ranges(W, H, B0)
+    ranges = all0[np.sort(np.argsort(-energy, kind="stable")[:12])]
+    refs = []
+    for l, (B, L) in enumerate(wl.levels):
+        last = l == len(wl.levels) - 1
+        ref = oracle.encode_level(img, pools[l]["xy"], ranges, B, list(wl.s_num), wl.s_den, wl.split_rms, last,
+                                  workers=WORKERS)
+        refs.append((ranges, ref))
+        if last:
+            break
+        ranges = oracle.children(ranges, ref["split"], B)
+        if len(ranges) == 0:
+            break
+    return wl, img, all0, pools, refs
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("engine", [fic.ENGINE_MFMA, fic.ENGINE_FP32], ids=["mfma", "fp32"])
+def test_config5_4096_sampled_parity(ctx, c5_reference, engine):
+    wl, img, all0, pools, refs = c5_reference
+    print("c5 engine", engine, "subtree ranges per level", [len(r) for r, _ in refs], flush=True)
+    p = params(wl.levels, wl.pct, wl.pool_max, wl.s_num, wl.s_den, wl.split_rms, engine)
+    got, _ = gpu_run(ctx, img, p)
+    for l, ref_pool in enumerate(pools):
+        for f in ("xy", "key", "sum4", "a"):
+            np.testing.assert_array_equal(got[l]["pool"][f], ref_pool[f], err_msg="c5 level %d pool %s" % (l, f))
+    np.testing.assert_array_equal(got[0]["codes"]["xy"], all0)
+    for l, (ranges, ref) in enumerate(refs):
+        pos = {int(v): i for i, v in enumerate(got[l]["codes"]["xy"])}
+        idx = np.array([pos[int(v)] for v in ranges], np.int64)
+        for f in ("split", "domain", "iso", "s_idx", "offset", "err"):
+            np.testing.assert_array_equal(got[l]["codes"][f][idx], ref[f], err_msg="c5 level %d %s" % (l, f))
 
 
 def test_stepwise_entry_points_match_oracle(ctx):

@@ -87,9 +87,10 @@ def test_engine_choice(runs):
     x = kinds(runs["mixed_f16x_3lv"])
     assert x.count("k_mfma_search") == 2 * 2 and x.count("k_fp32_search") == 2 and "k_f16_search" not in x
     assert runs["mixed_f16x_3lv"]["forms"] == [3, 3] * 2
-    # B=32 levels take the FP32 engine even when MFMA is asked for
-    assert "k_fp32_search" in kinds(runs["mixed_b32_4lv"]) and "k_f16_search" in kinds(runs["mixed_b32_4lv"])
-    assert "k_mfma_search" in kinds(runs["mixed_b32_4lv"])
+    # B=32 levels take the int8 planes form: no FP32 search in the default mix
+    b32 = kinds(runs["mixed_b32_4lv"])
+    assert "k_fp32_search" not in b32 and b32.count("k_f16_search") == b32.count("k_mfma_search") // 3
+    assert runs["mixed_b32_4lv"]["forms"] == [2, 2, 3] * (b32.count("k_mfma_search") // 3)
     assert "k_fp32_search" not in kinds(runs["paper_b2_cap"])   # B = 2 runs on the f16 engine
 
 
