@@ -130,10 +130,14 @@ def main():
 
     from paper_1502_00324_amd import fic
     from paper_1502_00324_amd.configs import WORKLOADS
-    from paper_1502_00324_amd.synth import make_image
+    from paper_1502_00324_amd.synth import make_image, sha256
 
     wl = WORKLOADS[args.workload]
     images = [make_image(s, w, h, n) for (s, w, h, n) in wl.images]
+    # the bytes recorded in the input manifest (same generator draws here)
+    with open(os.path.join(ROOT, "tests", "golden", "synth_manifest.json")) as f:
+        manifest = json.load(f).get(args.workload, [])
+    inputs_match = [e["sha256"] for e in manifest] == [sha256(im) for im in images]
     dev = torch.device("cuda:0")
     imgs = [torch.from_numpy(im).to(dev) for im in images]
     ctx = fic.Context(0)
@@ -265,6 +269,7 @@ def main():
         "dtype": "+".join(sorted({ENGINE_NAME[fic.level_engine(engine, B)].replace("mfma_", "")
                                   for (B, L) in wl.levels})),
         "data": "synthetic (seeded 1/f^2 noise + rectangles)",
+        "inputs_match_manifest": inputs_match,
         "config": {"workload": wl.name + ": " + wl.notes, "images": len(images),
                    "levels": [{"B": B, "L": L} for (B, L) in wl.levels],
                    "pool": "drop ceil(%d/%d * Nd) lowest-%s candidates" % (wl.pct + (args.pool_key,)),
