@@ -66,7 +66,8 @@ enum {
  *             decimated positions for B = 2 (zero-padded to 16), 4, 8, 16;
  *             FP32 at B = 32 (32 x 32 result tiles).
  *   MFMA_F16_16X16: f16 matrix cores in the 16 x 16 result tiles of the
- *             int8 engine, for B = 8 and 16; FP32 elsewhere. */
+ *             int8 engine for B = 2..16; at B = 2 and 4 the prune threshold
+ *             rides in the same contraction; FP32 at B = 32. */
 enum {
     FIC_ENGINE_MFMA = 0,
     FIC_ENGINE_FP32 = 1,

@@ -164,7 +164,7 @@ int engine_for(int engine, int B) {
         return (B == 2 || B == 4) ? E_F16 : B == 8 ? E_H16 : mfma_supported(B) ? E_I8 : E_FP32;
     if (engine == FIC_ENGINE_MFMA_I8) return mfma_supported(B) ? E_I8 : E_FP32;
     if (engine == FIC_ENGINE_MFMA_F16) return f16_supported(B) ? E_F16 : E_FP32;
-    if (engine == FIC_ENGINE_MFMA_F16_16X16) return (B == 8 || B == 16) ? E_H16 : E_FP32;
+    if (engine == FIC_ENGINE_MFMA_F16_16X16) return B <= 16 ? E_H16 : E_FP32;
     return E_FP32;
 }
 

@@ -43,7 +43,7 @@ bool f16_supported(int B) { return B == 2 || B == 4 || B == 8 || B == 16; }
 struct F16Shape { int B, rq, dt, wpe; };
 static const F16Shape kF16Shapes[] = {
     {2, 1, 8, 4},
-    {4, 1, 8, 4}, {4, 2, 8, 2}, {4, 1, 16, 3}, {4, 2, 4, 3},
+    {4, 1, 8, 4}, {4, 2, 8, 2}, {4, 1, 16, 3}, {4, 2, 4, 3}, {4, 1, 8, 3},
     {8, 2, 4, 2}, {8, 1, 4, 3}, {8, 1, 8, 2}, {8, 2, 2, 2},
     {16, 1, 1, 3}, {16, 1, 2, 2},
 };
@@ -249,23 +249,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     };
     // the tile's fragments are read up front (in groups of up to 8 K-steps),
     // so one LDS wait covers a group rather than every MFMA
-    constexpr int KG = KS < 8 ? KS : 8;
-    auto mfma_tile = [&](f16x (&acc)[RQ], int buf, int dt) {
+    // With up to 4 K-steps a tile's fragments are read into registers one
+    // tile ahead of its MFMAs (two sets alternate), so the LDS latency is
+    // covered by the previous tile; longer tiles read them in groups of 8.
+    constexpr bool PREF = KS <= 4;
+    constexpr int KG = PREF ? KS : 8;
+    auto read_tile = [&](h8 (&bf)[KG], int buf, int dt, int s0) {
+#pragma unroll
+        for (int s = 0; s < KG; ++s) {
+            const uint4 u = bl[buf][(dt * KS + s0 + s) * 64 + lane];
+            __builtin_memcpy(&bf[s], &u, sizeof(h8));
+        }
+    };
+    auto mfma_tile = [&](f16x (&acc)[RQ], int buf, int dt, h8 (&bq)[KG]) {
 #pragma unroll
         for (int qi = 0; qi < RQ; ++qi) acc[qi] = f16x{0.f};
 #pragma unroll
         for (int s0 = 0; s0 < KS; s0 += KG) {
-            h8 bf[KG];
-#pragma unroll
-            for (int s = 0; s < KG; ++s) {
-                const uint4 u = bl[buf][(dt * KS + s0 + s) * 64 + lane];
-                __builtin_memcpy(&bf[s], &u, sizeof(h8));
-            }
+            if constexpr (!PREF) read_tile(bq, buf, dt, s0);
 #pragma unroll
             for (int s = 0; s < KG; ++s)
 #pragma unroll
                 for (int qi = 0; qi < RQ; ++qi)
-                    acc[qi] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[qi][s0 + s], bf[s], acc[qi], 0, 0, 0);
+                    acc[qi] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[qi][s0 + s], bq[s], acc[qi], 0, 0, 0);
         }
     };
     for (int cj = 0; cj < ncs; ++cj) {
@@ -292,11 +298,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             if (wave_on) {
                 const int tbase = t0 + stg * DT;
                 f16x acc[2][RQ];
-                mfma_tile(acc[0], buf, 0);
+                h8 bq[2][KG];
+                if constexpr (PREF) read_tile(bq[0], buf, 0, 0);
+                mfma_tile(acc[0], buf, 0, bq[0]);
+                if (PREF && DT > 1) read_tile(bq[1], buf, 1, 0);
 #pragma unroll
                 for (int dt = 0; dt < DT; ++dt) {
                     const int cur = dt & 1;
-                    if (dt + 1 < DT) mfma_tile(acc[cur ^ 1], buf, dt + 1);
+                    if (dt + 1 < DT) {
+                        mfma_tile(acc[cur ^ 1], buf, dt + 1, bq[(dt + 1) & 1]);
+                        // the set of tile dt is free once tile dt's MFMAs were issued
+                        if (PREF && dt + 2 < DT) read_tile(bq[dt & 1], buf, dt + 2, 0);
+                    }
                     const float2 di = dl[buf][dt * kDomTile32 + (lane & 31)];
                     bool pass[RQ][2];
                     float mx[RQ][2];
@@ -397,6 +410,7 @@ hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st) {
         FIC_F16(1, 2, 8, 2);
         FIC_F16(1, 1, 16, 3);
         FIC_F16(1, 2, 4, 3);
+        FIC_F16(1, 1, 8, 3);
     } else if (B == 8) {
         FIC_F16(4, 2, 4, 2);
         FIC_F16(4, 1, 4, 3);

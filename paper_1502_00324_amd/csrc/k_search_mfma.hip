@@ -1,4 +1,5 @@
-// Int8 MFMA search engine (gfx950, v_mfma_i32_16x16x64_i8).
+// 16-row MFMA search engine (gfx950, v_mfma_i32_16x16x64_i8 and
+// v_mfma_f32_16x16x32_f16).
 //
 // The cross term of every (range, isometry) x domain pair is a dense
 // contraction.  Centred at 128, both operands fit int8 and the int32
@@ -15,10 +16,30 @@
 //       (every partial sum an integer of magnitude <= B^2 2^16 <= 2^24); the
 //       accumulators are floats, so the epilogue needs no conversion or
 //       combination.  Same 16-row layout as the int8 forms.
+//   f16 with the fused threshold (pl = 4, B = 2 and 4, one K-step of 32):
+//       K-groups 0 and 1 (lanes 0..31) hold the <= 16 decimated positions,
+//       centred at each block's own rounded mean: r - m_r and D4 - m_d with
+//       m_r = round(Sr/n), m_d = round(Sd4/n) (magnitudes <= 255 and <= 1020,
+//       exact in f16; sums <= n 2^18 <= 2^22, exact in f32), so
+//         acc1 = sum (r - m_r)(D4 - m_d) = Bx/n + e_r e_d / n,
+//         e_r = Sr - n m_r, e_d = Sd4 - n m_d, |e_r e_d / n| <= n/4.
+//       K-group 2 (lanes 32..47) holds the prune threshold as a short dot
+//       product: rows (tn_hi, tn_hi, tn_lo, 65504, K_r), columns
+//       (-sA_hi, -sA_lo, -sA_hi, kill_d, 128), so the accumulator is
+//         acc = acc1 - tn sA + 128 K_r + 65504 kill_d
+//       up to the dropped terms (< 2^-20 tn sA), with tn = tn_hi + tn_lo and
+//       sA = sqrt A = sA_hi + sA_lo as f16 pairs, 128 K_r = n/4 + 16 the
+//       margin (the centring, the split and the f32 sums), kill_d = -1024
+//       past the pool, and K_r = 65504 (no best yet: every pair passes) or
+//       -65504 (nothing can win: no pair passes).  A pair can reach the
+//       range's best only if Bx/n > tn sA, hence only if acc > 0, so the test
+//       is the isometry maximum and one compare.  The threshold rows live in
+//       the A registers and are rewritten whenever tn changes; passing pairs
+//       recompute acc1 without them and confirm with Bx = n acc1 - e_r e_d.
 // The planes form does half the MFMA work of the raw form and moves half the
-// domain bytes; planes and f16 need B^2 >= 64, so B = 4 keeps the raw form.
-// Up to B = 32 the int32 planes are exact (|C_hi| <= B^2 2^14 <= 2^24); the
-// f16 form is exact up to B = 16 only.
+// domain bytes; planes and f16 need B^2 >= 64, so B = 4 keeps the raw form in
+// the int8 engine.  Up to B = 32 the int32 planes are exact (|C_hi| <= B^2
+// 2^14 <= 2^24); the f16 form is exact up to B = 16 only.
 //
 // Fragment layouts (16 bytes per lane, 64 lanes per 1 KiB fragment, verified
 // for this instruction: lane L feeds A row L%16 and B column L%16 with the
@@ -56,9 +77,9 @@ bool mfma_supported(int B) { return B == 4 || B == 8 || B == 16 || B == 32; }
 
 // Operand form (pl), range quads per wave (RQ), domain tiles per LDS stage
 // (DT) and the occupancy the register allocation aims at (waves per SIMD).
-// Each range size and form class (int8: pl 1 or 2; f16: pl 3) has a measured
-// default (its first entry); FIC_MFMA_SHAPE="pl,rq,dt,wpe" selects another
-// compiled shape of the same class (used to tune).
+// Each range size and form class (int8: pl 1 or 2; f16: pl 3 or 4) has a
+// measured default (its first entry); FIC_MFMA_SHAPE="pl,rq,dt,wpe" selects
+// another compiled shape of the same class (used to tune).
 struct Shape { int B, pl, rq, dt, wpe; };
 static const Shape kShapes[] = {
     {4, 1, 2, 16, 3}, {4, 1, 1, 16, 3}, {4, 1, 4, 16, 2},
@@ -67,15 +88,17 @@ static const Shape kShapes[] = {
     {8, 3, 2, 8, 3}, {8, 3, 1, 8, 4}, {8, 3, 2, 16, 2}, {8, 3, 3, 8, 2}, {8, 3, 4, 8, 2},
     {16, 3, 1, 2, 3}, {16, 3, 2, 1, 2}, {16, 3, 1, 1, 4}, {16, 3, 2, 2, 2},
     {32, 2, 1, 1, 2}, {32, 2, 2, 1, 1}, {32, 2, 1, 2, 1},
+    {4, 4, 2, 8, 3}, {4, 4, 2, 16, 3}, {4, 4, 1, 8, 4}, {4, 4, 2, 8, 4}, {4, 4, 3, 8, 3}, {4, 4, 4, 8, 2},
+    {2, 4, 2, 8, 3},
 };
 static Shape mfma_shape(int B, bool f16) {
     const char *e = getenv("FIC_MFMA_SHAPE");
     int pl = 0, rq = 0, dt = 0, wpe = 0;
     if (e && sscanf(e, "%d,%d,%d,%d", &pl, &rq, &dt, &wpe) == 4)
         for (const Shape &s : kShapes)
-            if (s.B == B && (s.pl == 3) == f16 && s.pl == pl && s.rq == rq && s.dt == dt && s.wpe == wpe) return s;
+            if (s.B == B && (s.pl >= 3) == f16 && s.pl == pl && s.rq == rq && s.dt == dt && s.wpe == wpe) return s;
     for (const Shape &s : kShapes)
-        if (s.B == B && (s.pl == 3) == f16) return s;
+        if (s.B == B && (s.pl >= 3) == f16) return s;
     return Shape{B, 1, 1, 1, 1};
 }
 
@@ -134,7 +157,7 @@ MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, bool f16) {
     MfmaGeom g;
     const Shape sh = mfma_shape(B, f16);
     g.pl = sh.pl;
-    g.ka = sh.pl == 2 ? B * B / 64 : sh.pl == 3 ? B * B / 32 : B * B / 16;
+    g.ka = sh.pl == 2 ? B * B / 64 : sh.pl == 3 ? B * B / 32 : sh.pl == 4 ? 1 : B * B / 16;
     g.kt = sh.pl == 2 ? 2 * g.ka : g.ka;
     g.rpw = 16 * sh.rq;
     const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
@@ -147,7 +170,7 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
     const int *pre = b.pre + K_AFRAG * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int B = d.B, KA = d.geo.ka, planes = d.geo.pl == 2, f16 = d.geo.pl == 3;
+    const int B = d.B, KA = d.geo.ka, planes = d.geo.pl == 2, f16 = d.geo.pl == 3, ft = d.geo.pl == 4;
     const int nquads = d.geo.nrg * (d.geo.rpw / 4);
     const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;
     if (slot >= (int64_t)nquads * 2 * KA * 64) return;
@@ -160,7 +183,26 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
     const int t = 4 * h + (i & 3);
     const int r = q * 4 + (i >> 2);
     uint32_t w[4] = {0u, 0u, 0u, 0u};
-    if (f16 && r < min(*d.nr, d.range_cap)) {
+    if (ft) {
+        // positions in K-groups 0 and 1 minus the range's rounded mean; the
+        // threshold group (2) is written by the search kernel, group 3 is 0
+        h8v hv = h8v{0};
+        if (kg < 2 && r < min(*d.nr, d.range_cap)) {
+            const uint32_t v = d.rxy[r];
+            const int x0 = v & 0xffff, y0 = v >> 16, n = B * B;
+            const int ti = iso_inv(t), cen = round_mean(d.ri[r].sr, n);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * kg + e;
+                if (k >= n) continue;   // B = 2: 4 positions
+                const int cy = k / B, cx = k - cy * B;
+                int sy, sx;
+                iso_src(ti, B, cy, cx, sy, sx);
+                hv[e] = (_Float16)((int)d.pix[(size_t)(y0 + sy) * d.pitch + x0 + sx] - cen);
+            }
+        }
+        __builtin_memcpy(w, &hv, sizeof(w));
+    } else if (f16 && r < min(*d.nr, d.range_cap)) {
         const uint32_t v = d.rxy[r];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int ti = iso_inv(t);
@@ -202,7 +244,8 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     const int *pre = b.pre + K_BFRAG * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
-    const int B = d.B, KA = d.geo.ka, KT = d.geo.kt, planes = d.geo.pl == 2, f16 = d.geo.pl == 3;
+    const int B = d.B, KA = d.geo.ka, KT = d.geo.kt, planes = d.geo.pl == 2, f16 = d.geo.pl == 3,
+              ft = d.geo.pl == 4;
     const int ntiles = (d.pool_cap + kDomTile - 1) / kDomTile;
     const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;   // can pass 2^31
     if (slot >= (int64_t)ntiles * KT * 64) return;
@@ -213,7 +256,37 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     const int p = tile * kDomTile + j;
     const bool valid = p < min(*d.pcount, d.pool_cap);
     uint32_t w[4] = {0u, 0u, 0u, 0u};
-    if (valid && f16) {
+    if (ft) {
+        // K-groups 0, 1: positions minus the domain's rounded mean of D4;
+        // group 2: the threshold operand (-sA_hi, -sA_lo, -sA_hi, kill, 128)
+        h8v hv = h8v{0};
+        const int n = B * B;
+        if (kg < 2 && valid) {
+            const uint32_t v = d.pxy[p];
+            const int x0 = v & 0xffff, y0 = v >> 16, pitch = d.pitch;
+            const int cen = round_mean(d.psum4[p], n);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * kg + e;
+                if (k >= n) continue;
+                const int cy = k / B, cx = k - cy * B;
+                const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
+                hv[e] = (_Float16)(q[0] + q[1] + q[pitch] + q[pitch + 1] - cen);
+            }
+        } else if (kg == 2) {
+            if (valid) {
+                const float sa = sqrt_down((double)d.pa[p]);
+                const _Float16 hi = (_Float16)sa, lo = (_Float16)(sa - (float)hi);
+                hv[0] = -hi;
+                hv[1] = -lo;
+                hv[2] = -hi;
+            } else {
+                hv[3] = (_Float16)-1024.0f;
+            }
+            hv[4] = (_Float16)128.0f;
+        }
+        __builtin_memcpy(w, &hv, sizeof(w));
+    } else if (valid && f16) {
         const uint32_t v = d.pxy[p];
         const int x0 = v & 0xffff, y0 = v >> 16, pitch = d.pitch;
         h8v hv;
@@ -258,12 +331,15 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
 // of domain tiles.  Domain fragments go global -> registers -> LDS in stages
 // of DT tiles, double-buffered: the loads for stage s+1 are issued before the
 // MFMAs of stage s and written to the other LDS buffer after them.
-template <int PL> struct AccOf { typedef v4i type; };   // int32 accumulators
-template <> struct AccOf<3> { typedef v4f type; };      // f16 form: f32 accumulators
+template <int PL> struct AccOf { typedef v4i type; typedef int max_type; };   // int32 accumulators
+template <> struct AccOf<3> { typedef v4f type; typedef float max_type; };  // f16 form: f32 accumulators
+template <> struct AccOf<4> { typedef v4f type; typedef float max_type; };  // f16, fused threshold
 
 template <int KA, int PL, int RQ, int DT, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_mfma_search(BatchDev bt, SSet ss) {
     typedef typename AccOf<PL>::type Acc;
+    typedef typename AccOf<PL>::max_type MaxT;   // C'max: exact int, or an exact integer in a float
+    constexpr bool FT = PL == 4;                 // the threshold is in the accumulators
     constexpr int NP = PL == 2 ? 2 : 1;          // accumulator planes
     constexpr int KB = KA * NP;                  // K-steps of a domain tile
     // share range bests across workgroups only when a stage is long enough
@@ -328,6 +404,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         bk[qi] = 0;
     }
 
+    // Fused threshold: K-group 2 (lanes 32..47) of both halves' A fragment
+    // holds the row's threshold; row i = lane % 16 belongs to range i / 4 of
+    // the quad, whose tn lives in result lanes 16 (i / 4) .. + 15.
+    const float ft_k = (float)(n / 4 + 16) / 128.0f;
+    auto build_thr = [&](int qi) {
+        const float t = __shfl(tn[qi], 16 * ((lane & 15) >> 2), 64);
+        _Float16 th = (_Float16)0, tl = (_Float16)0, kr;
+        if (__builtin_isnan(t)) {
+            kr = (_Float16)-65504.0f;            // nothing can win: no pair passes
+        } else if (t < -1e29f) {
+            kr = (_Float16)65504.0f;             // no best yet: every pair passes
+        } else {
+            th = (_Float16)t;
+            tl = (_Float16)(t - (float)th);
+            kr = (_Float16)ft_k;
+        }
+        h8v hv = h8v{0};
+        hv[0] = th;
+        hv[1] = th;
+        hv[2] = tl;
+        hv[3] = (_Float16)65504.0f;              // times the domain's kill value
+        hv[4] = kr;                              // times 128
+        v4i w;
+        __builtin_memcpy(&w, &hv, sizeof(w));
+        if (lane >= 32 && lane < 48) {
+            A[qi][0][0] = w;
+            A[qi][1][0] = w;
+        }
+    };
+    if constexpr (FT) {
+#pragma unroll
+        for (int qi = 0; qi < RQ; ++qi) build_thr(qi);
+    }
+
     // Drain the one-time loads above now: vmcnt is in-order, so a wait for
     // them inside the tile loop would also wait for the stage prefetch.
     __builtin_amdgcn_s_waitcnt(0);
@@ -362,35 +472,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // one tile later, so no MFMA result is waited for at issue time
     // (up to 8 K-steps the tile's fragments are read up front; longer tiles
     // read each K-step's fragments just before its MFMAs, to bound registers)
-    auto mfma_tile = [&](Acc (&acc)[RQ][2][NP], int buf, int dt) {
-        constexpr int KR = KB <= 8 ? KB : NP;   // fragments read per batch
-        v4i Bf[KR];
-        auto rd = [&](int s) {
-            const uint4 u = bl[buf][(dt * KB + s) * 64 + lane];
-            return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
-        };
-        if constexpr (KB <= 8) {
+    // Up to 8 K-steps a tile's fragments are read into registers one tile
+    // ahead of its MFMAs (two register sets alternate), so the LDS latency is
+    // covered by the previous tile; longer tiles read each K-step's fragments
+    // just before its MFMAs, to bound registers.
+    constexpr bool PREF = KB <= 8;
+    constexpr int KR = PREF ? KB : NP;
+    auto rd = [&](int buf, int dt, int s) {
+        const uint4 u = bl[buf][(dt * KB + s) * 64 + lane];
+        return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+    };
+    auto read_tile = [&](v4i (&Bf)[KR], int buf, int dt) {
 #pragma unroll
-            for (int s = 0; s < KB; ++s) Bf[s] = rd(s);
-        }
+        for (int s = 0; s < KR; ++s) Bf[s] = rd(buf, dt, s);
+    };
+    auto mfma_tile = [&](Acc (&acc)[RQ][2][NP], int buf, int dt, v4i (&Bf)[KR]) {
 #pragma unroll
         for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl) acc[qi][0][pl] = acc[qi][1][pl] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KA; ++s) {
-            if constexpr (KB > 8) {
+            if constexpr (!PREF) {
 #pragma unroll
-                for (int pl = 0; pl < NP; ++pl) Bf[pl] = rd(pl * KA + s);
+                for (int pl = 0; pl < NP; ++pl) Bf[pl] = rd(buf, dt, pl * KA + s);
             }
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl) {
-                const v4i &b = KB <= 8 ? Bf[pl * KA + s] : Bf[pl];
+                const v4i &b = PREF ? Bf[pl * KA + s] : Bf[pl];
 #pragma unroll
                 for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        if constexpr (PL == 3)
+                        if constexpr (PL >= 3)
                             acc[qi][h][pl] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(A[qi][h][s]), as_h8(b),
                                                                                     acc[qi][h][pl], 0, 0, 0);
                         else
@@ -406,9 +520,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     };
     // the largest C' over the 8 isometries of each lane's pair; in the f16
     // form the f32 accumulators hold exact integers
-    auto cmax = [&](const Acc (&x)[NP], const Acc (&y)[NP]) -> int {
-        if constexpr (PL == 3) {
-            return (int)max8f(x[0].x, x[0].y, x[0].z, x[0].w, y[0].x, y[0].y, y[0].z, y[0].w);
+    auto cmax = [&](const Acc (&x)[NP], const Acc (&y)[NP]) -> MaxT {
+        if constexpr (PL >= 3) {
+            return max8f(x[0].x, x[0].y, x[0].z, x[0].w, y[0].x, y[0].y, y[0].z, y[0].w);
         } else {
             const v4i cx = cprime(x), cy = cprime(y);
             return max8(cx.x, cx.y, cx.z, cx.w, cy.x, cy.y, cy.z, cy.w);
@@ -437,32 +551,82 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             // software pipeline: the MFMAs of tile dt+1 are issued before the
             // prune test of tile dt, in the same basic block
             Acc acc[2][RQ][2][NP];
-            mfma_tile(acc[0], buf, 0);
+            v4i Bq[2][KR];
+            if constexpr (PREF) read_tile(Bq[0], buf, 0);
+            mfma_tile(acc[0], buf, 0, Bq[0]);
+            if (PREF && DT > 1) read_tile(Bq[1], buf, 1);
 #pragma unroll
             for (int dt = 0; dt < DT; ++dt) {
                 const int cur = dt & 1;
-                if (dt + 1 < DT) mfma_tile(acc[cur ^ 1], buf, dt + 1);
-                const float2 di = dl[buf][dt * kDomTile + (lane & 15)];
+                if (dt + 1 < DT) {
+                    mfma_tile(acc[cur ^ 1], buf, dt + 1, Bq[(dt + 1) & 1]);
+                    // the set of tile dt is free once tile dt's MFMAs were issued
+                    if (PREF && dt + 2 < DT) read_tile(Bq[dt & 1], buf, dt + 2);
+                }
                 bool pass[RQ];
                 bool any = false;
-                int mx[RQ];
+                MaxT mx[RQ];
+                float2 di = make_float2(0.f, 0.f);
+                if constexpr (FT) {
+                    // the threshold is in the accumulators: max over the 8 isometries > 0
 #pragma unroll
-                for (int qi = 0; qi < RQ; ++qi) {
-                    mx[qi] = cmax(acc[cur][qi][0], acc[cur][qi][1]);
-                    const float rhs = fmaf(tn[qi], di.y, fmaf(-bn[qi], di.x, -an[qi]));
-                    // false on NaN: rows past the ranges, domains past the
-                    // pool or the chunk, and ranges already at val 0
-                    pass[qi] = (float)mx[qi] > rhs;
-                    any |= pass[qi];
+                    for (int qi = 0; qi < RQ; ++qi) {
+                        mx[qi] = cmax(acc[cur][qi][0], acc[cur][qi][1]);
+                        pass[qi] = mx[qi] > 0.f;
+                        any |= pass[qi];
+                    }
+                } else {
+                    di = dl[buf][dt * kDomTile + (lane & 15)];
+#pragma unroll
+                    for (int qi = 0; qi < RQ; ++qi) {
+                        mx[qi] = cmax(acc[cur][qi][0], acc[cur][qi][1]);
+                        const float rhs = fmaf(tn[qi], di.y, fmaf(-bn[qi], di.x, -an[qi]));
+                        // false on NaN: rows past the ranges, domains past the
+                        // pool or the chunk, and ranges already at val 0
+                        pass[qi] = (float)mx[qi] > rhs;
+                        any |= pass[qi];
+                    }
+                }
+                // f16 form: issue the next tile's MFMAs one at a time between
+                // groups of 3 VALU of this test (measured ~2 % faster at B = 8)
+                if (PL == 3 && dt + 1 < DT) {
+#pragma unroll
+                    for (int i = 0; i < RQ * 2 * KB; ++i) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+                        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);   // VALU
+                    }
                 }
                 if (__builtin_amdgcn_ballot_w64(any)) {  // rare: exact evaluation, then share the best
                     const int col = dt * kDomTile + (lane & 15);
                     const int p = tbase * kDomTile + col;
-                    const int64_t sd4 = (int64_t)di.x, A = dla[buf][col];  // Sd4 < 2^24: exact in float
+                    if constexpr (FT) di = dl[buf][col];
+                    const int64_t sd4 = (int64_t)di.x, Ad = dla[buf][col];  // Sd4 < 2^24: exact in float
+                    // FT: the domain tile's fragment again, for acc1 without the threshold
+                    v4i bt1 = v4i{0, 0, 0, 0};
+                    int64_t ed = 0;
+                    if constexpr (FT) {
+                        const uint4 u = bl[buf][(dt * KB) * 64 + lane];
+                        bt1 = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+                        ed = sd4 - (int64_t)n * round_mean(sd4, n);
+                    }
 #pragma unroll
                     for (int qi = 0; qi < RQ; ++qi) {
                         bool imp = false;
-                        if (pass[qi]) imp = confirm_pair(mx[qi], p, sd4, A, sr[qi], cr[qi], n, sl, sc, best[qi], bp[qi], bk[qi]);
+                        if constexpr (FT) {
+                            // all lanes: the MFMA is wave-wide
+                            const v4i z = v4i{0, 0, 0, 0};
+                            const v4i a0 = lane < 32 ? A[qi][0][0] : z, a1 = lane < 32 ? A[qi][1][0] : z;
+                            const v4f x0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(a0), as_h8(bt1), v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                            const v4f x1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(a1), as_h8(bt1), v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                            if (pass[qi]) {
+                                const float c1 = max8f(x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w);
+                                const int64_t er = (int64_t)sr[qi] - (int64_t)n * round_mean(sr[qi], n);
+                                imp = confirm_bx((int64_t)n * (int64_t)c1 - er * ed, p, Ad, cr[qi], sl, sc, best[qi],
+                                                 bp[qi], bk[qi]);
+                            }
+                        } else if (pass[qi]) {
+                            imp = confirm_pair((int)mx[qi], p, sd4, Ad, sr[qi], cr[qi], n, sl, sc, best[qi], bp[qi], bk[qi]);
+                        }
                         if (__builtin_amdgcn_ballot_w64(imp)) {
                             // the 16 lanes holding this range share their best: the
                             // threshold may use it because a pair is only rejected
@@ -473,6 +637,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                 tn[qi] = tn_from(gb, cr[qi], sc, tfac);
                                 if (SHARE && (lane & 15) == 0) gbest_push(&ri[rr[qi]].gbest, gb);
                             }
+                            if constexpr (FT) build_thr(qi);   // uniform: inside a ballot
                         }
                     }
                 }
@@ -480,11 +645,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         }
         if (stg + 1 < nstage) swrite(buf ^ 1);
 #pragma unroll
-        for (int qi = 0; qi < RQ; ++qi)
-            if (gl[qi] < tb[qi]) {
+        for (int qi = 0; qi < RQ; ++qi) {
+            const bool changed = gl[qi] < tb[qi];
+            if (changed) {
                 tb[qi] = gl[qi];
                 tn[qi] = tn_shared(gl[qi], cr[qi], sc, tfac);
             }
+            if (FT && __builtin_amdgcn_ballot_w64(changed)) build_thr(qi);
+        }
         __syncthreads();
     }
   }
@@ -555,6 +723,14 @@ hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
         FIC_SEARCH(16, 2, 1, 1, 2);
         FIC_SEARCH(16, 2, 2, 1, 1);
         FIC_SEARCH(16, 2, 1, 2, 1);
+    }
+    if (B == 4 || B == 2) {
+        FIC_SEARCH(1, 4, 2, 8, 3);
+        FIC_SEARCH(1, 4, 2, 16, 3);
+        FIC_SEARCH(1, 4, 1, 8, 4);
+        FIC_SEARCH(1, 4, 2, 8, 4);
+        FIC_SEARCH(1, 4, 3, 8, 3);
+        FIC_SEARCH(1, 4, 4, 8, 2);
     }
 #undef FIC_SEARCH
     return hipErrorInvalidValue;

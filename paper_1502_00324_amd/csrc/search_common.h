@@ -79,15 +79,13 @@ __device__ inline SConst make_sconst(const SSet &ss) {
     return c;
 }
 
-// Exact evaluation of one (range, domain) pair given C'max, the domain
-// moments (Sd4, A) and the range moments (Sr, Cr), all exact integers.
-// Updates the lane's running best with a strict comparison (along a lane the
-// domain index only grows, so equal values keep the earlier domain) and
-// returns whether it improved.
-__device__ __forceinline__ bool confirm_pair(int cmax, int p, int64_t sd4, int64_t A, int64_t sr, int64_t cr, int n,
-                                             const SLds &ss, const SConst &sc, int64_t &best, int &bp, int &bk) {
-    const int64_t x4 = (int64_t)cmax + 128 * sd4 + 512 * sr - 65536 * (int64_t)n;
-    const int64_t bx = (int64_t)n * x4 - sr * sd4;
+// Exact evaluation of one (range, domain) pair, all in integers: from
+// Bx = n X4 - Sr Sd4, A and Cr (confirm_bx), or from C'max and the moments
+// Sd4, A, Sr, Cr (confirm_pair).  Updates the lane's running best with a
+// strict comparison (along a lane the domain index only grows, so equal
+// values keep the earlier domain) and returns whether it improved.
+__device__ __forceinline__ bool confirm_bx(int64_t bx, int p, int64_t A, int64_t cr, const SLds &ss,
+                                           const SConst &sc, int64_t &best, int &bp, int &bk) {
     const int64_t den = sc.den;
     const int64_t lhs = 8 * den * bx;
     // midpoint rule: s_{j+1} beats s_j iff 8 den Bx > A (num_j + num_{j+1}); the
@@ -107,6 +105,20 @@ __device__ __forceinline__ bool confirm_pair(int cmax, int p, int64_t sd4, int64
         return true;
     }
     return false;
+}
+
+__device__ __forceinline__ bool confirm_pair(int cmax, int p, int64_t sd4, int64_t A, int64_t sr, int64_t cr, int n,
+                                             const SLds &ss, const SConst &sc, int64_t &best, int &bp, int &bk) {
+    const int64_t x4 = (int64_t)cmax + 128 * sd4 + 512 * sr - 65536 * (int64_t)n;
+    return confirm_bx((int64_t)n * x4 - sr * sd4, p, A, cr, ss, sc, best, bp, bk);
+}
+
+// Rounded block mean round(s/n) (half up): the centre of the operands of the
+// fused-threshold form.
+__device__ inline int round_mean(int64_t s, int n) { return (int)((2 * s + n) / (2 * n)); }
+
+__device__ inline uint32_t pack_h2(_Float16 lo, _Float16 hi) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
 }
 
 // (1 - 2^-20) / n, the final factor of the prune threshold below.

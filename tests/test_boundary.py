@@ -133,7 +133,7 @@ def test_level_engine_resolution():
     assert [fic.level_engine(M, B) for B in (2, 4, 8, 16, 32)] == [H, H, X, I8, I8]
     assert [fic.level_engine(I8, B) for B in (2, 4, 8, 16, 32)] == [F, I8, I8, I8, I8]
     assert [fic.level_engine(H, B) for B in (2, 4, 8, 16, 32)] == [H, H, H, H, F]
-    assert [fic.level_engine(X, B) for B in (2, 4, 8, 16, 32)] == [F, F, X, X, F]
+    assert [fic.level_engine(X, B) for B in (2, 4, 8, 16, 32)] == [X, X, X, X, F]
     assert all(fic.level_engine(F, B) == F for B in (2, 4, 8, 16, 32))
     assert fic.lib().fic_level_engine(5, 8) == fic.FIC_E_INVALID
     assert fic.lib().fic_level_engine(M, 12) == fic.FIC_E_INVALID

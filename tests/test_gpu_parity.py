@@ -107,6 +107,21 @@ def test_b32_extreme_magnitudes(ctx, engine):
     np.testing.assert_array_equal(dec, oracle.decode(160, 128, ref, 4))
 
 
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+def test_small_blocks_extreme_magnitudes(ctx, engine):
+    """Pixels 0 or 255 only at B = 4 and 2: the mean-centred operands of the
+    one-step levels reach +-255 and +-1020, the cross terms their largest
+    magnitudes, and most ranges split (S with 0 and 1 only keeps errors up)."""
+    rng = np.random.default_rng(8)
+    img = (rng.integers(0, 2, (48, 80)) * 255).astype(np.uint8)
+    levels = [(4, 1), (2, 1)]
+    for s_num, s_den in ((K16, 16), ((0, 1), 1)):
+        got, dec = gpu_run(ctx, img, params(levels, (1, 4), 0, s_num, s_den, (20, 1), engine), iters=4)
+        ref = oracle_run(img, levels, (1, 4), 0, list(s_num), s_den, (20, 1))
+        assert_levels_equal(got, ref, "small_extreme")
+        np.testing.assert_array_equal(dec, oracle.decode(80, 48, ref, 4))
+
+
 @pytest.mark.parametrize("engine", [fic.ENGINE_MFMA, fic.ENGINE_FP32], ids=["mfma", "fp32"])
 def test_b32_xcd_chunks(ctx, engine):
     """512 x 512 at B = 32, L = 2: ~25 k domains in ~40 chunks, enough for the

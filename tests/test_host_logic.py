@@ -82,11 +82,11 @@ def test_engine_choice(runs):
     assert i8.count("k_mfma_search") == 2 * 3 and "k_f16_search" not in i8
     assert h.count("k_f16_search") == 2 * 3 and "k_mfma_search" not in h
     # the int8 engine: raw form at B=4, hi/lo planes at 8 and 16; the f16
-    # 16x16 form at B=8 and 16 only (B=4 falls back to FP32)
+    # 16x16 engine: plain f16 at B=8 and 16, the fused threshold at B=4
     assert runs["mixed_i8_3lv"]["forms"] == [2, 2, 1] * 2
     x = kinds(runs["mixed_f16x_3lv"])
-    assert x.count("k_mfma_search") == 2 * 2 and x.count("k_fp32_search") == 2 and "k_f16_search" not in x
-    assert runs["mixed_f16x_3lv"]["forms"] == [3, 3] * 2
+    assert x.count("k_mfma_search") == 2 * 3 and "k_fp32_search" not in x and "k_f16_search" not in x
+    assert runs["mixed_f16x_3lv"]["forms"] == [3, 3, 4] * 2
     # B=32 levels take the int8 planes form: no FP32 search in the default mix
     b32 = kinds(runs["mixed_b32_4lv"])
     assert "k_fp32_search" not in b32 and b32.count("k_f16_search") == b32.count("k_mfma_search") // 3
