@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--graphs", action="store_true",
                     help="replay each encode as a captured HIP graph (stage times then come from extra eager steps)")
     ap.add_argument("--fp32-steps", type=int, default=2, help="timed steps of the plain FP32 engine (0 skips)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in default tile shapes instead of running the autotuner first")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample budget (0 skips)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM counter calibration for profiling runs)")
@@ -150,6 +152,19 @@ def main():
                    fic.ENGINE_MFMA_F16_16X16: "mfma_f16_16x16"}
     p = mk(engine)
     bufs = ctx.alloc_encode([(im.shape[1], im.shape[0]) for im in images], p, dev)
+    # tile shapes: the library's autotuner times every compiled shape of each
+    # matrix level on these images (untimed here) and keeps the fastest
+    tiles = {}
+    if not args.no_autotune:
+        ctx.autotune(imgs, p, bufs, reps=3)
+    tune = ctx.get_tuning()
+    for (B, L) in wl.levels:
+        name = ENGINE_NAME[fic.level_engine(engine, B)]
+        if name in fic.FORM_NAMES:
+            f = fic.FORM_NAMES.index(name)
+            c = max(0, tune.choice[f][B.bit_length() - 1])
+            tiles["B=%d" % B] = {"form": name, "candidate": c, "of": fic.shape_count(f, B),
+                                 "pl_rq_dt_wpe": list(fic.shape_describe(f, B, c))}
     if args.graphs:
         ctx.set_graphs(4)
     for _ in range(args.warmup):
@@ -277,7 +292,8 @@ def main():
                    "pool_max": wl.pool_max, "split_rms": wl.split_rms[0],
                    "engine": args.engine + ": " + ", ".join("B=%d %s" % (B, ENGINE_NAME[fic.level_engine(engine, B)])
                                                             for (B, L) in wl.levels),
-                   "parallelism": "single GPU", "graph_replay": bool(args.graphs)},
+                   "parallelism": "single GPU", "graph_replay": bool(args.graphs),
+                   "tiles": tiles, "autotuned": not args.no_autotune},
         "comparisons_per_step": triples,
         "levels": [{"B": B, "ranges": R, "pool": P, "comparisons": R * P * 8} for (B, R, P) in counts[0]]
         if len(counts) == 1 else None,

@@ -173,6 +173,43 @@ int fic_ctx_set_timing(fic_ctx *ctx, int enable);
 /* Waits for the recorded events, writes their sums to *out and clears them. */
 int fic_ctx_read_timing(fic_ctx *ctx, fic_timing *out);
 
+/* Tile shapes of the matrix search kernels.  Each matrix form has, per block
+ * size B, a list of compiled shapes (operand form, range quads per wave,
+ * domain tiles per LDS stage, waves per SIMD the register allocation aims
+ * at); candidate 0 is the measured default.  A context keeps one choice per
+ * (form, log2 B) that every later plan of that context uses; all shapes give
+ * identical codes.  Forms: the 16-row kernel in int8 (MFMA_I8), the 16-row
+ * kernel in f16 (MFMA_F16_16X16), the 32x32 f16 kernel (MFMA_F16).  The
+ * FIC_MFMA_SHAPE / FIC_F16_SHAPE environment overrides take precedence. */
+enum { FIC_FORM_I8 = 0, FIC_FORM_F16_16X16 = 1, FIC_FORM_F16 = 2, FIC_FORMS = 3 };
+typedef struct {
+    int32_t choice[FIC_FORMS][6];    /* candidate per form and log2(B); -1 = the default */
+} fic_tuning;
+
+/* Number of compiled shapes for (form, B); 0 when the form has none. */
+int fic_shape_count(int32_t form, int32_t B);
+/* out[4] = (operand form, range quads per wave, tiles per stage, waves per
+ * SIMD) of candidate index; FIC_E_INVALID when it does not exist.  The
+ * operand form is 1 raw int8, 2 int8 hi/lo planes, 3 f16, 4 f16 with the
+ * fused threshold, 0 for the 32x32 f16 kernel. */
+int fic_shape_describe(int32_t form, int32_t B, int32_t index, int32_t *out);
+/* The context's current choices (all -1 after fic_ctx_create). */
+int fic_ctx_get_tuning(fic_ctx *ctx, fic_tuning *out);
+/* Replaces the context's choices; every entry must be -1 or an existing
+ * candidate (FIC_E_INVALID otherwise, nothing changed).  Drops cached graphs. */
+int fic_ctx_set_tuning(fic_ctx *ctx, const fic_tuning *in);
+/* Autotuner: for every level of p searched by a matrix form, times each
+ * compiled shape of that (form, B) on these images and keeps the fastest in
+ * the context (entries of other forms and sizes keep their values); *out,
+ * if not null, receives the resulting choices.  Per candidate: one warm-up
+ * encode, then reps (1..100) encodes with stage timing, scored by the summed
+ * operand preparation, search and finalisation time of that level.  The
+ * buffers are those of fic_encode and end up holding an ordinary encode.
+ * Blocks the host until done; stage timing must be off (FIC_E_INVALID);
+ * drops cached graphs.  Errors of the encodes are returned as they are. */
+int fic_autotune(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_params *p, fic_pool *pools,
+                 fic_level_codes *codes, int32_t reps, fic_stream stream, fic_tuning *out);
+
 /* ---- host-only helpers (no device needed) ----------------------------- */
 
 /* FIC_OK if params are usable for a width x height image:

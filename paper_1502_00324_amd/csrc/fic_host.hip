@@ -168,6 +168,13 @@ int engine_for(int engine, int B) {
     return E_FP32;
 }
 
+// floor(log2 v) for v in 1..32: the slot of block size v
+int log2i(int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v && l < 5) ++l;
+    return l;
+}
+
 int check_sset(const int32_t *num, int count, int den) {
     if (!num || count < 1 || count > kMaxS || den < 1 || den > 1024) return FIC_E_INVALID;
     for (int k = 0; k < count; ++k) {
@@ -238,7 +245,7 @@ struct LevelPlan {
 // of one encode lays them out identically, so later levels reuse them).
 // Returns false when a launch of the batch would need 2^31 or more workgroups.
 bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int engine, int level0,
-                bool build_integ, int pool_key) {
+                bool build_integ, int pool_key, const int8_t (*tune)[6]) {
     bool fits = true;
     const int n = (int)in.size();
     pl.h.assign(n, ImgLvl());
@@ -250,6 +257,8 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
     const int eng = do_search ? engine_for(engine, B) : E_FP32;
     pl.bh.B = B;
     pl.bh.eng = eng;
+    const int form = form_of_engine(eng);
+    if (form >= 0) pl.bh.shape = pick_shape(form, B, tune ? tune[form][log2i(B)] : -1);
     pl.bh.pool_key = pool_key;
     pl.bh.L = in[0].L;
     pl.bh.KS = KS;
@@ -343,8 +352,8 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
             if (eng != E_FP32) {
                 // int8: A fragments per quad and half; f16: per quad (32 rows)
                 const bool f16 = eng == E_F16;
-                d.geo = f16 ? f16_geometry(d.B, d.range_cap, d.pool_cap)
-                            : mfma_geometry(d.B, d.range_cap, d.pool_cap, eng == E_H16);
+                d.geo = f16 ? f16_geometry(d.B, d.range_cap, d.pool_cap, pl.bh.shape)
+                            : mfma_geometry(d.B, d.range_cap, d.pool_cap, pl.bh.shape);
                 const int nquads = d.geo.nrg * (d.geo.rpw / 4);
                 const int tile = f16 ? kDomTile32 : kDomTile;
                 const int ntiles = (int)cdiv(d.pool_cap, tile);
@@ -642,12 +651,6 @@ int reserve(fic_ctx *ctx, const size_t *bytes) {
     return FIC_OK;
 }
 
-static int log2i(int v) {
-    int l = 0;
-    while ((1 << (l + 1)) <= v && l < 5) ++l;
-    return l;
-}
-
 static hipEvent_t take_event(Timer *t) {
     if (!t->spare.empty()) {
         hipEvent_t e = t->spare.back();
@@ -692,6 +695,33 @@ static void destroy_timer(Timer *t) {
     recycle(t);
     for (hipEvent_t e : t->spare) (void)hipEventDestroy(e);
     delete t;
+}
+
+// ---------------------------------------------------------------- tile shapes
+int mfma_shape_count(int B, bool f16);
+bool mfma_shape_at(int B, bool f16, int index, TileShape &out);
+TileShape mfma_pick(int B, bool f16, int choice);
+int f16_shape_count(int B);
+bool f16_shape_at(int B, int index, TileShape &out);
+TileShape f16_pick(int B, int choice);
+
+int form_of_engine(int eng) { return eng == E_I8 ? F_I8 : eng == E_H16 ? F_H16 : eng == E_F16 ? F_F16 : -1; }
+
+int shape_count(int form, int B) {
+    if (form == F_I8) return mfma_supported(B) ? mfma_shape_count(B, false) : 0;
+    if (form == F_H16) return mfma_shape_count(B, true);
+    if (form == F_F16) return f16_supported(B) ? f16_shape_count(B) : 0;
+    return 0;
+}
+
+bool shape_at(int form, int B, int index, TileShape &out) {
+    if (form == F_I8 || form == F_H16) return mfma_shape_at(B, form == F_H16, index, out);
+    if (form == F_F16) return f16_shape_at(B, index, out);
+    return false;
+}
+
+TileShape pick_shape(int form, int B, int choice) {
+    return form == F_F16 ? f16_pick(B, choice) : mfma_pick(B, form == F_H16, choice);
 }
 
 }  // namespace fic
@@ -770,6 +800,7 @@ int fic_ctx_create(fic_ctx **out, int device) {
     fic_ctx *ctx = new fic_ctx;
     memset(ctx, 0, sizeof(*ctx));
     ctx->device = device;
+    memset(ctx->tune, -1, sizeof(ctx->tune));
     build_table();
     if (hipMalloc(&ctx->table, sizeof(g_table)) != hipSuccess) {
         delete ctx;
@@ -829,6 +860,93 @@ int fic_ctx_set_graphs(fic_ctx *ctx, int32_t max_graphs) {
 
 int fic_ctx_graph_count(fic_ctx *ctx) { return ctx && ctx->graphs ? (int)ctx->graphs->e.size() : 0; }
 
+int fic_shape_count(int32_t form, int32_t B) {
+    if (form < 0 || form >= F_NUM || B < 1 || B > 32 || !pow2(B)) return 0;
+    return shape_count(form, B);
+}
+
+int fic_shape_describe(int32_t form, int32_t B, int32_t index, int32_t *out) {
+    if (!out || fic_shape_count(form, B) <= index || index < 0) return FIC_E_INVALID;
+    TileShape t;
+    if (!shape_at(form, B, index, t)) return FIC_E_INVALID;
+    out[0] = t.pl;
+    out[1] = t.rq;
+    out[2] = t.dt;
+    out[3] = t.wpe;
+    return FIC_OK;
+}
+
+int fic_ctx_get_tuning(fic_ctx *ctx, fic_tuning *out) {
+    if (!ctx || !out) return FIC_E_INVALID;
+    for (int f = 0; f < F_NUM; ++f)
+        for (int l = 0; l < 6; ++l) out->choice[f][l] = ctx->tune[f][l];
+    return FIC_OK;
+}
+
+int fic_ctx_set_tuning(fic_ctx *ctx, const fic_tuning *in) {
+    if (!ctx || !in) return FIC_E_INVALID;
+    for (int f = 0; f < F_NUM; ++f)
+        for (int l = 0; l < 6; ++l) {
+            const int c = in->choice[f][l];
+            if (c < -1 || c >= fic_shape_count(f, 1 << l)) return FIC_E_INVALID;
+        }
+    for (int f = 0; f < F_NUM; ++f)
+        for (int l = 0; l < 6; ++l) ctx->tune[f][l] = (int8_t)in->choice[f][l];
+    if (ctx->graphs) drop_graphs(ctx->graphs);
+    return FIC_OK;
+}
+
+int fic_autotune(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_params *p, fic_pool *pools,
+                 fic_level_codes *codes, int32_t reps, fic_stream stream, fic_tuning *out) {
+    if (!ctx || !p || reps < 1 || reps > 100 || ctx->timer) return FIC_E_INVALID;
+    // first an ordinary encode: validates everything and warms the scratch
+    int st = fic_encode(ctx, imgs, n_images, p, pools, codes, stream);
+    if (st != FIC_OK) return st;
+    struct Entry { int form, slot, count, best; double best_ms; };
+    std::vector<Entry> ent;
+    int maxc = 0;
+    for (int l = 0; l < p->levels; ++l) {
+        const int B = p->block0 >> l, form = form_of_engine(engine_for(p->engine, B));
+        const int c = form >= 0 ? shape_count(form, B) : 0;
+        if (c > 1) {
+            ent.push_back(Entry{form, log2i(B), c, 0, 1e300});
+            maxc = std::max(maxc, c);
+        }
+    }
+    int8_t saved[3][6];
+    memcpy(saved, ctx->tune, sizeof(saved));
+    for (int i = 0; i < maxc && st == FIC_OK; ++i) {
+        for (const Entry &e : ent) ctx->tune[e.form][e.slot] = (int8_t)std::min(i, e.count - 1);
+        st = fic_encode(ctx, imgs, n_images, p, pools, codes, stream);   // warm-up of this candidate
+        if (st != FIC_OK) break;
+        st = fic_ctx_set_timing(ctx, 1);
+        for (int r = 0; r < reps && st == FIC_OK; ++r) st = fic_encode(ctx, imgs, n_images, p, pools, codes, stream);
+        fic_timing t;
+        const int st2 = st == FIC_OK ? fic_ctx_read_timing(ctx, &t) : FIC_OK;
+        fic_ctx_set_timing(ctx, 0);
+        if (st == FIC_OK) st = st2;
+        if (st != FIC_OK) break;
+        for (Entry &e : ent) {
+            if (i >= e.count) continue;
+            const double ms = t.ms[FIC_T_PREP][e.slot] + t.ms[FIC_T_SEARCH][e.slot] + t.ms[FIC_T_FINAL][e.slot];
+            if (ms < e.best_ms) {
+                e.best_ms = ms;
+                e.best = i;
+            }
+        }
+    }
+    if (st != FIC_OK) {
+        memcpy(ctx->tune, saved, sizeof(saved));
+        return st;
+    }
+    for (const Entry &e : ent) ctx->tune[e.form][e.slot] = (int8_t)e.best;
+    if (ctx->graphs) drop_graphs(ctx->graphs);
+    // leave the buffers holding an encode with the chosen shapes
+    st = fic_encode(ctx, imgs, n_images, p, pools, codes, stream);
+    if (st == FIC_OK && out) fic_ctx_get_tuning(ctx, out);
+    return st;
+}
+
 int fic_ctx_set_timing(fic_ctx *ctx, int enable) {
     if (!ctx) return FIC_E_INVALID;
     int st = enter(ctx);
@@ -875,7 +993,7 @@ int fic_build_domain_pool(fic_ctx *ctx, const fic_image *img, int32_t B, int32_t
     std::vector<ImgIn> in(1);
     in[0] = ImgIn{img, B, L, pct.num, pct.den, pool_max, out, nullptr, nullptr, 0, nullptr, nullptr, nullptr};
     std::vector<LevelPlan> plans(1);
-    if (!plan_level(plans[0], in, false, FIC_ENGINE_MFMA, 0, true, pool_key)) return FIC_E_NOMEM;
+    if (!plan_level(plans[0], in, false, FIC_ENGINE_MFMA, 0, true, pool_key, ctx->tune)) return FIC_E_NOMEM;
     st = reserve_plans(ctx, plans, 0);
     if (st != FIC_OK) return st;
     bind(ctx, plans[0]);
@@ -904,7 +1022,7 @@ int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, c
     in[0] = ImgIn{img, B, B, 0, 1, 0, const_cast<fic_pool *>(pool), ranges_xy, n_ranges, range_capacity, out,
                   children_xy, n_children};
     std::vector<LevelPlan> plans(1);
-    if (!plan_level(plans[0], in, true, engine, 0, true, FIC_POOL_ENTROPY)) return FIC_E_NOMEM;
+    if (!plan_level(plans[0], in, true, engine, 0, true, FIC_POOL_ENTROPY, ctx->tune)) return FIC_E_NOMEM;
     plans[0].bh.ss = make_sset(s_num, s_count, s_den);
     plans[0].bh.rms = split_rms;
     plans[0].bh.is_last = is_last ? 1 : 0;
@@ -966,7 +1084,7 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
                           cl->xy, cl->count, (img->width / B) * (img->height / B), cl,
                           last ? nullptr : codes[i * NL + l + 1].xy, last ? nullptr : codes[i * NL + l + 1].count};
         }
-        if (!plan_level(plans[l], in, true, p->engine, l == 0, l == 0, p->pool_key)) return FIC_E_NOMEM;
+        if (!plan_level(plans[l], in, true, p->engine, l == 0, l == 0, p->pool_key, ctx->tune)) return FIC_E_NOMEM;
         plans[l].bh.ss = make_sset(p->s_num[l], p->s_count[l], p->s_den[l]);
         plans[l].bh.rms = p->split_rms[l];
         plans[l].bh.is_last = last ? 1 : 0;

@@ -106,6 +106,7 @@ struct fic_ctx {
     fic::GraphCache *graphs;     // non-null once graph replay has been enabled
     void *staging;               // pinned host buffer for the level tables
     size_t staging_bytes;
+    int8_t tune[3][6];           // tile-shape candidate per (form, log2 B), -1 = default
     hipEvent_t staging_event;    // last copy out of the staging buffer
 };
 
@@ -121,6 +122,19 @@ void mark(fic_ctx *ctx, int kind, int B, hipStream_t st);
 inline void *sp(fic_ctx *ctx, Slot s) { return ctx->slot[s].ptr; }
 
 // ---------------------------------------------------------------- search geometry
+// Tile shape of a matrix search kernel: operand form (16-row engine only),
+// range quads per wave, domain tiles per LDS stage, waves per SIMD the
+// register allocation aims at.  Each (form, B) has a list of compiled shapes;
+// candidate 0 is the measured default, a context's tuning picks another.
+struct TileShape { int pl, rq, dt, wpe; };
+enum Form { F_I8 = 0, F_H16 = 1, F_F16 = 2, F_NUM = 3 };   // = FIC_FORM_*
+int shape_count(int form, int B);
+bool shape_at(int form, int B, int index, TileShape &out);
+// The shape a plan uses: an FIC_MFMA_SHAPE / FIC_F16_SHAPE override if it
+// names a compiled shape, else candidate `choice` (>= 0), else the default.
+TileShape pick_shape(int form, int B, int choice);
+int form_of_engine(int eng);   // Engine -> Form, -1 for FP32
+
 struct MfmaGeom {
     int pl;       // operand form: 1 = raw pixels (K = 4B^2), 2 = decimated hi/lo planes (K = 2 B^2)
     int ka;       // 64-deep K-steps of a range fragment (per half)
@@ -134,8 +148,8 @@ struct MfmaGeom {
     int nslot;    // partial results per range
     int nwg;      // workgroups
 };
-MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, bool f16);   // 16-row engine (int8 or f16 form)
-MfmaGeom f16_geometry(int B, int range_cap, int pool_cap);    // f16 engine
+MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, const TileShape &sh);   // 16-row engine
+MfmaGeom f16_geometry(int B, int range_cap, int pool_cap, const TileShape &sh);    // 32x32 f16 engine
 void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt);
 
 // Range group, chunk walk and partial-result slot of search workgroup lb.
@@ -274,6 +288,7 @@ struct BatchHost {
     BatchDev dev;
     int blocks[K_NUM];   // total workgroups per kind
     int B, L, KS, any_cap, eng, pool_key;
+    TileShape shape;     // matrix engines: the tile shape every image of the level uses
     int fused_sel;       // every image has <= kFusedSelMax candidates: one-workgroup selection
     SSet ss;
     fic_ratio rms;

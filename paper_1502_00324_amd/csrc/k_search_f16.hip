@@ -47,19 +47,34 @@ static const F16Shape kF16Shapes[] = {
     {8, 2, 4, 2}, {8, 1, 4, 3}, {8, 1, 8, 2}, {8, 2, 2, 2},
     {16, 1, 1, 3}, {16, 1, 2, 2},
 };
-static F16Shape f16_shape(int B) {
+// Candidates of B in table order; index 0 is the default.
+int f16_shape_count(int B) {
+    int c = 0;
+    for (const F16Shape &s : kF16Shapes) c += s.B == B;
+    return c;
+}
+bool f16_shape_at(int B, int index, TileShape &out) {
+    int c = 0;
+    for (const F16Shape &s : kF16Shapes)
+        if (s.B == B && c++ == index) {
+            out = TileShape{0, s.rq, s.dt, s.wpe};
+            return true;
+        }
+    return false;
+}
+TileShape f16_pick(int B, int choice) {
     const char *e = getenv("FIC_F16_SHAPE");
     int rq = 0, dt = 0, wpe = 0;
     if (e && sscanf(e, "%d,%d,%d", &rq, &dt, &wpe) == 3)
         for (const F16Shape &s : kF16Shapes)
-            if (s.B == B && s.rq == rq && s.dt == dt && s.wpe == wpe) return s;
-    for (const F16Shape &s : kF16Shapes)
-        if (s.B == B) return s;
-    return F16Shape{B, 1, 1, 1};
+            if (s.B == B && s.rq == rq && s.dt == dt && s.wpe == wpe) return TileShape{0, s.rq, s.dt, s.wpe};
+    TileShape t{0, 1, 1, 1};
+    if (choice >= 0 && f16_shape_at(B, choice, t)) return t;
+    f16_shape_at(B, 0, t);
+    return t;
 }
 
-MfmaGeom f16_geometry(int B, int range_cap, int pool_cap) {
-    const F16Shape sh = f16_shape(B);
+MfmaGeom f16_geometry(int B, int range_cap, int pool_cap, const TileShape &sh) {
     MfmaGeom g;
     g.pl = 0;
     g.ka = (B * B + 15) / 16;   // B = 2: the 4 positions zero-padded to one step
@@ -222,8 +237,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     __builtin_amdgcn_s_waitcnt(0);
 
     uint4 pre[PER_T];
-    float2 dpre = make_float2(0.f, 0.f);
-    int64_t apre = 0;
+    // per-domain moments of a stage: DT * kDomTile32 entries over the 256 threads
+    constexpr int PER_D = (DT * kDomTile32 + 255) / 256;
+    float2 dpre[PER_D];
+    int64_t apre[PER_D];
     int t0 = 0, t1 = 0;
     auto gload = [&](int stg) {
         const int tbase = t0 + stg * DT;
@@ -233,18 +250,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             pre[i] = tbase + e / (KS * 64) < t1 ? bfrag[(size_t)tbase * KS * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
         }
         // tiles past the chunk end get NaN moments: no pair on them passes
-        if (tid < DT * kDomTile32) {
-            const int p = tbase * kDomTile32 + tid;
-            dpre = tbase + tid / kDomTile32 < t1 ? dinfo[p] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
-            apre = p < P ? pa[p] : 0;
+#pragma unroll
+        for (int i = 0; i < PER_D; ++i) {
+            const int e = tid + 256 * i;
+            if (e < DT * kDomTile32) {
+                const int p = tbase * kDomTile32 + e;
+                dpre[i] = tbase + e / kDomTile32 < t1 ? dinfo[p] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+                apre[i] = p < P ? pa[p] : 0;
+            }
         }
     };
     auto swrite = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
-        if (tid < DT * kDomTile32) {
-            dl[buf][tid] = dpre;
-            dla[buf][tid] = apre;
+#pragma unroll
+        for (int i = 0; i < PER_D; ++i) {
+            const int e = tid + 256 * i;
+            if (e < DT * kDomTile32) {
+                dl[buf][e] = dpre[i];
+                dla[buf][e] = apre[i];
+            }
         }
     };
     // the tile's fragments are read up front (in groups of up to 8 K-steps),
@@ -400,7 +425,7 @@ static hipError_t launch_f16_t(const BatchHost &b, hipStream_t st) {
 hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st) {
     if (b.blocks[K_SEARCH] == 0) return hipSuccess;
     const int B = b.B;
-    const F16Shape sh = f16_shape(B);
+    const TileShape sh = b.shape;
 #define FIC_F16(KS, RQ, DT, WPE) \
     if (sh.rq == RQ && sh.dt == DT && sh.wpe == WPE) return launch_f16_t<KS, RQ, DT, WPE>(b, st)
     if (B == 2) {

@@ -91,15 +91,32 @@ static const Shape kShapes[] = {
     {4, 4, 2, 8, 3}, {4, 4, 2, 16, 3}, {4, 4, 1, 8, 4}, {4, 4, 2, 8, 4}, {4, 4, 3, 8, 3}, {4, 4, 4, 8, 2},
     {2, 4, 2, 8, 3},
 };
-static Shape mfma_shape(int B, bool f16) {
+// Candidates of (B, int8 or f16 class) in table order; index 0 is the default.
+int mfma_shape_count(int B, bool f16) {
+    int c = 0;
+    for (const Shape &s : kShapes) c += s.B == B && (s.pl >= 3) == f16;
+    return c;
+}
+bool mfma_shape_at(int B, bool f16, int index, TileShape &out) {
+    int c = 0;
+    for (const Shape &s : kShapes)
+        if (s.B == B && (s.pl >= 3) == f16 && c++ == index) {
+            out = TileShape{s.pl, s.rq, s.dt, s.wpe};
+            return true;
+        }
+    return false;
+}
+TileShape mfma_pick(int B, bool f16, int choice) {
     const char *e = getenv("FIC_MFMA_SHAPE");
     int pl = 0, rq = 0, dt = 0, wpe = 0;
     if (e && sscanf(e, "%d,%d,%d,%d", &pl, &rq, &dt, &wpe) == 4)
         for (const Shape &s : kShapes)
-            if (s.B == B && (s.pl >= 3) == f16 && s.pl == pl && s.rq == rq && s.dt == dt && s.wpe == wpe) return s;
-    for (const Shape &s : kShapes)
-        if (s.B == B && (s.pl >= 3) == f16) return s;
-    return Shape{B, 1, 1, 1, 1};
+            if (s.B == B && (s.pl >= 3) == f16 && s.pl == pl && s.rq == rq && s.dt == dt && s.wpe == wpe)
+                return TileShape{s.pl, s.rq, s.dt, s.wpe};
+    TileShape t{1, 1, 1, 1};
+    if (choice >= 0 && mfma_shape_at(B, f16, choice, t)) return t;
+    mfma_shape_at(B, f16, 0, t);
+    return t;
 }
 
 // Work split (both matrix engines).  A workgroup owns rpw ranges (a range
@@ -153,9 +170,8 @@ void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt) 
     g.nwg = g.nrg * g.nslot;
 }
 
-MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, bool f16) {
+MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, const TileShape &sh) {
     MfmaGeom g;
-    const Shape sh = mfma_shape(B, f16);
     g.pl = sh.pl;
     g.ka = sh.pl == 2 ? B * B / 64 : sh.pl == 3 ? B * B / 32 : sh.pl == 4 ? 1 : B * B / 16;
     g.kt = sh.pl == 2 ? 2 * g.ka : g.ka;
@@ -443,8 +459,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     __builtin_amdgcn_s_waitcnt(0);
 
     uint4 pre[PER_T];
-    float2 dpre = make_float2(0.f, 0.f);
-    int64_t apre = 0;
+    // per-domain moments of a stage: DT * kDomTile entries over the 256 threads
+    constexpr int PER_D = (DT * kDomTile + 255) / 256;
+    float2 dpre[PER_D];
+    int64_t apre[PER_D];
     int t0 = 0, t1 = 0;  // tile range of the chunk being streamed
     auto gload = [&](int stg) {
         const int tbase = t0 + stg * DT;
@@ -454,18 +472,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             pre[i] = tbase + e / (KB * 64) < t1 ? bfrag[(size_t)tbase * KB * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
         }
         // tiles past the chunk end get NaN moments: no pair on them passes
-        if (tid < DT * kDomTile) {
-            const int p = tbase * kDomTile + tid;
-            dpre = tbase + tid / kDomTile < t1 ? dinfo[p] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
-            apre = p < P ? pa[p] : 0;
+#pragma unroll
+        for (int i = 0; i < PER_D; ++i) {
+            const int e = tid + 256 * i;
+            if (e < DT * kDomTile) {
+                const int p = tbase * kDomTile + e;
+                dpre[i] = tbase + e / kDomTile < t1 ? dinfo[p] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+                apre[i] = p < P ? pa[p] : 0;
+            }
         }
     };
     auto swrite = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
-        if (tid < DT * kDomTile) {
-            dl[buf][tid] = dpre;
-            dla[buf][tid] = apre;
+#pragma unroll
+        for (int i = 0; i < PER_D; ++i) {
+            const int e = tid + 256 * i;
+            if (e < DT * kDomTile) {
+                dl[buf][e] = dpre[i];
+                dla[buf][e] = apre[i];
+            }
         }
     };
     // acc[qi][h][plane]: the planes are combined (4 hi + lo) at the test,
@@ -689,7 +715,7 @@ static hipError_t launch_search_t(const BatchHost &b, hipStream_t st) {
 hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
     if (b.blocks[K_SEARCH] == 0) return hipSuccess;
     const int B = b.B;
-    const Shape sh = mfma_shape(B, b.eng == E_H16);
+    const TileShape sh = b.shape;
 #define FIC_SEARCH(KA, PL, RQ, DT, WPE) \
     if (sh.pl == PL && sh.rq == RQ && sh.dt == DT && sh.wpe == WPE) return launch_search_t<KA, PL, RQ, DT, WPE>(b, st)
     if (B == 4) {

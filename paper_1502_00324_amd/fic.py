@@ -53,6 +53,15 @@ class Timing(ctypes.Structure):
     _fields_ = [("ms", (ctypes.c_double * 6) * T_KINDS), ("launches", (i32 * 6) * T_KINDS)]
 
 
+FORM_I8, FORM_F16_16X16, FORM_F16 = 0, 1, 2
+FORMS = 3
+FORM_NAMES = ("mfma_i8", "mfma_f16_16x16", "mfma_f16")
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("choice", (i32 * 6) * FORMS)]
+
+
 class PoolC(ctypes.Structure):
     _fields_ = [("capacity", i32), ("count", vp), ("xy", vp), ("key", vp), ("sum4", vp), ("a", vp)]
 
@@ -102,6 +111,12 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(CodesC), vp]
         L.fic_decode.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(PoolC), ctypes.POINTER(CodesC), i32, i32,
                                  i32, vp, vp]
+        L.fic_shape_count.argtypes = [i32, i32]
+        L.fic_shape_describe.argtypes = [i32, i32, i32, vp]
+        L.fic_ctx_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.fic_ctx_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.fic_autotune.argtypes = [vp, ctypes.POINTER(Image), i32, ctypes.POINTER(Params), ctypes.POINTER(PoolC),
+                                   ctypes.POINTER(CodesC), i32, vp, ctypes.POINTER(Tuning)]
         _lib = L
     return _lib
 
@@ -112,7 +127,8 @@ EXPORTED = ("fic_ctx_create", "fic_ctx_destroy", "fic_ctx_set_scratch_limit", "f
             "fic_validate_params", "fic_query_capacity", "fic_level_engine", "fic_entropy_table",
             "fic_build_domain_pool",
             "fic_encode_level", "fic_encode", "fic_decode", "fic_pack_capacity", "fic_pack", "fic_unpack_header",
-            "fic_unpack", "fic_s_histogram")
+            "fic_unpack", "fic_s_histogram", "fic_shape_count", "fic_shape_describe", "fic_ctx_get_tuning",
+            "fic_ctx_set_tuning", "fic_autotune")
 
 
 def strerror(status: int) -> str:
@@ -151,6 +167,23 @@ def make_params(levels, block0=None, pct=(3, 10), pool_max=0, s_num=tuple(range(
     p.engine = engine
     p.pool_key = pool_key
     return p
+
+
+def shape_count(form: int, B: int) -> int:
+    """Compiled tile shapes of a matrix form at block size B (0: none)."""
+    return lib().fic_shape_count(form, B)
+
+
+def shape_describe(form: int, B: int, index: int) -> tuple:
+    """(operand form, range quads per wave, tiles per stage, waves per SIMD)."""
+    out = np.zeros(4, np.int32)
+    _check(lib().fic_shape_describe(form, B, index, out.ctypes.data), "fic_shape_describe")
+    return tuple(int(v) for v in out)
+
+
+def tuning_dict(t: Tuning) -> dict:
+    """{(form name, B): candidate} for the entries that are not -1."""
+    return {(FORM_NAMES[f], 1 << l): t.choice[f][l] for f in range(FORMS) for l in range(6) if t.choice[f][l] >= 0}
 
 
 def level_engine(engine: int, B: int) -> int:
@@ -374,6 +407,39 @@ class Context:
 
     def graph_count(self) -> int:
         return lib().fic_ctx_graph_count(self.h)
+
+    def get_tuning(self) -> Tuning:
+        t = Tuning()
+        _check(lib().fic_ctx_get_tuning(self.h, ctypes.byref(t)), "fic_ctx_get_tuning")
+        return t
+
+    def set_tuning(self, choices: dict | Tuning):
+        """choices: a Tuning, or {(form name or index, B): candidate} (others: default)."""
+        if isinstance(choices, Tuning):
+            t = choices
+        else:
+            t = Tuning()
+            for f in range(FORMS):
+                for l in range(6):
+                    t.choice[f][l] = -1
+            for (form, B), c in choices.items():
+                f = FORM_NAMES.index(form) if isinstance(form, str) else int(form)
+                t.choice[f][int(B).bit_length() - 1] = int(c)
+        _check(lib().fic_ctx_set_tuning(self.h, ctypes.byref(t)), "fic_ctx_set_tuning")
+
+    def autotune(self, images, p: Params, bufs=None, reps: int = 3) -> dict:
+        """Times every compiled tile shape of p's matrix levels on these images
+        and keeps the fastest in the context.  Returns {(form, B): candidate}."""
+        if bufs is None:
+            bufs = self.alloc_encode([(im.shape[1], im.shape[0]) for im in images], p, images[0].device)
+        n = len(images)
+        imgs = (Image * n)(*[_image(im) for im in images])
+        pools = (PoolC * (n * p.levels))(*[pl.c() for (pls, _) in bufs for pl in pls])
+        codes = (CodesC * (n * p.levels))(*[cd.c() for (_, cds) in bufs for cd in cds])
+        t = Tuning()
+        _check(lib().fic_autotune(self.h, imgs, n, ctypes.byref(p), pools, codes, int(reps), _stream(),
+                                  ctypes.byref(t)), "fic_autotune")
+        return tuning_dict(t)
 
     def set_timing(self, enable: bool):
         _check(lib().fic_ctx_set_timing(self.h, int(enable)), "fic_ctx_set_timing")

@@ -40,7 +40,7 @@ class BatchDev(ctypes.Structure):
 
 
 HOOK = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_uint, ctypes.c_uint, ctypes.POINTER(ctypes.c_void_p))
-log = {"launches": [], "errors": [], "forms": []}
+log = {"launches": [], "errors": [], "forms": [], "shapes": []}
 
 
 def on_launch(name, grid, block, args):
@@ -69,6 +69,10 @@ def on_launch(name, grid, block, args):
             # operand form: the second template argument of the mangled name
             m = re.search(r"k_mfma_searchILi(\d+)ELi(\d+)E", name)
             log["forms"].append(int(m.group(2)) if m else -1)
+        if short in ("k_mfma_search", "k_f16_search"):
+            # the tile shape: (pl, rq, dt, wpe), pl = 0 for the 32x32 kernel
+            a = [int(v) for v in re.findall(r"Li(\d+)E", name.split(short, 1)[1].split("EEv", 1)[0])]
+            log["shapes"].append(a[1:] if short == "k_mfma_search" else [0] + a[1:])
         if short in ("k_mfma_search", "k_f16_search") and (pre[kind] % 8 != 0).any():
             log["errors"].append("%s: an image's workgroups do not start on a multiple of 8" % short)
     if grid != want:
@@ -92,7 +96,7 @@ def buffers(keep, shape_caps):
     return pool, codes, cnt
 
 
-def encode_case(L, h, shapes, levels, engine, pool_max=0, reps=2, timing_toggle=False):
+def encode_case(L, h, shapes, levels, engine, pool_max=0, reps=2, timing_toggle=False, autotune=None):
     keep = []
     images = [make_image(11 + i, w, hh, 8) for i, (w, hh) in enumerate(shapes)]
     keep += images
@@ -110,6 +114,12 @@ def encode_case(L, h, shapes, levels, engine, pool_max=0, reps=2, timing_toggle=
             pools[i * NL + l], codes[i * NL + l], cnt = buffers(keep, (int(pc[l]), int(rc[l])))
             cnt[0] = int(rc[l])     # the kernels do not run: pretend every range splits
     statuses = []
+    if autotune is not None:
+        t = fic.Tuning()
+        statuses.append(L.fic_autotune(h, imgs, n, ctypes.byref(p), pools, codes, 1, None, ctypes.byref(t)))
+        autotune.update({"%d,%d" % (f, 1 << l): t.choice[f][l] for f in range(fic.FORMS) for l in range(6)
+                         if t.choice[f][l] >= 0})
+        return statuses
     for r in range(reps):
         if timing_toggle:
             L.fic_ctx_set_timing(h, 1)
@@ -131,10 +141,10 @@ def main():
     out = {}
 
     def scenario(name, fn):
-        log["launches"], log["errors"], log["forms"] = [], [], []
+        log["launches"], log["errors"], log["forms"], log["shapes"] = [], [], [], []
         st = fn()
         out[name] = {"status": st, "errors": list(log["errors"]), "launches": list(log["launches"]),
-                     "forms": list(log["forms"])}
+                     "forms": list(log["forms"]), "shapes": list(log["shapes"])}
 
     M, F, I8, H = fic.ENGINE_MFMA, fic.ENGINE_FP32, fic.ENGINE_MFMA_I8, fic.ENGINE_MFMA_F16
     X = fic.ENGINE_MFMA_F16_16X16
@@ -180,6 +190,45 @@ def main():
 
     scenario("graphs", graphs)
     out["graphs"]["graph"] = log["graph"]
+    # tile shapes: the compiled candidates, the autotuner (all inert timings tie,
+    # so the first candidate wins), and a forced choice
+    cands = {}
+    for f in range(fic.FORMS):
+        for B in (2, 4, 8, 16, 32):
+            cands["%d,%d" % (f, B)] = [list(fic.shape_describe(f, B, i)) for i in range(fic.shape_count(f, B))]
+    out["candidates"] = cands
+    for eng, name in ((I8, "i8"), (X, "f16x"), (H, "f16")):
+        for B, Ls in ((32, 4), (16, 2), (8, 2), (4, 2), (2, 2)):
+            if fic.level_engine(eng, B) == F:
+                continue
+            res = {}
+            scenario("autotune_%s_%d" % (name, B),
+                     lambda: encode_case(L, h, [(128, 128), (96, 64)], [(B, Ls)], eng, autotune=res))
+            out["autotune_%s_%d" % (name, B)]["tuning"] = res
+
+    def forced():
+        t = fic.Tuning()
+        L.fic_ctx_get_tuning(h, ctypes.byref(t))
+        before = [list(r) for r in t.choice]
+        t.choice[fic.FORM_I8][4] = 2        # B = 16: third candidate
+        t.choice[fic.FORM_I8][3] = 1        # B = 8: second
+        st = [L.fic_ctx_set_tuning(h, ctypes.byref(t))]
+        bad = fic.Tuning()
+        L.fic_ctx_get_tuning(h, ctypes.byref(bad))
+        bad.choice[fic.FORM_I8][4] = 99
+        log["bad_set"] = L.fic_ctx_set_tuning(h, ctypes.byref(bad))
+        L.fic_ctx_get_tuning(h, ctypes.byref(bad))
+        log["after_bad"] = [list(r) for r in bad.choice]
+        log["before"] = before
+        st += encode_case(L, h, [(128, 128)], [(16, 2), (8, 2), (4, 2)], I8, reps=1)
+        for r in range(fic.FORMS):
+            for l in range(6):
+                t.choice[r][l] = -1
+        st.append(L.fic_ctx_set_tuning(h, ctypes.byref(t)))
+        return st
+
+    scenario("tuning_forced", forced)
+    out["tuning_forced"].update({k: log[k] for k in ("bad_set", "after_bad", "before")})
     L.fic_ctx_set_scratch_limit(h, 1 << 10)
     scenario("over_limit", lambda: encode_case(L, h, [(1024, 1024)], [(8, 1), (4, 1)], M, reps=1))
     L.fic_ctx_set_scratch_limit(h, 0)

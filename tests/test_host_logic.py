@@ -122,3 +122,42 @@ def test_graph_capture_and_replay(runs):
     assert len(s["launches"]) == g["captured"] and g["replays"] == 5
     # at most two graphs kept; 0 frees them
     assert g["counts"] == [1, 2, 0]
+
+
+FORM_OF = {"i8": 0, "f16x": 1, "f16": 2}
+
+
+def test_shape_candidates_listed(runs):
+    c = runs["candidates"]
+    # every matrix form has compiled shapes for its block sizes, the default first
+    assert [len(c["0,%d" % B]) for B in (2, 4, 8, 16, 32)][1:] == [3, 6, 6, 3]
+    assert len(c["0,2"]) == 0 and len(c["1,32"]) == 0 and len(c["2,32"]) == 0
+    assert c["0,16"][0] == [2, 2, 1, 3] and c["0,32"][0] == [2, 1, 1, 2] and c["1,8"][0] == [3, 2, 8, 3]
+    assert c["2,4"][0] == [0, 1, 8, 4] and all(s[0] == 4 for s in c["1,4"])
+    for k, v in c.items():
+        assert len({tuple(s) for s in v}) == len(v), k   # no duplicates
+
+
+def test_autotune_times_every_candidate(runs):
+    names = [n for n in runs if n.startswith("autotune_")]
+    assert len(names) >= 12
+    for name in names:
+        s = runs[name]
+        assert all(v == 0 for v in s["status"]) and s["errors"] == [], name
+        eng, B = name.split("_")[1], int(name.split("_")[2])
+        form = FORM_OF[eng]
+        cands = runs["candidates"]["%d,%d" % (form, B)]
+        assert {tuple(x) for x in s["shapes"]} == {tuple(x) for x in cands}, name
+        # the stub's events time everything at 0: the first candidate is kept
+        if len(cands) > 1:
+            assert s["tuning"]["%d,%d" % (form, B)] == 0, name
+
+
+def test_forced_tuning_is_used_and_validated(runs):
+    s = runs["tuning_forced"]
+    assert all(v == 0 for v in s["status"]) and s["errors"] == []
+    c = runs["candidates"]
+    assert s["shapes"] == [c["0,16"][2], c["0,8"][1], c["0,4"][0]]
+    assert s["bad_set"] == -1
+    after = s["after_bad"]
+    assert after[0][4] == 2 and after[0][3] == 1   # the rejected call changed nothing
