@@ -48,11 +48,26 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def level_counts(bufs, p):
-    """(B, ranges, pool) per level and image, read back after a run."""
+def level_counts(bufs, p, images):
+    """(B, ranges, pool, searched ranges) per level and image, read back after
+    a run.  Searched: every range but the constant ones when the level's S
+    holds 0 (their code is fixed without a search)."""
+    import numpy as np
     out = []
-    for pools, codes in bufs:
-        out.append([(p.block0 >> l, int(codes[l].count.item()), int(pools[l].count.item())) for l in range(p.levels)])
+    for (pools, codes), img in zip(bufs, images):
+        per = []
+        f = img.astype(np.int64)
+        for l in range(p.levels):
+            B = p.block0 >> l
+            R = int(codes[l].count.item())
+            xy = codes[l].xy[:R].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+            flat = 0
+            if p.s_num[l][0] == 0 and R:
+                x, y = xy & 0xFFFF, xy >> 16
+                blocks = np.stack([f[yy:yy + B, xx:xx + B] for xx, yy in zip(x, y)])
+                flat = int((blocks.reshape(R, -1).max(1) == blocks.reshape(R, -1).min(1)).sum())
+            per.append((B, R, int(pools[l].count.item()), R - flat))
+        out.append(per)
     return out
 
 
@@ -91,7 +106,7 @@ def cpu_baseline(wl, images, counts, budget_s):
                                 else wl.s_den[l], wl.split_rms, l == len(wl.levels) - 1, workers=1)
             t_search += time.perf_counter() - t1
             done += len(pick)
-        _, R, P = counts[0][l]
+        _, R, P, _ = counts[0][l]
         per_range = t_search / done
         t_total += t_pool + per_range * R
         total_triples += R * P * 8
@@ -183,11 +198,14 @@ def main():
         sec = run_steps(ctx, imgs, p, bufs, args.steps, torch)
         stages = ctx.read_timing()
         ctx.set_timing(False)
-    counts = level_counts(bufs, p)
-    triples_by_B = {}
+    counts = level_counts(bufs, p, images)
+    # comparisons the search kernels evaluate (ranges searched x pool x 8);
+    # the exhaustive count also holds the constant ranges coded in closed form
+    triples_by_B, exhaustive = {}, 0
     for per_img in counts:
-        for (B, R, P) in per_img:
-            triples_by_B[B] = triples_by_B.get(B, 0) + R * P * 8
+        for (B, R, P, Rs) in per_img:
+            triples_by_B[B] = triples_by_B.get(B, 0) + Rs * P * 8
+            exhaustive += R * P * 8
     triples = sum(triples_by_B.values())
     value = triples / sec
 
@@ -277,7 +295,7 @@ def main():
 
     per_stage = {"%s_B%d" % (n, B): round(v[0] / max(args.steps, 1), 4) for (n, B), v in sorted(stages.items())}
     out = {
-        "metric": "range x domain x isometry comparisons/s (whole encode, all quadtree levels)",
+        "metric": "range x domain x isometry comparisons/s (ranges searched, whole encode, all quadtree levels)",
         "value": value, "unit": "comparisons/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(sec * 1e3, 3), "encode_ms_per_image": round(sec * 1e3 / len(images), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -295,7 +313,9 @@ def main():
                    "parallelism": "single GPU", "graph_replay": bool(args.graphs),
                    "tiles": tiles, "autotuned": not args.no_autotune},
         "comparisons_per_step": triples,
-        "levels": [{"B": B, "ranges": R, "pool": P, "comparisons": R * P * 8} for (B, R, P) in counts[0]]
+        "exhaustive_comparisons_per_step": exhaustive,
+        "levels": [{"B": B, "ranges": R, "ranges_searched": Rs, "pool": P, "comparisons": Rs * P * 8}
+                   for (B, R, P, Rs) in counts[0]]
         if len(counts) == 1 else None,
         "stage_ms_per_step": per_stage,
         "roofline": roofline, "fp32_baseline": fp32, "cpu_baseline": cpu, "bitstream": bitstream, "decode": decode,

@@ -347,6 +347,7 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
             blk[K_FINAL] = cdiv(d.range_cap, 4);
             blk[K_CCMP] = cdiv(d.range_cap, kScanBlock);
             d.ri = (RInfo *)take(S_RINFO, sizeof(RInfo) * (size_t)(d.range_cap + 1));
+            d.sidx = (int32_t *)take(S_RINFO, sizeof(int32_t) * (size_t)(d.range_cap + 1));
             d.cblocksum = (int *)take(S_CBLOCK, sizeof(int) * (size_t)(blk[K_CCMP] + 1));
             d.cblockoff = (int *)take(S_CBLOCK, sizeof(int) * (size_t)(blk[K_CCMP] + 1));
             if (eng != E_FP32) {
@@ -413,6 +414,8 @@ void bind(fic_ctx *ctx, LevelPlan &pl, void *tables = nullptr) {
         rb(d.pblockoff, S_PBLOCK);
         if (d.nslot > 0) {  // planned with a search
             rb(d.ri, S_RINFO);
+            rb(d.sidx, S_RINFO);
+            d.ns = d.sidx + d.range_cap;
             rb(d.cblocksum, S_CBLOCK);
             rb(d.cblockoff, S_CBLOCK);
             rb(d.part, S_PARTIAL);
@@ -426,6 +429,7 @@ void bind(fic_ctx *ctx, LevelPlan &pl, void *tables = nullptr) {
             }
         } else {
             d.ri = nullptr;
+            d.sidx = d.ns = nullptr;
         }
     }
     char *base = (char *)(tables ? tables : ctx->slot[S_TABLES].ptr) + pl.table_off;

@@ -216,6 +216,10 @@ struct ImgLvl {
     PoolSel *sel;
     int *pblocksum, *pblockoff, *cblocksum, *cblockoff;
     RInfo *ri;
+    // the ranges the search kernels take (search order -> range index) and
+    // their count: every range but the constant ones when S holds 0, whose
+    // code is fixed (range moments kernel)
+    int32_t *sidx, *ns;
     Partial *part;
     uint4 *afrag, *bfrag;
     float2 *dinfo;

@@ -29,30 +29,63 @@ hipError_t launch_level0_b(const BatchHost &b, hipStream_t st) {
 // One wave per range.  The prune margin is n/4 + 4 in units of C'; the float
 // rounding of the prune test is below n/16 in the same units.
 // One thread per range: Sr and sum r^2 from the summed-area tables.
-__global__ __launch_bounds__(256) void k_range_info(BatchDev b) {
+__global__ __launch_bounds__(256) void k_range_info(BatchDev b, int s_has_zero) {
     const int *pre = b.pre + K_RANGE * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
     const int r = (blockIdx.x - pre[im]) * 256 + threadIdx.x;
-    if (r >= min(*d.nr, d.range_cap)) return;
-    const int B = d.B, n = B * B;
-    const uint32_t v = d.rxy[r];
-    const int x0 = v & 0xffff, y0 = v >> 16;
-    const IntegGeom g = integ_geom(d.W, d.H);
-    const int64_t s = box_sum(g.si(d.integ), g.ws, x0, y0, B, B);
-    const int64_t ss = box_sum(g.sii(d.integ), g.ws, x0, y0, B, B);
-    RInfo o;
-    o.cr = (int64_t)n * ss - s * s;
-    o.sr = (int32_t)s;
-    o.bn = (float)(128.0 - (double)s / n);
-    o.an = (float)(512.0 * s - 65536.0 * n + (n / 4 + 4));
-    o.pad = 0.f;
-    o.gbest = INT64_MAX;
-    d.ri[r] = o;
+    const bool live = r < min(*d.nr, d.range_cap);
+    bool searched = false;
+    if (live) {
+        const int B = d.B, n = B * B;
+        const uint32_t v = d.rxy[r];
+        const int x0 = v & 0xffff, y0 = v >> 16;
+        const IntegGeom g = integ_geom(d.W, d.H);
+        const int64_t s = box_sum(g.si(d.integ), g.ws, x0, y0, B, B);
+        const int64_t ss = box_sum(g.sii(d.integ), g.ws, x0, y0, B, B);
+        RInfo o;
+        o.cr = (int64_t)n * ss - s * s;
+        o.sr = (int32_t)s;
+        o.bn = (float)(128.0 - (double)s / n);
+        o.an = (float)(512.0 * s - 65536.0 * n + (n / 4 + 4));
+        o.pad = 0.f;
+        o.gbest = INT64_MAX;
+        d.ri[r] = o;
+        // A constant range (Cr = 0) has Bx = n X4 - Sr Sd4 = 0 against every
+        // domain, so val = num^2 A >= 0; with 0 in S the first pair in the
+        // search order, domain 0, isometry 0, s index 0, already reaches
+        // val 0, and nothing beats or ties it earlier.  Its code is written
+        // here (one partial, the other slots empty) and the search skips it.
+        if (o.cr == 0 && s_has_zero) {
+            Partial* q = d.part + (size_t)r * d.nslot;
+            q[0] = Partial{0, 0, 0};
+            for (int j = 1; j < d.nslot; ++j) q[j] = Partial{INT64_MAX, -1, 0};
+        } else {
+            searched = true;
+        }
+    }
+    // append the searched ranges to the search list, one atomic per wave
+    const uint64_t m = __ballot(searched);
+    if (m) {
+        const int lane = threadIdx.x & 63, leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(d.ns, __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (searched) d.sidx[base + __popcll(m & ((1ull << lane) - 1))] = r;
+    }
+}
+
+// Clears the search-list count of every image before the range moments.
+__global__ void k_search_list_reset(BatchDev b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < b.n) *b.d[i].ns = 0;
 }
 
 hipError_t launch_range_info_b(const BatchHost &b, hipStream_t st) {
-    if (b.blocks[K_RANGE] > 0) k_range_info<<<b.blocks[K_RANGE], 256, 0, st>>>(b.dev);
+    if (b.blocks[K_RANGE] > 0) {
+        k_search_list_reset<<<(b.dev.n + 255) / 256, 256, 0, st>>>(b.dev);
+        k_range_info<<<b.blocks[K_RANGE], 256, 0, st>>>(b.dev, b.ss.num[0] == 0 ? 1 : 0);
+    }
     return hipGetLastError();
 }
 

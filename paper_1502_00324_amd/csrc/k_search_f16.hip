@@ -99,10 +99,11 @@ __global__ __launch_bounds__(256) void k_f16_afrag(BatchDev b) {
     const int s = rest % KS, q = rest / KS;
     const int m = lane & 31, kb = lane >> 5;
     const int j = m >> 3, h = (m >> 2) & 1, i = m & 3;
-    const int r = 4 * q + 2 * h + (j >> 1);
+    const int js = 4 * q + 2 * h + (j >> 1);   // entry of the search list
+    const int r = js < *d.ns ? d.sidx[js] : -1;
     const int t = 4 * (j & 1) + i;
     h8 w;
-    if (r < min(*d.nr, d.range_cap)) {
+    if (r >= 0) {
         const uint32_t v = d.rxy[r];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int ti = iso_inv(t);
@@ -200,7 +201,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const float tfac = tn_factor(n);
     int rg, cfirst, cstep, ncs, slot;
     chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
-    const int R = min(*dsc.nr, range_cap), P = min(*dsc.pcount, pool_cap);
+    // R: the length of the search list (constant ranges are coded already)
+    const int R = min(*dsc.ns, range_cap), P = min(*dsc.pcount, pool_cap);
+    const int32_t *__restrict__ sidx = dsc.sidx;
     if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
     const int ntiles = (P + kDomTile32 - 1) / kDomTile32;
     const int q0 = (rg * 4 + wave) * RQ;
@@ -218,14 +221,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         for (int s = 0; s < KS; ++s) A[qi][s] = afrag[((size_t)(q0 + qi) * KS + s) * 64 + lane];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int r = (q0 + qi) * 4 + 2 * hh + u;
-            rr[qi][u] = r < R ? r : -1;
-            const RInfo x = ri[r < R ? r : 0];
+            const int js = (q0 + qi) * 4 + 2 * hh + u;
+            const int r = js < R ? sidx[js] : -1;
+            rr[qi][u] = r;
+            const RInfo x = ri[r >= 0 ? r : 0];
             bn[qi][u] = x.bn;
             an[qi][u] = x.an;
             sr[qi][u] = (int)x.sr;
             cr[qi][u] = x.cr;
-            tn[qi][u] = r < R ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
+            tn[qi][u] = r >= 0 ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
             tb[qi][u] = INT64_MAX;
             best[qi][u] = INT64_MAX;
             bp[qi][u] = INT32_MAX;

@@ -47,12 +47,13 @@ __global__ __launch_bounds__(256) void k_fp32_views(BatchDev b) {
     const int64_t e = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;
     const int B = d.B, n = B * B, Rpad = d.rpad;
     if (e >= (int64_t)n * Rpad) return;
-    const int j = (int)(e / Rpad), r = (int)(e - (int64_t)j * Rpad);
+    // column js of the view array holds entry js of the search list
+    const int j = (int)(e / Rpad), js = (int)(e - (int64_t)j * Rpad);
     const int cy = j / B, cx = j - cy * B;
-    const bool valid = r < min(*d.nr, d.range_cap);
+    const bool valid = js < min(*d.ns, d.range_cap);
     int x0 = 0, y0 = 0;
     if (valid) {
-        const uint32_t v = d.rxy[r];
+        const uint32_t v = d.rxy[d.sidx[js]];
         x0 = v & 0xffff;
         y0 = v >> 16;
     }
@@ -116,17 +117,19 @@ __global__ __launch_bounds__(256) void k_fp32_search(BatchDev bt, SSet ss) {
     Partial *__restrict__ part = dsc.part;
     const int Rpad = dsc.rpad, Ppad = dsc.ppad, tiles_per_chunk = dsc.ftpc, nchunk = dsc.fnchunk;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap;
-    const int R = min(*dsc.nr, range_cap), P = min(*dsc.pcount, pool_cap);
+    // R: the length of the search list (constant ranges are coded already)
+    const int R = min(*dsc.ns, range_cap), P = min(*dsc.pcount, pool_cap);
     const int lb = blockIdx.x - bpre[im];
     const int nrg = (range_cap + kF32Ranges - 1) / kF32Ranges;
     const int rg = lb % nrg;
     if (lb >= nrg * nchunk || rg * kF32Ranges >= R) return;  // uniform over the block
-    const int r = rg * kF32Ranges + tr;
-    const bool rvalid = r < R;
+    const int js = rg * kF32Ranges + tr;
+    const bool rvalid = js < R;
+    const int r = rvalid ? dsc.sidx[js] : 0;   // the range of search entry js
     const int chunk = lb / nrg;
     const int ntiles = (P + kF32Doms - 1) / kF32Doms;
     const int t0 = chunk * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
-    const RInfo x = ri[rvalid ? r : rg * kF32Ranges];
+    const RInfo x = ri[r];
     const float bn = x.bn, an = x.an;
     float tn = -1e30f;
     int64_t best = INT64_MAX;

@@ -197,13 +197,15 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
     const int h = rest & 1, q = rest >> 1;
     const int i = lane & 15, kg = lane >> 4;
     const int t = 4 * h + (i & 3);
-    const int r = q * 4 + (i >> 2);
+    // row i of quad q: entry 4q + i/4 of the search list
+    const int js = q * 4 + (i >> 2);
+    const int r = js < *d.ns ? d.sidx[js] : -1;
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     if (ft) {
         // positions in K-groups 0 and 1 minus the range's rounded mean; the
         // threshold group (2) is written by the search kernel, group 3 is 0
         h8v hv = h8v{0};
-        if (kg < 2 && r < min(*d.nr, d.range_cap)) {
+        if (kg < 2 && r >= 0) {
             const uint32_t v = d.rxy[r];
             const int x0 = v & 0xffff, y0 = v >> 16, n = B * B;
             const int ti = iso_inv(t), cen = round_mean(d.ri[r].sr, n);
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
             }
         }
         __builtin_memcpy(w, &hv, sizeof(w));
-    } else if (f16 && r < min(*d.nr, d.range_cap)) {
+    } else if (f16 && r >= 0) {
         const uint32_t v = d.rxy[r];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int ti = iso_inv(t);
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
             hv[e] = (_Float16)((int)d.pix[(size_t)(y0 + sy) * d.pitch + x0 + sx] - 128);
         }
         __builtin_memcpy(w, &hv, sizeof(w));
-    } else if (r < min(*d.nr, d.range_cap)) {
+    } else if (r >= 0) {
         const uint32_t v = d.rxy[r];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int ti = iso_inv(t), D = 2 * B;
@@ -386,10 +388,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
     const float tfac = tn_factor(n);
-    const int32_t *nr = dsc.nr, *np = dsc.pcount;
+    const int32_t *np = dsc.pcount;
     int rg, cfirst, cstep, ncs, slot;
     chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
-    const int R = min(*nr, range_cap), P = min(*np, pool_cap);
+    // R: the length of the search list (constant ranges are coded already)
+    const int R = min(*dsc.ns, range_cap), P = min(*np, pool_cap);
+    const int32_t *__restrict__ sidx = dsc.sidx;
     if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
     const int ntiles = (P + kDomTile - 1) / kDomTile;
     const int q0 = (rg * 4 + wave) * RQ;
@@ -406,14 +410,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int s = 0; s < KA; ++s) A[qi][h][s] = afrag[(((size_t)(q0 + qi) * 2 + h) * KA + s) * 64 + lane];
-        const int r = (q0 + qi) * 4 + g;
-        rr[qi] = r < R ? r : -1;
-        const RInfo x = ri[r < R ? r : 0];
+        const int js = (q0 + qi) * 4 + g;
+        const int r = js < R ? sidx[js] : -1;
+        rr[qi] = r;
+        const RInfo x = ri[r >= 0 ? r : 0];
         bn[qi] = x.bn;
         an[qi] = x.an;
         sr[qi] = (int)x.sr;
         cr[qi] = x.cr;
-        tn[qi] = r < R ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
+        tn[qi] = r >= 0 ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
         tb[qi] = INT64_MAX;
         best[qi] = INT64_MAX;
         bp[qi] = INT32_MAX;
