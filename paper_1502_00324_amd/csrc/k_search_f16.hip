@@ -23,6 +23,15 @@
 //   K index k = 16 s + 8 (L/32) + e -> decimated position (k / B, k % B).
 // With rows arranged this way lane L holds all 8 isometries of two ranges
 // (4q + 2(L/32) and the next) against domain L%32: values 0..7 and 8..15.
+//
+// Up to B = 8 the operands are centred at each block's own rounded mean
+// instead: r - m_r and D4 - m_d with m_r = round(Sr/n), m_d = round(Sd4/n)
+// (magnitudes <= 255 and <= 1020, exact in f16; sums <= n 2^18 <= 2^24,
+// exact in f32).  Then acc = Bx/n + e_r e_d / n with e_r = Sr - n m_r,
+// e_d = Sd4 - n m_d and |e_r e_d / n| <= n/4, so the prune test
+// Bx/n > tn sqrt(A) becomes acc > tn sqrt(A) - (n/2 + 4) (n/4 for the
+// centring, n/4 + 4 of float margin as in the other engines): one FMA per
+// pair instead of two, and the confirm takes Bx = n acc - e_r e_d.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -35,6 +44,9 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f16x __attribute__((ext_vector_type(16)));
 
 bool f16_supported(int B) { return B == 2 || B == 4 || B == 8 || B == 16; }
+
+// Mean-centred operands (the header describes them): every size up to 8.
+__host__ __device__ inline bool f16_centred(int B) { return B <= 8; }
 
 // Range quads per wave (RQ), domain tiles per LDS stage (DT) and the
 // occupancy the register allocation aims at (waves per SIMD); the first entry
@@ -107,6 +119,7 @@ __global__ __launch_bounds__(256) void k_f16_afrag(BatchDev b) {
         const uint32_t v = d.rxy[r];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int ti = iso_inv(t);
+        const int cen = f16_centred(B) ? round_mean(d.ri[r].sr, B * B) : 128;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = 16 * s + 8 * kb + e;
@@ -117,7 +130,7 @@ __global__ __launch_bounds__(256) void k_f16_afrag(BatchDev b) {
             const int cy = k / B, cx = k - cy * B;
             int sy, sx;
             iso_src(ti, B, cy, cx, sy, sx);
-            w[e] = (_Float16)((int)d.pix[(size_t)(y0 + sy) * d.pitch + x0 + sx] - 128);
+            w[e] = (_Float16)((int)d.pix[(size_t)(y0 + sy) * d.pitch + x0 + sx] - cen);
         }
     } else {
 #pragma unroll
@@ -144,6 +157,7 @@ __global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
     if (valid) {
         const uint32_t v = d.pxy[p];
         const int x0 = v & 0xffff, y0 = v >> 16, pitch = d.pitch;
+        const int cen = f16_centred(B) ? round_mean(d.psum4[p], B * B) : 512;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = 16 * s + 8 * kb + e;
@@ -153,7 +167,7 @@ __global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
             }
             const int cy = k / B, cx = k - cy * B;
             const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
-            w[e] = (_Float16)(q[0] + q[1] + q[pitch] + q[pitch + 1] - 512);
+            w[e] = (_Float16)(q[0] + q[1] + q[pitch] + q[pitch + 1] - cen);
         }
     } else {
 #pragma unroll
@@ -172,6 +186,7 @@ __global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
 // before the prune test of tile t.
 template <int KS, int RQ, int DT, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_f16_search(BatchDev bt, SSet ss) {
+    constexpr bool CEN = KS <= 4;                // mean-centred operands (B <= 8)
     constexpr int STAGE = DT * KS * 64;          // uint4 per stage
     // share range bests across workgroups only when a stage is long enough
     // (>= 4 tiles) to hide the coherent load of the shared values
@@ -199,6 +214,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
     const float tfac = tn_factor(n);
+    const float cmargin = (float)(n / 2 + 4);   // centred test: n/4 centring + n/4 + 4 float margin
     int rg, cfirst, cstep, ncs, slot;
     chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
     // R: the length of the search list (constant ranges are coded already)
@@ -350,7 +366,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                             const f16x &a = acc[cur][qi];
                             const int o = 8 * u;
                             mx[qi][u] = max8f(a[o], a[o + 1], a[o + 2], a[o + 3], a[o + 4], a[o + 5], a[o + 6], a[o + 7]);
-                            const float rhs = fmaf(tn[qi][u], di.y, fmaf(-bn[qi][u], di.x, -an[qi][u]));
+                            const float rhs = CEN ? fmaf(tn[qi][u], di.y, -cmargin)
+                                                  : fmaf(tn[qi][u], di.y, fmaf(-bn[qi][u], di.x, -an[qi][u]));
                             // false on NaN: rows past the ranges, domains past the
                             // pool or the chunk, and ranges already at val 0
                             pass[qi][u] = mx[qi][u] > rhs;
@@ -365,9 +382,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
                             for (int u = 0; u < 2; ++u) {
                                 bool imp = false;
-                                if (pass[qi][u])
-                                    imp = confirm_pair((int)mx[qi][u], p, sd4, A, sr[qi][u], cr[qi][u], n, sl, sc,
-                                                       best[qi][u], bp[qi][u], bk[qi][u]);
+                                if (pass[qi][u]) {
+                                    if (CEN) {
+                                        const int64_t er = (int64_t)sr[qi][u] - (int64_t)n * round_mean(sr[qi][u], n);
+                                        const int64_t ed = sd4 - (int64_t)n * round_mean(sd4, n);
+                                        imp = confirm_bx((int64_t)n * (int64_t)mx[qi][u] - er * ed, p, A, cr[qi][u], sl,
+                                                         sc, best[qi][u], bp[qi][u], bk[qi][u]);
+                                    } else {
+                                        imp = confirm_pair((int)mx[qi][u], p, sd4, A, sr[qi][u], cr[qi][u], n, sl, sc,
+                                                           best[qi][u], bp[qi][u], bk[qi][u]);
+                                    }
+                                }
                                 if (__builtin_amdgcn_ballot_w64(imp)) {
                                     // the 32 lanes holding this range share their best: a
                                     // pair is only rejected when it cannot even tie it
