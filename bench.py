@@ -219,12 +219,24 @@ def main():
     alg_ops = triples_by_B[dom_B] * 2 * dom_B * dom_B / launches_per_step   # decimated MACs x 2 per launch
     achieved = alg_ops / (avg_ms * 1e-3) / 1e12
     peak = PEAK[dom_engine]
+    # HBM bytes from the committed counter passes, when they were taken on
+    # these sources and on the kernel instantiation this run used
     traffic = None
+    tile = tiles.get("B=%d" % dom_B, {})
+    sh = tile.get("pl_rq_dt_wpe")
+    want = None
+    if sh and tile.get("form") == "mfma_f16":
+        want = "k_f16_search<%d, %d, %d, %d>" % ((dom_B * dom_B + 15) // 16, sh[1], sh[2], sh[3])
+    elif sh:
+        pl = sh[0]
+        ka = {1: dom_B * dom_B // 16, 2: dom_B * dom_B // 64, 3: dom_B * dom_B // 32, 4: 1}[pl]
+        want = "k_mfma_search<%d, %d, %d, %d, %d>" % (ka, pl, sh[1], sh[2], sh[3])
     tf = traffic_file(wl.name)
-    if os.path.exists(tf):
+    if os.path.exists(tf) and want:
         with open(tf) as f:
             tr = json.load(f)
-        if tr.get("source_hash") == kernel_source_hash():
+        det = tr.get("per_launch_detail", {}).get(str(dom_B), {})
+        if tr.get("source_hash") == kernel_source_hash() and want in det.get("kernel", ""):
             traffic = tr.get("per_launch_bytes", {}).get(str(dom_B))
     issued = issued_ops(dom_engine, dom_B) / (2 * dom_B * dom_B)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",

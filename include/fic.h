@@ -203,7 +203,9 @@ int fic_ctx_set_tuning(fic_ctx *ctx, const fic_tuning *in);
  * the context (entries of other forms and sizes keep their values); *out,
  * if not null, receives the resulting choices.  Per candidate: one warm-up
  * encode, then reps (1..100) encodes with stage timing, scored by the summed
- * operand preparation, search and finalisation time of that level.  The
+ * operand preparation, search and finalisation time of that level; a
+ * candidate displaces the best so far (candidate 0 first) only when at
+ * least 3 % faster.  The
  * buffers are those of fic_encode and end up holding an ordinary encode.
  * Blocks the host until done; stage timing must be off (FIC_E_INVALID);
  * drops cached graphs.  Errors of the encodes are returned as they are. */
