@@ -2,8 +2,9 @@
  * Fractal image encoder ORACLE -- test infrastructure only.
  *
  * Only the tests, the package's smoke() check and the benchmark's CPU
- * baseline may load this library.  It is a plain, slow, single-threaded,
- * exact-integer statement of what the encoder computes, written from the
+ * baseline may load this library.  It is a plain, slow, exact-integer
+ * statement of what the encoder computes (single-threaded unless a caller
+ * splits its independent candidate keys or ranges over threads), written from the
  * paper (Salarian & Miar Naimi, "Modified Fast Fractal Image Compression
  * Algorithm in spatial domain").  It shares no code, header, table or
  * generator with the GPU library.
