@@ -206,11 +206,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const MfmaGeom geo = dsc.geo;
     const int lb = blockIdx.x - bpre[im];   // image blocks start at multiples of 8
     if (lb >= geo.nwg) return;
-    const h8 *__restrict__ afrag = (const h8 *)dsc.afrag;
-    const uint4 *__restrict__ bfrag = dsc.bfrag;
-    const float2 *__restrict__ dinfo = dsc.dinfo;
+    const gptr<h8> afrag = as_global((const h8 *)dsc.afrag);
+    const gptr<uint4> bfrag = as_global(dsc.bfrag);
+    const gptr<float2> dinfo = as_global(dsc.dinfo);
     RInfo *__restrict__ ri = dsc.ri;
-    const int64_t *__restrict__ pa = dsc.pa;
+    const gptr<int64_t> pa = as_global(dsc.pa);
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
     const float tfac = tn_factor(n);
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
     // R: the length of the search list (constant ranges are coded already)
     const int R = min(*dsc.ns, range_cap), P = min(*dsc.pcount, pool_cap);
-    const int32_t *__restrict__ sidx = dsc.sidx;
+    const gptr<int32_t> sidx = as_global(dsc.sidx);
     if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
     const int ntiles = (P + kDomTile32 - 1) / kDomTile32;
     const int q0 = (rg * 4 + wave) * RQ;
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
             const int e = tid + 256 * i;
-            pre[i] = tbase + e / (KS * 64) < t1 ? bfrag[(size_t)tbase * KS * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
+            pre[i] = tbase + e / (KS * 64) < t1 ? ldg(bfrag, (size_t)tbase * KS * 64 + e) : make_uint4(0u, 0u, 0u, 0u);
         }
         // tiles past the chunk end get NaN moments: no pair on them passes
 #pragma unroll
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             const int e = tid + 256 * i;
             if (e < DT * kDomTile32) {
                 const int p = tbase * kDomTile32 + e;
-                dpre[i] = tbase + e / kDomTile32 < t1 ? dinfo[p] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+                dpre[i] = tbase + e / kDomTile32 < t1 ? ldg(dinfo, p) : make_float2(__builtin_nanf(""), __builtin_nanf(""));
                 apre[i] = p < P ? pa[p] : 0;
             }
         }

@@ -273,6 +273,31 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     const int j = lane & 15, kg = lane >> 4;
     const int p = tile * kDomTile + j;
     const bool valid = p < min(*d.pcount, d.pool_cap);
+    if (planes) {
+        // one thread per K-step of the hi plane writes both planes of its
+        // 16 positions (each D4 read once)
+        if (s >= KA) return;
+        uint32_t wh[4] = {0u, 0u, 0u, 0u}, wl[4] = {0u, 0u, 0u, 0u};
+        if (valid) {
+            const uint32_t v = d.pxy[p];
+            const int x0 = v & 0xffff, y0 = v >> 16, pitch = d.pitch;
+#pragma unroll
+            for (int bb = 0; bb < 16; ++bb) {
+                const int k = 64 * s + 16 * kg + bb;
+                const int cy = k / B, cx = k - cy * B;
+                const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
+                const int d4 = q[0] + q[1] + q[pitch] + q[pitch + 1];
+                wh[bb >> 2] |= (uint32_t)(uint8_t)(int8_t)((d4 >> 2) - 128) << (8 * (bb & 3));
+                wl[bb >> 2] |= (uint32_t)(d4 & 3) << (8 * (bb & 3));
+            }
+        }
+        d.bfrag[slot] = make_uint4(wh[0], wh[1], wh[2], wh[3]);
+        d.bfrag[slot + (int64_t)KA * 64] = make_uint4(wl[0], wl[1], wl[2], wl[3]);
+        if (s == 0 && kg == 0)
+            d.dinfo[p] = valid ? make_float2((float)d.psum4[p], sqrt_down((double)d.pa[p]))
+                               : make_float2(__builtin_nanf(""), __builtin_nanf(""));  // never passes
+        return;
+    }
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     if (ft) {
         // K-groups 0, 1: positions minus the domain's rounded mean of D4;
@@ -316,25 +341,15 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
             hv[e] = (_Float16)(q[0] + q[1] + q[pitch] + q[pitch + 1] - 512);
         }
         __builtin_memcpy(w, &hv, sizeof(w));
-    } else if (valid) {
+    } else if (valid) {   // raw form: the pixels of the 2B x 2B block
         const uint32_t v = d.pxy[p];
         const int x0 = v & 0xffff, y0 = v >> 16;
         const int D = 2 * B, pitch = d.pitch;
-        const int lo = planes && s >= KA;
-        const int sk = planes ? s % KA : s;
 #pragma unroll
         for (int bb = 0; bb < 16; ++bb) {
-            const int k = 64 * sk + 16 * kg + bb;
-            int val;
-            if (planes) {
-                const int cy = k / B, cx = k - cy * B;
-                const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
-                const int d4 = q[0] + q[1] + q[pitch] + q[pitch + 1];
-                val = lo ? (d4 & 3) : (d4 >> 2) - 128;
-            } else {
-                const int dy = k / D, dx = k - dy * D;
-                val = (int)d.pix[(size_t)(y0 + dy) * pitch + x0 + dx] - 128;
-            }
+            const int k = 64 * s + 16 * kg + bb;
+            const int dy = k / D, dx = k - dy * D;
+            const int val = (int)d.pix[(size_t)(y0 + dy) * pitch + x0 + dx] - 128;
             w[bb >> 2] |= (uint32_t)(uint8_t)(int8_t)val << (8 * (bb & 3));
         }
     }
@@ -380,11 +395,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const MfmaGeom geo = dsc.geo;
     const int lb = blockIdx.x - bpre[im];   // image blocks start at multiples of 8
     if (lb >= geo.nwg) return;
-    const v4i *__restrict__ afrag = (const v4i *)dsc.afrag;
-    const uint4 *__restrict__ bfrag = dsc.bfrag;
-    const float2 *__restrict__ dinfo = dsc.dinfo;
+    const gptr<v4i> afrag = as_global((const v4i *)dsc.afrag);
+    const gptr<uint4> bfrag = as_global(dsc.bfrag);
+    const gptr<float2> dinfo = as_global(dsc.dinfo);
     RInfo *__restrict__ ri = dsc.ri;
-    const int64_t *__restrict__ pa = dsc.pa;
+    const gptr<int64_t> pa = as_global(dsc.pa);
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
     const float tfac = tn_factor(n);
@@ -393,7 +408,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
     // R: the length of the search list (constant ranges are coded already)
     const int R = min(*dsc.ns, range_cap), P = min(*np, pool_cap);
-    const int32_t *__restrict__ sidx = dsc.sidx;
+    const gptr<int32_t> sidx = as_global(dsc.sidx);
     if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
     const int ntiles = (P + kDomTile - 1) / kDomTile;
     const int q0 = (rg * 4 + wave) * RQ;
@@ -474,7 +489,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
             const int e = tid + 256 * i;
-            pre[i] = tbase + e / (KB * 64) < t1 ? bfrag[(size_t)tbase * KB * 64 + e] : make_uint4(0u, 0u, 0u, 0u);
+            pre[i] = tbase + e / (KB * 64) < t1 ? ldg(bfrag, (size_t)tbase * KB * 64 + e) : make_uint4(0u, 0u, 0u, 0u);
         }
         // tiles past the chunk end get NaN moments: no pair on them passes
 #pragma unroll
@@ -482,7 +497,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             const int e = tid + 256 * i;
             if (e < DT * kDomTile) {
                 const int p = tbase * kDomTile + e;
-                dpre[i] = tbase + e / kDomTile < t1 ? dinfo[p] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+                dpre[i] = tbase + e / kDomTile < t1 ? ldg(dinfo, p) : make_float2(__builtin_nanf(""), __builtin_nanf(""));
                 apre[i] = p < P ? pa[p] : 0;
             }
         }

@@ -25,6 +25,30 @@
 
 namespace fic {
 
+// Buffer pointers read out of the batch descriptors carry no address space
+// for the compiler, so loads through them become flat loads, and a flat load
+// counts on the LDS wait counter as well: every LDS wait in a loop would then
+// also wait for the global prefetch in flight.  All these buffers live in
+// global memory; these casts say so.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T *p) {
+    return (gptr<T>)p;
+}
+// Class types (uint4, float2) cannot be copied out of another address
+// space; they are read as the plain vectors they hold.
+typedef uint32_t gv4u __attribute__((ext_vector_type(4)));
+typedef float gv2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint4 ldg(gptr<uint4> p, size_t i) {
+    const gv4u v = ((gptr<gv4u>)p)[i];
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ldg(gptr<float2> p, size_t i) {
+    const gv2f v = ((gptr<gv2f>)p)[i];
+    return make_float2(v.x, v.y);
+}
+
 __device__ inline bool lex_less_vp(int64_t va, int pa, int64_t vb, int pb) {
     return va < vb || (va == vb && pa < pb);
 }
@@ -148,11 +172,14 @@ __device__ __forceinline__ float tn_from(int64_t best, int64_t cr, const SConst 
 }
 
 // The best of every workgroup searching a range, kept as an atomic minimum.
+// (global address space: a flat access would make every later wait drain
+// both counters)
 __device__ __forceinline__ int64_t gbest_load(const int64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((gptr<int64_t>)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void gbest_push(int64_t *p, int64_t v) {
-    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_min((__attribute__((address_space(1))) int64_t *)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int WIDTH>
