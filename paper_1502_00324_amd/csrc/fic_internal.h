@@ -61,6 +61,19 @@ struct PoolSel {
     unsigned long long gmin;
 };
 
+// ---------------------------------------------------------------- address spaces
+// Buffer pointers read out of the batch descriptors carry no address space
+// for the compiler, so loads through them become flat loads, and a flat load
+// counts on the LDS wait counter as well: every LDS wait in a loop would then
+// also wait for the global loads in flight.  All these buffers live in
+// global memory; these casts say so.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T *p) {
+    return (gptr<T>)p;
+}
+
 // ---------------------------------------------------------------- isometries
 // out[y][x] = in[sy][sx] for isometry t = 4m + r of a B x B block:
 // r clockwise quarter turns, then a left-right mirror when m = 1.

@@ -13,10 +13,15 @@ namespace fic {
 // small images still give the GPU enough waves).  Each lane keeps a private
 // 256-bin histogram in LDS (layout [bin][lane], no atomics) and updates G
 // incrementally: adding a pixel whose bin held c adds T[c+1] - T[c].
-
-__global__ __launch_bounds__(64) void k_pool_keys(BatchDev b, const int64_t *__restrict__ T) {
+// DSZ = 2B is the window side; the differences T[c+1] - T[c] sit in LDS up to
+// 1024 pixels per window, else they are read from the table.
+template <int DSZ>
+__global__ __launch_bounds__(64) void k_pool_keys(BatchDev b, const int64_t *__restrict__ table) {
+    constexpr int M = DSZ * DSZ, NW = DSZ / 4;   // window pixels, 4-byte words per window row
+    constexpr bool LT = M <= 1024;
     __shared__ uint16_t hist[256][64];
-    __shared__ int64_t dtab[1025];
+    __shared__ int64_t dtab[LT ? M : 1];
+    const gptr<int64_t> T = as_global(table);
     const int *pre = b.pre + K_KEYS * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
     const ImgLvl &d = b.d[im];
@@ -24,9 +29,8 @@ __global__ __launch_bounds__(64) void k_pool_keys(BatchDev b, const int64_t *__r
     const int ngx = (d.nx + 63) / 64;
     const int gx = lb % ngx, gy = lb / ngx;
     const int lane = threadIdx.x;
-    const int dsz = 2 * d.B, M = dsz * dsz, L = d.L, pitch = d.pitch, nx = d.nx;
-    const bool lds_tab = M <= 1024;
-    if (lds_tab)
+    const int L = d.L, pitch = d.pitch, nx = d.nx;
+    if constexpr (LT)
         for (int c = lane; c < M; c += 64) dtab[c] = T[c + 1] - T[c];
     for (int v = 0; v < 256; ++v) hist[v][lane] = 0;
     __syncthreads();
@@ -35,43 +39,81 @@ __global__ __launch_bounds__(64) void k_pool_keys(BatchDev b, const int64_t *__r
     const int cy1 = min(d.ny, cy0 + d.strip);
     // inactive lanes stay for the wave reduction below
     const bool active = cx < nx && cy0 < d.ny;
-    const uint8_t *col = d.pix + (size_t)(active ? cx : 0) * L;
+    const gptr<uint8_t> col = as_global(d.pix) + (size_t)(active ? cx : 0) * L;
     uint16_t *h = &hist[0][lane];
-    auto dlt = [&](int c) -> int64_t { return lds_tab ? dtab[c] : T[c + 1] - T[c]; };
+    auto dlt = [&](int c) -> int64_t {
+        if constexpr (LT)
+            return dtab[c];
+        else
+            return T[c + 1] - T[c];
+    };
     int64_t g = 0, gm = INT64_MAX;
-    auto add_row = [&](int y) {
-        const uint8_t *row = col + (size_t)y * pitch;
-        for (int i = 0; i < dsz; ++i) {
-            const int v = row[i];
-            const int c = h[v * 64];
-            g += dlt(c);
-            h[v * 64] = (uint16_t)(c + 1);
+    // a window row as 4-byte words (unaligned loads)
+    typedef uint32_t u32u __attribute__((aligned(1)));
+    auto load_row = [&](uint32_t (&w)[NW], int y) {
+        const gptr<u32u> row = (gptr<u32u>)(col + (size_t)y * pitch);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) w[k] = row[k];
+    };
+    // Four pixels per step: their four counts are read together, one LDS
+    // round trip instead of four.  A pixel equal to an earlier one of the
+    // group takes that one's update through the equality terms, and the
+    // writes, in program order, leave the last count.
+    auto apply_row = [&](const uint32_t (&w)[NW], bool add) {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const uint32_t x = w[k];
+            const int v0 = x & 255, v1 = (x >> 8) & 255, v2 = (x >> 16) & 255, v3 = x >> 24;
+            int c0 = h[v0 * 64], c1 = h[v1 * 64], c2 = h[v2 * 64], c3 = h[v3 * 64];
+            const int e1 = v1 == v0, e2 = (v2 == v0) + (v2 == v1), e3 = (v3 == v0) + (v3 == v1) + (v3 == v2);
+            if (add) {
+                c1 += e1;
+                c2 += e2;
+                c3 += e3;
+                g += dlt(c0) + dlt(c1) + dlt(c2) + dlt(c3);
+                h[v0 * 64] = (uint16_t)(c0 + 1);
+                h[v1 * 64] = (uint16_t)(c1 + 1);
+                h[v2 * 64] = (uint16_t)(c2 + 1);
+                h[v3 * 64] = (uint16_t)(c3 + 1);
+            } else {
+                c1 -= e1;
+                c2 -= e2;
+                c3 -= e3;
+                g -= dlt(c0 - 1) + dlt(c1 - 1) + dlt(c2 - 1) + dlt(c3 - 1);
+                h[v0 * 64] = (uint16_t)(c0 - 1);
+                h[v1 * 64] = (uint16_t)(c1 - 1);
+                h[v2 * 64] = (uint16_t)(c2 - 1);
+                h[v3 * 64] = (uint16_t)(c3 - 1);
+            }
         }
     };
-    auto remove_row = [&](int y) {
-        const uint8_t *row = col + (size_t)y * pitch;
-        for (int i = 0; i < dsz; ++i) {
-            const int v = row[i];
-            const int c = h[v * 64];
-            g -= dlt(c - 1);
-            h[v * 64] = (uint16_t)(c - 1);
+    // A sequence of row operations (row of op o, add or remove), each row
+    // loaded one operation ahead of its use.  Every removal follows the
+    // addition of its row, so no count goes below zero.
+    auto run = [&](int nops, auto row_of, auto add_of) {
+        uint32_t w0[NW], w1[NW];
+        load_row(w0, row_of(0));
+        for (int o = 0; o < nops; o += 2) {
+            if (o + 1 < nops) load_row(w1, row_of(o + 1));
+            apply_row(w0, add_of(o));
+            if (o + 2 < nops) load_row(w0, row_of(o + 2));
+            if (o + 1 < nops) apply_row(w1, add_of(o + 1));
         }
     };
     if (active) {
         int ytop = cy0 * L;
-        for (int r = 0; r < dsz; ++r) add_row(ytop + r);
+        run(DSZ, [&](int o) { return ytop + o; }, [](int) { return true; });
         d.keys[(size_t)cy0 * nx + cx] = g;
         gm = g;
         for (int cy = cy0 + 1; cy < cy1; ++cy) {
             const int ynew = cy * L;
-            if (L < dsz) {
-                for (int r = 0; r < L; ++r) {
-                    remove_row(ytop + r);
-                    add_row(ytop + dsz + r);
-                }
+            if (L < DSZ) {
+                // slide by L rows: remove row ytop + r, then add row ytop + DSZ + r
+                run(2 * L, [&](int o) { return ytop + (o >> 1) + (o & 1) * DSZ; },
+                    [](int o) { return (o & 1) != 0; });
             } else {
-                for (int r = 0; r < dsz; ++r) remove_row(ytop + r);
-                for (int r = 0; r < dsz; ++r) add_row(ynew + r);
+                run(2 * DSZ, [&](int o) { return o < DSZ ? ytop + o : ynew + o - DSZ; },
+                    [](int o) { return o >= DSZ; });
             }
             ytop = ynew;
             d.keys[(size_t)cy * nx + cx] = g;
@@ -346,7 +388,16 @@ hipError_t launch_pool_b(const BatchHost &b, const int64_t *table, hipStream_t s
     k_sel_init<<<dv.n, 256, 0, st>>>(dv);
     if (b.blocks[K_KEYS] > 0) {
         if (b.pool_key == FIC_POOL_VARIANCE) k_pool_keys_var<<<b.blocks[K_KEYS], 256, 0, st>>>(dv);
-        else k_pool_keys<<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table);
+        else {
+            switch (b.B) {
+                case 2: k_pool_keys<4><<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table); break;
+                case 4: k_pool_keys<8><<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table); break;
+                case 8: k_pool_keys<16><<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table); break;
+                case 16: k_pool_keys<32><<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table); break;
+                case 32: k_pool_keys<64><<<b.blocks[K_KEYS], 64, 0, st>>>(dv, table); break;
+                default: return hipErrorInvalidValue;
+            }
+        }
     }
     if (b.fused_sel) {
         k_sel_fused<<<dv.n, 1024, 0, st>>>(dv);

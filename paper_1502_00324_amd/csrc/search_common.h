@@ -25,17 +25,6 @@
 
 namespace fic {
 
-// Buffer pointers read out of the batch descriptors carry no address space
-// for the compiler, so loads through them become flat loads, and a flat load
-// counts on the LDS wait counter as well: every LDS wait in a loop would then
-// also wait for the global prefetch in flight.  All these buffers live in
-// global memory; these casts say so.
-template <class T>
-using gptr = const __attribute__((address_space(1))) T *;
-template <class T>
-__device__ __forceinline__ gptr<T> as_global(const T *p) {
-    return (gptr<T>)p;
-}
 // Class types (uint4, float2) cannot be copied out of another address
 // space; they are read as the plain vectors they hold.
 typedef uint32_t gv4u __attribute__((ext_vector_type(4)));
