@@ -258,6 +258,23 @@ __global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
     d.afrag[slot] = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// D4 of the 8 decimated positions (cy, cx0 .. cx0 + 7) of a domain at
+// (x0, y0): 2x2 sums over 16 bytes of image rows y0 + 2cy and y0 + 2cy + 1,
+// read as 4-byte words (unaligned); each 16-bit half of a word sum holds one
+// D4 <= 1020.
+__device__ __forceinline__ void d4_row8(gptr<uint8_t> pix, int pitch, int x0, int y0, int cy, int cx0, int (&d4)[8]) {
+    typedef uint32_t u32u __attribute__((aligned(1)));
+    const gptr<uint8_t> q = pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx0;
+    const gptr<u32u> r0 = (gptr<u32u>)q, r1 = (gptr<u32u>)(q + pitch);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t a = r0[i], c = r1[i];
+        const uint32_t t = (a & 0x00ff00ffu) + ((a >> 8) & 0x00ff00ffu) + (c & 0x00ff00ffu) + ((c >> 8) & 0x00ff00ffu);
+        d4[2 * i] = (int)(t & 0xffffu);
+        d4[2 * i + 1] = (int)(t >> 16);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     const int *pre = b.pre + K_BFRAG * (b.n + 1);
     const int im = find_img(pre, b.n, blockIdx.x);
@@ -278,17 +295,21 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
         // 16 positions (each D4 read once)
         if (s >= KA) return;
         uint32_t wh[4] = {0u, 0u, 0u, 0u}, wl[4] = {0u, 0u, 0u, 0u};
-        if (valid) {
+        if (valid) {   // B >= 8: each group of 8 positions lies in one decimated row
             const uint32_t v = d.pxy[p];
-            const int x0 = v & 0xffff, y0 = v >> 16, pitch = d.pitch;
+            const int x0 = v & 0xffff, y0 = v >> 16;
 #pragma unroll
-            for (int bb = 0; bb < 16; ++bb) {
-                const int k = 64 * s + 16 * kg + bb;
+            for (int g8 = 0; g8 < 2; ++g8) {
+                const int k = 64 * s + 16 * kg + 8 * g8;
                 const int cy = k / B, cx = k - cy * B;
-                const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
-                const int d4 = q[0] + q[1] + q[pitch] + q[pitch + 1];
-                wh[bb >> 2] |= (uint32_t)(uint8_t)(int8_t)((d4 >> 2) - 128) << (8 * (bb & 3));
-                wl[bb >> 2] |= (uint32_t)(d4 & 3) << (8 * (bb & 3));
+                int d4[8];
+                d4_row8(as_global(d.pix), d.pitch, x0, y0, cy, cx, d4);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int bb = 8 * g8 + e;
+                    wh[bb >> 2] |= (uint32_t)(uint8_t)(int8_t)((d4[e] >> 2) - 128) << (8 * (bb & 3));
+                    wl[bb >> 2] |= (uint32_t)(d4[e] & 3) << (8 * (bb & 3));
+                }
             }
         }
         d.bfrag[slot] = make_uint4(wh[0], wh[1], wh[2], wh[3]);
@@ -329,17 +350,16 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
             hv[4] = (_Float16)128.0f;
         }
         __builtin_memcpy(w, &hv, sizeof(w));
-    } else if (valid && f16) {
+    } else if (valid && f16) {   // B >= 8: the 8 positions lie in one decimated row
         const uint32_t v = d.pxy[p];
-        const int x0 = v & 0xffff, y0 = v >> 16, pitch = d.pitch;
+        const int x0 = v & 0xffff, y0 = v >> 16;
+        const int k = 32 * s + 8 * kg;
+        const int cy = k / B, cx = k - cy * B;
+        int d4[8];
+        d4_row8(as_global(d.pix), d.pitch, x0, y0, cy, cx, d4);
         h8v hv;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = 32 * s + 8 * kg + e;
-            const int cy = k / B, cx = k - cy * B;
-            const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
-            hv[e] = (_Float16)(q[0] + q[1] + q[pitch] + q[pitch + 1] - 512);
-        }
+        for (int e = 0; e < 8; ++e) hv[e] = (_Float16)(d4[e] - 512);
         __builtin_memcpy(w, &hv, sizeof(w));
     } else if (valid) {   // raw form: the pixels of the 2B x 2B block
         const uint32_t v = d.pxy[p];
