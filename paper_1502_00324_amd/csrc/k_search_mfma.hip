@@ -552,20 +552,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
         for (int s = 0; s < KR; ++s) Bf[s] = rd(buf, dt, s);
     };
+    // Longer tiles keep a ring of KD + 1 K-steps: step s + KD is read while
+    // the MFMAs of step s issue.
+    constexpr int KD = 2;
     auto mfma_tile = [&](Acc (&acc)[RQ][2][NP], int buf, int dt, v4i (&Bf)[KR]) {
 #pragma unroll
         for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl) acc[qi][0][pl] = acc[qi][1][pl] = Acc{0, 0, 0, 0};
+        v4i ring[PREF ? 1 : KD + 1][NP];
+        if constexpr (!PREF) {
+#pragma unroll
+            for (int s = 0; s < KD; ++s)
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl) ring[s][pl] = rd(buf, dt, pl * KA + s);
+        }
 #pragma unroll
         for (int s = 0; s < KA; ++s) {
             if constexpr (!PREF) {
+                if (s + KD < KA) {
 #pragma unroll
-                for (int pl = 0; pl < NP; ++pl) Bf[pl] = rd(buf, dt, pl * KA + s);
+                    for (int pl = 0; pl < NP; ++pl) ring[(s + KD) % (KD + 1)][pl] = rd(buf, dt, pl * KA + s + KD);
+                }
+                // keep the reads here: the scheduler would sink them next to their MFMAs
+                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl) {
-                const v4i &b = PREF ? Bf[pl * KA + s] : Bf[pl];
+                const v4i &b = PREF ? Bf[pl * KA + s] : ring[s % (KD + 1)][pl];
 #pragma unroll
                 for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
