@@ -289,6 +289,30 @@ VARIANCE_CASES = [
 ]
 
 
+# (B, L, pct, DN): steps below, at and above the window side 2B (the sliding
+# and the reloading key update), odd steps, on an image of odd width and height
+# (unaligned rows)
+POOL_GEOMS = [(2, 1, (3, 10), 0), (2, 3, (1, 2), 0), (2, 5, (3, 10), 40), (4, 3, (3, 10), 0), (4, 9, (0, 1), 0),
+              (8, 1, (3, 10), 0), (8, 7, (1, 2), 25), (16, 3, (3, 10), 0), (16, 33, (0, 1), 0), (32, 5, (3, 10), 0),
+              (32, 70, (0, 1), 0)]
+
+
+@pytest.mark.parametrize("geom", POOL_GEOMS, ids=lambda g: "B%d_L%d" % g[:2])
+def test_entropy_pool_any_step(ctx, geom):
+    """The entropy pool alone (Sec. 3, Eq 5-6) against the oracle: candidate
+    keys of every window size, selection, compaction and moments."""
+    B, L, pct, dn = geom
+    W, H = 203, 139
+    img = make_image(50 + B + L, W, H, 7)
+    ref = oracle.build_pool(img, B, L, pct, dn)
+    pool = ctx.build_domain_pool(torch.from_numpy(img).cuda(), B, L, pct, dn)
+    torch.cuda.synchronize()
+    got = pool.numpy()
+    assert len(got["xy"]) == len(ref["xy"]) > 0
+    for f in ("xy", "key", "sum4", "a"):
+        np.testing.assert_array_equal(got[f], ref[f], err_msg=f)
+
+
 @pytest.mark.parametrize("engine", [fic.ENGINE_MFMA, fic.ENGINE_FP32], ids=["mfma", "fp32"])
 @pytest.mark.parametrize("case", VARIANCE_CASES, ids=lambda c: c[0])
 def test_variance_pool_parity(ctx, case, engine):
