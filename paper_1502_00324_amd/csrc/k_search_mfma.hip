@@ -58,6 +58,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "fic_internal.h"
 #include "search_common.h"
 
@@ -402,7 +404,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     constexpr int STAGE = DT * KB * 64;          // uint4 per stage
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
-    __shared__ uint4 bl[2][STAGE];
+    // the two stage buffers of fragments, separate arrays: a stage's
+    // direct-to-LDS loads into one are then known not to touch the other
+    __shared__ uint4 bl0[STAGE];
+    __shared__ uint4 bl1[STAGE];
     __shared__ float2 dl[2][DT * kDomTile];     // (Sd4, sqrt A) per domain
     __shared__ int64_t dla[2][DT * kDomTile];   // exact A per domain
     __shared__ SLds sl;
@@ -498,18 +503,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // them inside the tile loop would also wait for the stage prefetch.
     __builtin_amdgcn_s_waitcnt(0);
 
-    uint4 pre[PER_T];
     // per-domain moments of a stage: DT * kDomTile entries over the 256 threads
     constexpr int PER_D = (DT * kDomTile + 255) / 256;
     float2 dpre[PER_D];
     int64_t apre[PER_D];
     int t0 = 0, t1 = 0;  // tile range of the chunk being streamed
-    auto gload = [&](int stg) {
+    // Fragments go straight from global memory to LDS (one 16-byte load per
+    // lane into 1 KiB per wave, no registers); indexes are clamped to the
+    // chunk's last tile, so the tiles past its end hold copies, harmless
+    // under their NaN moments.
+    auto gload = [&](uint4 *dst, int stg) {
         const int tbase = t0 + stg * DT;
+        const size_t fend = (size_t)t1 * KB * 64 - 1;
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
-            const int e = tid + 256 * i;
-            pre[i] = tbase + e / (KB * 64) < t1 ? ldg(bfrag, (size_t)tbase * KB * 64 + e) : make_uint4(0u, 0u, 0u, 0u);
+            const size_t e = min((size_t)tbase * KB * 64 + tid + 256 * i, fend);
+            __builtin_amdgcn_global_load_lds((gptr<void>)(bfrag + e),
+                                             (__attribute__((address_space(3))) void *)(dst + 64 * wave + 256 * i),
+                                             16, 0, 0);
         }
         // tiles past the chunk end get NaN moments: no pair on them passes
 #pragma unroll
@@ -523,8 +534,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         }
     };
     auto swrite = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
 #pragma unroll
         for (int i = 0; i < PER_D; ++i) {
             const int e = tid + 256 * i;
@@ -544,18 +553,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // just before its MFMAs, to bound registers.
     constexpr bool PREF = KB <= 8;
     constexpr int KR = PREF ? KB : NP;
-    auto rd = [&](int buf, int dt, int s) {
-        const uint4 u = bl[buf][(dt * KB + s) * 64 + lane];
+    auto rd = [&](const uint4 *Bs, int dt, int s) {
+        const uint4 u = Bs[(dt * KB + s) * 64 + lane];
         return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
     };
-    auto read_tile = [&](v4i (&Bf)[KR], int buf, int dt) {
+    auto read_tile = [&](v4i (&Bf)[KR], const uint4 *Bs, int dt) {
 #pragma unroll
-        for (int s = 0; s < KR; ++s) Bf[s] = rd(buf, dt, s);
+        for (int s = 0; s < KR; ++s) Bf[s] = rd(Bs, dt, s);
     };
     // Longer tiles keep a ring of KD + 1 K-steps: step s + KD is read while
     // the MFMAs of step s issue.
     constexpr int KD = 2;
-    auto mfma_tile = [&](Acc (&acc)[RQ][2][NP], int buf, int dt, v4i (&Bf)[KR]) {
+    auto mfma_tile = [&](Acc (&acc)[RQ][2][NP], const uint4 *Bs, int dt, v4i (&Bf)[KR]) {
 #pragma unroll
         for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
@@ -565,14 +574,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
             for (int s = 0; s < KD; ++s)
 #pragma unroll
-                for (int pl = 0; pl < NP; ++pl) ring[s][pl] = rd(buf, dt, pl * KA + s);
+                for (int pl = 0; pl < NP; ++pl) ring[s][pl] = rd(Bs, dt, pl * KA + s);
         }
 #pragma unroll
         for (int s = 0; s < KA; ++s) {
             if constexpr (!PREF) {
                 if (s + KD < KA) {
 #pragma unroll
-                    for (int pl = 0; pl < NP; ++pl) ring[(s + KD) % (KD + 1)][pl] = rd(buf, dt, pl * KA + s + KD);
+                    for (int pl = 0; pl < NP; ++pl) ring[(s + KD) % (KD + 1)][pl] = rd(Bs, dt, pl * KA + s + KD);
                 }
                 // keep the reads here: the scheduler would sink them next to their MFMAs
                 __builtin_amdgcn_sched_barrier(0);
@@ -614,13 +623,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     t1 = min(ntiles, t0 + geo.tpc);
     const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
     if (nstage > 0) {
-        gload(0);
+        gload(bl0, 0);
         swrite(0);
     }
+    // the direct-to-LDS loads count on vmcnt only: every wave drains its own
+    // before the barrier that publishes the stage
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int stg = 0; stg < nstage; ++stg) {
-        const int buf = stg & 1;
-        if (stg + 1 < nstage) gload(stg + 1);
+    // one stage on LDS buffer `buf` (a constant: each buffer is one array)
+    auto stage = [&](auto bc, int stg) {
+        constexpr int buf = decltype(bc)::value;
+        uint4 *const Bs = buf ? bl1 : bl0;
+        if (stg + 1 < nstage) gload(buf ? bl0 : bl1, stg + 1);
         // the range bests of other workgroups: issued after the stage prefetch
         // (so its wait does not include them) and applied at the stage end
         int64_t gl[RQ];
@@ -632,16 +646,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             // prune test of tile dt, in the same basic block
             Acc acc[2][RQ][2][NP];
             v4i Bq[2][KR];
-            if constexpr (PREF) read_tile(Bq[0], buf, 0);
-            mfma_tile(acc[0], buf, 0, Bq[0]);
-            if (PREF && DT > 1) read_tile(Bq[1], buf, 1);
+            if constexpr (PREF) read_tile(Bq[0], Bs, 0);
+            mfma_tile(acc[0], Bs, 0, Bq[0]);
+            if (PREF && DT > 1) read_tile(Bq[1], Bs, 1);
 #pragma unroll
             for (int dt = 0; dt < DT; ++dt) {
                 const int cur = dt & 1;
                 if (dt + 1 < DT) {
-                    mfma_tile(acc[cur ^ 1], buf, dt + 1, Bq[(dt + 1) & 1]);
+                    mfma_tile(acc[cur ^ 1], Bs, dt + 1, Bq[(dt + 1) & 1]);
                     // the set of tile dt is free once tile dt's MFMAs were issued
-                    if (PREF && dt + 2 < DT) read_tile(Bq[dt & 1], buf, dt + 2);
+                    if (PREF && dt + 2 < DT) read_tile(Bq[dt & 1], Bs, dt + 2);
                 }
                 bool pass[RQ];
                 bool any = false;
@@ -685,7 +699,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                     v4i bt1 = v4i{0, 0, 0, 0};
                     int64_t ed = 0;
                     if constexpr (FT) {
-                        const uint4 u = bl[buf][(dt * KB) * 64 + lane];
+                        const uint4 u = Bs[(dt * KB) * 64 + lane];
                         bt1 = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
                         ed = sd4 - (int64_t)n * round_mean(sd4, n);
                     }
@@ -733,7 +747,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             }
             if (FT && __builtin_amdgcn_ballot_w64(changed)) build_thr(qi);
         }
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the next stage
         __syncthreads();
+    };
+    for (int stg = 0; stg < nstage; stg += 2) {
+        stage(std::integral_constant<int, 0>{}, stg);
+        if (stg + 1 < nstage) stage(std::integral_constant<int, 1>{}, stg + 1);
     }
   }
 
