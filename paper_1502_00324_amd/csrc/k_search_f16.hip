@@ -35,6 +35,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "fic_internal.h"
 #include "search_common.h"
 
@@ -193,7 +195,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     constexpr bool SHARE = DT >= 4;
     constexpr int PER_T = STAGE / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
-    __shared__ uint4 bl[2][STAGE];
+    // the two stage buffers of fragments, separate arrays: a stage's
+    // direct-to-LDS loads into one are then known not to touch the other
+    __shared__ uint4 bl0[STAGE];
+    __shared__ uint4 bl1[STAGE];
     __shared__ float2 dl[2][DT * kDomTile32];     // (Sd4, sqrt A) per domain
     __shared__ int64_t dla[2][DT * kDomTile32];   // exact A per domain
     __shared__ SLds sl;
@@ -256,18 +261,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // the tile loop would also wait for the stage prefetch
     __builtin_amdgcn_s_waitcnt(0);
 
-    uint4 pre[PER_T];
     // per-domain moments of a stage: DT * kDomTile32 entries over the 256 threads
     constexpr int PER_D = (DT * kDomTile32 + 255) / 256;
     float2 dpre[PER_D];
     int64_t apre[PER_D];
     int t0 = 0, t1 = 0;
-    auto gload = [&](int stg) {
+    // Fragments go straight from global memory to LDS (one 16-byte load per
+    // lane into 1 KiB per wave, no registers); indexes are clamped to the
+    // chunk's last tile, so the tiles past its end hold copies, harmless
+    // under their NaN moments.
+    auto gload = [&](uint4 *dst, int stg) {
         const int tbase = t0 + stg * DT;
+        const size_t fend = (size_t)t1 * KS * 64 - 1;
 #pragma unroll
         for (int i = 0; i < PER_T; ++i) {
-            const int e = tid + 256 * i;
-            pre[i] = tbase + e / (KS * 64) < t1 ? ldg(bfrag, (size_t)tbase * KS * 64 + e) : make_uint4(0u, 0u, 0u, 0u);
+            const size_t e = min((size_t)tbase * KS * 64 + tid + 256 * i, fend);
+            __builtin_amdgcn_global_load_lds((gptr<void>)(bfrag + e),
+                                             (__attribute__((address_space(3))) void *)(dst + 64 * wave + 256 * i),
+                                             16, 0, 0);
         }
         // tiles past the chunk end get NaN moments: no pair on them passes
 #pragma unroll
@@ -281,8 +292,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         }
     };
     auto swrite = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < PER_T; ++i) bl[buf][tid + 256 * i] = pre[i];
 #pragma unroll
         for (int i = 0; i < PER_D; ++i) {
             const int e = tid + 256 * i;
@@ -299,19 +308,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // covered by the previous tile; longer tiles read them in groups of 8.
     constexpr bool PREF = KS <= 4;
     constexpr int KG = PREF ? KS : 8;
-    auto read_tile = [&](h8 (&bf)[KG], int buf, int dt, int s0) {
+    auto read_tile = [&](h8 (&bf)[KG], const uint4 *Bs, int dt, int s0) {
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
-            const uint4 u = bl[buf][(dt * KS + s0 + s) * 64 + lane];
+            const uint4 u = Bs[(dt * KS + s0 + s) * 64 + lane];
             __builtin_memcpy(&bf[s], &u, sizeof(h8));
         }
     };
-    auto mfma_tile = [&](f16x (&acc)[RQ], int buf, int dt, h8 (&bq)[KG]) {
+    auto mfma_tile = [&](f16x (&acc)[RQ], const uint4 *Bs, int dt, h8 (&bq)[KG]) {
 #pragma unroll
         for (int qi = 0; qi < RQ; ++qi) acc[qi] = f16x{0.f};
 #pragma unroll
         for (int s0 = 0; s0 < KS; s0 += KG) {
-            if constexpr (!PREF) read_tile(bq, buf, dt, s0);
+            if constexpr (!PREF) read_tile(bq, Bs, dt, s0);
 #pragma unroll
             for (int s = 0; s < KG; ++s)
 #pragma unroll
@@ -325,13 +334,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         t1 = min(ntiles, t0 + geo.tpc);
         const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
         if (nstage > 0) {
-            gload(0);
+            gload(bl0, 0);
             swrite(0);
         }
+        // the direct-to-LDS loads count on vmcnt only: every wave drains its
+        // own before the barrier that publishes the stage
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        for (int stg = 0; stg < nstage; ++stg) {
-            const int buf = stg & 1;
-            if (stg + 1 < nstage) gload(stg + 1);
+        // one stage on LDS buffer `buf` (a constant: each buffer is one array)
+        auto stage = [&](auto bc, int stg) {
+            constexpr int buf = decltype(bc)::value;
+            uint4 *const Bs = buf ? bl1 : bl0;
+            if (stg + 1 < nstage) gload(buf ? bl0 : bl1, stg + 1);
             // the range bests of other workgroups: issued after the stage
             // prefetch (so its wait does not include them), applied at the end
             int64_t gl[RQ][2];
@@ -344,16 +358,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 const int tbase = t0 + stg * DT;
                 f16x acc[2][RQ];
                 h8 bq[2][KG];
-                if constexpr (PREF) read_tile(bq[0], buf, 0, 0);
-                mfma_tile(acc[0], buf, 0, bq[0]);
-                if (PREF && DT > 1) read_tile(bq[1], buf, 1, 0);
+                if constexpr (PREF) read_tile(bq[0], Bs, 0, 0);
+                mfma_tile(acc[0], Bs, 0, bq[0]);
+                if (PREF && DT > 1) read_tile(bq[1], Bs, 1, 0);
 #pragma unroll
                 for (int dt = 0; dt < DT; ++dt) {
                     const int cur = dt & 1;
                     if (dt + 1 < DT) {
-                        mfma_tile(acc[cur ^ 1], buf, dt + 1, bq[(dt + 1) & 1]);
+                        mfma_tile(acc[cur ^ 1], Bs, dt + 1, bq[(dt + 1) & 1]);
                         // the set of tile dt is free once tile dt's MFMAs were issued
-                        if (PREF && dt + 2 < DT) read_tile(bq[dt & 1], buf, dt + 2, 0);
+                        if (PREF && dt + 2 < DT) read_tile(bq[dt & 1], Bs, dt + 2, 0);
                     }
                     const float2 di = dl[buf][dt * kDomTile32 + (lane & 31)];
                     bool pass[RQ][2];
@@ -416,7 +430,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                         tb[qi][u] = gl[qi][u];
                         tn[qi][u] = tn_shared(gl[qi][u], cr[qi][u], sc, tfac);
                     }
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the next stage
             __syncthreads();
+        };
+        for (int stg = 0; stg < nstage; stg += 2) {
+            stage(std::integral_constant<int, 0>{}, stg);
+            if (stg + 1 < nstage) stage(std::integral_constant<int, 1>{}, stg + 1);
         }
     }
 
