@@ -108,8 +108,17 @@ __global__ __launch_bounds__(256) void k_finalize(BatchDev b, SSet ss, fic_ratio
     const int nslot = d.nslot;
     int64_t bv = INT64_MAX;
     int bp = INT32_MAX, bk = 0;
+    // partials read as 16-byte words (val lo, val hi, p, k) through a
+    // global-qualified pointer
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    static_assert(sizeof(Partial) == 16, "Partial is read as one 16-byte word");
+    const gptr<u32x4> pq = (gptr<u32x4>)as_global(d.part);
     for (int c = lane; c < nslot; c += 64) {
-        const Partial q = d.part[(size_t)r * nslot + c];
+        const u32x4 w = pq[(size_t)r * nslot + c];
+        Partial q;
+        q.val = (int64_t)(((uint64_t)w.y << 32) | w.x);
+        q.p = (int32_t)w.z;
+        q.k = (int32_t)w.w;
         if (q.p >= 0 && lex_less(q.val, q.p, bv, bp)) {
             bv = q.val;
             bp = q.p;
@@ -146,29 +155,52 @@ __global__ __launch_bounds__(256) void k_finalize(BatchDev b, SSet ss, fic_ratio
     if (nk != 0) {
         const uint32_t dv = d.pxy[bp];
         const int dx0 = dv & 0xffff, dy0 = dv >> 16;
-        int64_t x4[8];
+        const gptr<uint8_t> im = as_global(img);
+        // X4 of every isometry: |X4| <= 1024 * 255 * 1020 < 2^31
+        int32_t x4[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) x4[t] = 0;
         for (int i = lane; i < n; i += 64) {
             const int y = i / B, x = i - y * B;
-            const int rv = img[(size_t)(y0 + y) * pitch + x0 + x];
+            const int rv = im[(size_t)(y0 + y) * pitch + x0 + x];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 int cy, cx;
                 iso_src(t, B, y, x, cy, cx);
-                const uint8_t *q = img + (size_t)(dy0 + 2 * cy) * pitch + dx0 + 2 * cx;
-                x4[t] += (int64_t)rv * (q[0] + q[1] + q[pitch] + q[pitch + 1]);
+                const gptr<uint8_t> q = im + (size_t)(dy0 + 2 * cy) * pitch + dx0 + 2 * cx;
+                x4[t] += rv * (q[0] + q[1] + q[pitch] + q[pitch + 1]);
             }
         }
-        int64_t best = 0;
+        // The 8 wave sums by halving exchanges: after the steps at lane
+        // distances 32, 16 and 8 each lane holds one isometry's partial,
+        // t = (lane >> 3) & 7, summed over 8 lanes; three more steps finish
+        // the sums.  Then the largest sum, the smallest t on ties.
+        const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+        int32_t y4[4], z2[2];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int64_t s = wave_sum_i64(x4[t]);
-            if (t == 0 || s > best) {
-                best = s;
-                t_best = t;
+        for (int k = 0; k < 4; ++k) {
+            const int32_t keep = b5 ? x4[4 + k] : x4[k], give = b5 ? x4[k] : x4[4 + k];
+            y4[k] = keep + __shfl_xor(give, 32, 64);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int32_t keep = b4 ? y4[2 + k] : y4[k], give = b4 ? y4[k] : y4[2 + k];
+            z2[k] = keep + __shfl_xor(give, 16, 64);
+        }
+        int32_t w = (b3 ? z2[1] : z2[0]) + __shfl_xor(b3 ? z2[0] : z2[1], 8, 64);
+        w += __shfl_xor(w, 4, 64);
+        w += __shfl_xor(w, 2, 64);
+        w += __shfl_xor(w, 1, 64);
+        int32_t bw = w, bt = (b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0);
+#pragma unroll
+        for (int off = 8; off < 64; off <<= 1) {
+            const int32_t ow = __shfl_xor(bw, off, 64), ot = __shfl_xor(bt, off, 64);
+            if (ow > bw || (ow == bw && ot < bt)) {
+                bw = ow;
+                bt = ot;
             }
         }
+        t_best = bt;
     }
     if (lane == 0) {
         const int64_t o = (2 * sr + n) / (2 * n);
