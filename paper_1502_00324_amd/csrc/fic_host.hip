@@ -360,7 +360,8 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
                 const int ntiles = (int)cdiv(d.pool_cap, tile);
                 const long afr = (long)nquads * (f16 ? 1 : 2) * d.geo.ka;   // 1 KiB fragments
                 blk[K_AFRAG] = cdiv(afr * 64, 256);
-                blk[K_BFRAG] = cdiv((long)ntiles * d.geo.kt * 64, 256);
+                // int8 planes: one thread writes both planes of a K-step
+                blk[K_BFRAG] = cdiv((long)ntiles * (d.geo.pl == 2 ? d.geo.ka : d.geo.kt) * 64, 256);
                 blk[K_SEARCH] = cdiv(d.geo.nwg, 8) * 8;  // image blocks start at multiples of 8
                 d.nslot = d.geo.nslot;
                 d.afrag = (uint4 *)take(S_AFRAG, (size_t)afr * 1024);

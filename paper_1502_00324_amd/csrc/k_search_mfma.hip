@@ -284,18 +284,20 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
     const int B = d.B, KA = d.geo.ka, KT = d.geo.kt, planes = d.geo.pl == 2, f16 = d.geo.pl == 3,
               ft = d.geo.pl == 4;
     const int ntiles = (d.pool_cap + kDomTile - 1) / kDomTile;
-    const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;   // can pass 2^31
-    if (slot >= (int64_t)ntiles * KT * 64) return;
-    const int lane = (int)(slot & 63);
-    const int rest = (int)(slot >> 6);
-    const int s = rest % KT, tile = rest / KT;
+    // one thread per (tile, K-step, lane) of the output; in the planes form
+    // one per K-step of the hi plane, writing both planes
+    const int KS = planes ? KA : KT;
+    const int64_t gid = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;   // can pass 2^31
+    if (gid >= (int64_t)ntiles * KS * 64) return;
+    const int lane = (int)(gid & 63);
+    const int rest = (int)(gid >> 6);
+    const int s = rest % KS, tile = rest / KS;
+    const int64_t slot = ((int64_t)tile * KT + s) * 64 + lane;
     const int j = lane & 15, kg = lane >> 4;
     const int p = tile * kDomTile + j;
     const bool valid = p < min(*d.pcount, d.pool_cap);
     if (planes) {
-        // one thread per K-step of the hi plane writes both planes of its
-        // 16 positions (each D4 read once)
-        if (s >= KA) return;
+        // both planes of the thread's 16 positions (each D4 read once)
         uint32_t wh[4] = {0u, 0u, 0u, 0u}, wl[4] = {0u, 0u, 0u, 0u};
         if (valid) {   // B >= 8: each group of 8 positions lies in one decimated row
             const uint32_t v = d.pxy[p];
