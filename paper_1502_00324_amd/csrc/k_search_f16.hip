@@ -183,9 +183,11 @@ __global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
 
 // ---------------------------------------------------------------- search
 // A workgroup of 4 waves owns 16 RQ ranges (each wave RQ quads) and the
-// domain tiles of its chunks.  Domain fragments go global -> registers -> LDS
-// in stages of DT tiles, double-buffered; the MFMAs of tile t+1 are issued
-// before the prune test of tile t.
+// domain tiles of its chunks.  Domain fragments go straight from global
+// memory into LDS in stages of DT tiles, double-buffered (the loads of stage
+// s+1 are issued before the MFMAs of stage s); the per-domain moments pass
+// through registers.  The MFMAs of tile t+1 are issued before the prune test
+// of tile t.
 template <int KS, int RQ, int DT, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_f16_search(BatchDev bt, SSet ss) {
     constexpr bool CEN = KS <= 4;                // mean-centred operands (B <= 8)

@@ -385,9 +385,10 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
 
 // ---------------------------------------------------------------- search
 // A workgroup of 4 waves owns 16 RQ ranges (each wave RQ quads) and one chunk
-// of domain tiles.  Domain fragments go global -> registers -> LDS in stages
-// of DT tiles, double-buffered: the loads for stage s+1 are issued before the
-// MFMAs of stage s and written to the other LDS buffer after them.
+// of domain tiles.  Domain fragments go straight from global memory into
+// LDS in stages of DT tiles, double-buffered: the loads of stage s+1 into the
+// other buffer are issued before the MFMAs of stage s; the per-domain moments
+// pass through registers and are written after them.
 template <int PL> struct AccOf { typedef v4i type; typedef int max_type; };   // int32 accumulators
 template <> struct AccOf<3> { typedef v4f type; typedef float max_type; };  // f16 form: f32 accumulators
 template <> struct AccOf<4> { typedef v4f type; typedef float max_type; };  // f16, fused threshold
@@ -546,13 +547,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         }
     };
     // acc[qi][h][plane]: the planes are combined (4 hi + lo) at the test,
-    // one tile later, so no MFMA result is waited for at issue time
-    // (up to 8 K-steps the tile's fragments are read up front; longer tiles
-    // read each K-step's fragments just before its MFMAs, to bound registers)
+    // one tile later, so no MFMA result is waited for at issue time.
     // Up to 8 K-steps a tile's fragments are read into registers one tile
     // ahead of its MFMAs (two register sets alternate), so the LDS latency is
-    // covered by the previous tile; longer tiles read each K-step's fragments
-    // just before its MFMAs, to bound registers.
+    // covered by the previous tile; longer tiles keep a ring of a few K-steps
+    // (below), to bound registers.
     constexpr bool PREF = KB <= 8;
     constexpr int KR = PREF ? KB : NP;
     auto rd = [&](const uint4 *Bs, int dt, int s) {
