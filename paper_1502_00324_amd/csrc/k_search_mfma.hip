@@ -138,16 +138,18 @@ static int slots_per_xcd() {
     return v >= 1 && v <= 64 ? v : 2;
 }
 
-// Target chunk size in KiB of fragments (FIC_CHUNK_KIB overrides).
-static int chunk_kib() {
-    const char *e = getenv("FIC_CHUNK_KIB");
+// Target chunk size in KiB of fragments: measured best at 1536 for the f16
+// 32x32 form, 768 for the 16-row forms (FIC_CHUNK_KIB, FIC_MFMA_CHUNK_KIB
+// override them).
+static int chunk_kib(bool rows16) {
+    const char *e = getenv(rows16 ? "FIC_MFMA_CHUNK_KIB" : "FIC_CHUNK_KIB");
     const int v = e ? atoi(e) : 0;
-    return v >= 64 && v <= 16384 ? v : 1536;
+    return v >= 64 && v <= 16384 ? v : rows16 ? 768 : 1536;
 }
 
-void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt) {
+void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt, bool rows16) {
     g.nrg = (range_cap + g.rpw - 1) / g.rpw;
-    g.tpc = max(8 * dt, chunk_kib() / tile_kib);
+    g.tpc = max(8 * dt, chunk_kib(rows16) / tile_kib);
     g.nchunk = (ntiles + g.tpc - 1) / g.tpc;
     if (g.nchunk < 8) {
         // small pool: split finer only to give the GPU enough workgroups
@@ -179,7 +181,7 @@ MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, const TileShape &sh) 
     g.kt = sh.pl == 2 ? 2 * g.ka : g.ka;
     g.rpw = 16 * sh.rq;
     const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
-    split_chunks(g, range_cap, ntiles, g.kt, sh.dt);
+    split_chunks(g, range_cap, ntiles, g.kt, sh.dt, true);
     return g;
 }
 
