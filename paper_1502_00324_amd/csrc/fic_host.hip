@@ -353,8 +353,14 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
             if (eng != E_FP32) {
                 // int8: A fragments per quad and half; f16: per quad (32 rows)
                 const bool f16 = eng == E_F16;
-                d.geo = f16 ? f16_geometry(d.B, d.range_cap, d.pool_cap, pl.bh.shape)
-                            : mfma_geometry(d.B, d.range_cap, d.pool_cap, pl.bh.shape);
+                // chunks are counted for the pool size the percentile and the cap
+                // leave (the capacity may hold every candidate); the kernels split
+                // the actual pool evenly over them
+                long long pexp = d.nd - d.c;
+                if (d.pool_max > 0) pexp = min(pexp, (long long)d.pool_max);
+                pexp = max(1LL, min(pexp, (long long)d.pool_cap));
+                d.geo = f16 ? f16_geometry(d.B, d.range_cap, (int)pexp, pl.bh.shape)
+                            : mfma_geometry(d.B, d.range_cap, (int)pexp, pl.bh.shape);
                 const int nquads = d.geo.nrg * (d.geo.rpw / 4);
                 const int tile = f16 ? kDomTile32 : kDomTile;
                 const int ntiles = (int)cdiv(d.pool_cap, tile);

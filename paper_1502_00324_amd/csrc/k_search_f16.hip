@@ -332,8 +332,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     };
     for (int cj = 0; cj < ncs; ++cj) {
         const int chunk = cfirst + cj * cstep;
-        t0 = chunk * geo.tpc;
-        t1 = min(ntiles, t0 + geo.tpc);
+        // the chunks split the actual pool evenly (their count is fixed by the
+        // plan, the pool size only known here)
+        const int tpc = (ntiles + geo.nchunk - 1) / geo.nchunk;
+        t0 = chunk * tpc;
+        t1 = min(ntiles, t0 + tpc);
         const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
         if (nstage > 0) {
             gload(bl0, 0);

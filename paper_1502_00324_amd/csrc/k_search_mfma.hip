@@ -138,13 +138,13 @@ static int slots_per_xcd() {
     return v >= 1 && v <= 64 ? v : 2;
 }
 
-// Target chunk size in KiB of fragments: measured best at 1536 for the f16
-// 32x32 form, 768 for the 16-row forms (FIC_CHUNK_KIB, FIC_MFMA_CHUNK_KIB
-// override them).
+// Target chunk size in KiB of fragments, over the expected pool: measured
+// best at 2048 for the f16 32x32 form, 1024 for the 16-row forms
+// (FIC_CHUNK_KIB, FIC_MFMA_CHUNK_KIB override them).
 static int chunk_kib(bool rows16) {
     const char *e = getenv(rows16 ? "FIC_MFMA_CHUNK_KIB" : "FIC_CHUNK_KIB");
     const int v = e ? atoi(e) : 0;
-    return v >= 64 && v <= 16384 ? v : rows16 ? 768 : 1536;
+    return v >= 64 && v <= 16384 ? v : rows16 ? 1024 : 2048;
 }
 
 void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt, bool rows16) {
@@ -622,8 +622,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     };
   for (int cj = 0; cj < ncs; ++cj) {
     const int chunk = cfirst + cj * cstep;
-    t0 = chunk * geo.tpc;
-    t1 = min(ntiles, t0 + geo.tpc);
+    // the chunks split the actual pool evenly (their count is fixed by the
+    // plan, the pool size only known here)
+    const int tpc = (ntiles + geo.nchunk - 1) / geo.nchunk;
+    t0 = chunk * tpc;
+    t1 = min(ntiles, t0 + tpc);
     const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
     if (nstage > 0) {
         gload(bl0, 0);
