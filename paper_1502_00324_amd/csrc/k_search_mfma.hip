@@ -135,7 +135,7 @@ TileShape mfma_pick(int B, bool f16, int choice) {
 static int slots_per_xcd() {
     const char *e = getenv("FIC_SLOTS_PER_XCD");
     const int v = e ? atoi(e) : 0;
-    return v >= 1 && v <= 64 ? v : 2;
+    return v >= 1 && v <= 64 ? v : 4;
 }
 
 // Target chunk size in KiB of fragments, over the expected pool: measured
