@@ -147,6 +147,25 @@ def test_constant_and_block_constant_images(ctx, engine):
 
 
 @pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+def test_tied_entropy_pool_larger_than_planned(ctx, engine):
+    """Every 2B x 2B window of a period-2 pattern has the same histogram, so
+    all entropy keys tie, the percentile drops nothing strictly and the
+    equal-to-minimum rule keeps every candidate: the pool exceeds the size
+    the chunks were planned for (Nd - ceil(p Nd)), and the searched ranges
+    (not constant) must still see every domain."""
+    yy, xx = np.mgrid[0:96, 0:128]
+    for img in (np.where((yy + xx) % 2 == 0, 60, 190).astype(np.uint8),
+                np.where(xx % 2 == 0, 30, 220).astype(np.uint8)):
+        levels = [(8, 2), (4, 2)]
+        p = params(levels, (3, 10), 0, K16, 16, (8, 1), engine)
+        got, _ = gpu_run(ctx, img, p)
+        ref = oracle_run(img, levels, (3, 10), 0, K16, 16, (8, 1))
+        nd = ((128 - 16) // 2 + 1) * ((96 - 16) // 2 + 1)
+        assert len(ref[0]["pool"]["xy"]) == nd
+        assert_levels_equal(got, ref, "tied_pool")
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
 def test_config2_512_full_parity(ctx, engine):
     wl = WORKLOADS["c2_512"]
     seed, W, H, nrect = wl.images[0]
