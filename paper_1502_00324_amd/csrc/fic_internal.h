@@ -163,7 +163,7 @@ struct MfmaGeom {
 };
 MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, const TileShape &sh);   // 16-row engine
 MfmaGeom f16_geometry(int B, int range_cap, int pool_cap, const TileShape &sh);    // 32x32 f16 engine
-void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt, bool rows16);
+void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt, bool rows16, int slots);
 
 // Range group, chunk walk and partial-result slot of search workgroup lb.
 __device__ inline void chunk_walk(const MfmaGeom &geo, int lb, int &rg, int &cfirst, int &cstep, int &ncs,

@@ -95,7 +95,7 @@ MfmaGeom f16_geometry(int B, int range_cap, int pool_cap, const TileShape &sh) {
     g.kt = g.ka;
     g.rpw = 16 * sh.rq;
     const int ntiles = (pool_cap + kDomTile32 - 1) / kDomTile32;
-    split_chunks(g, range_cap, ntiles, g.kt, sh.dt, false);
+    split_chunks(g, range_cap, ntiles, g.kt, sh.dt, false, 4);
     return g;
 }
 

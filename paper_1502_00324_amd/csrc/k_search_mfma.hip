@@ -131,11 +131,12 @@ TileShape mfma_pick(int B, bool f16, int choice) {
 // its XCD with one running best over them (about a quarter of the XCD's
 // chunks, and enough to keep the partial results, one per range and slot,
 // under 256 MB).  tile_kib is the fragment size of one domain tile in KiB.
-// Partial-result slots per XCD and range group (FIC_SLOTS_PER_XCD overrides).
-static int slots_per_xcd() {
+// Partial-result slots per XCD and range group: measured best at 8 for
+// B = 32, 4 otherwise (FIC_SLOTS_PER_XCD overrides both).
+static int slots_per_xcd(int dflt) {
     const char *e = getenv("FIC_SLOTS_PER_XCD");
     const int v = e ? atoi(e) : 0;
-    return v >= 1 && v <= 64 ? v : 4;
+    return v >= 1 && v <= 64 ? v : dflt;
 }
 
 // Target chunk size in KiB of fragments, over the expected pool: measured
@@ -147,7 +148,7 @@ static int chunk_kib(bool rows16) {
     return v >= 64 && v <= 16384 ? v : rows16 ? 1024 : 2048;
 }
 
-void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt, bool rows16) {
+void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt, bool rows16, int slots) {
     g.nrg = (range_cap + g.rpw - 1) / g.rpw;
     g.tpc = max(8 * dt, chunk_kib(rows16) / tile_kib);
     g.nchunk = (ntiles + g.tpc - 1) / g.tpc;
@@ -164,7 +165,7 @@ void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt, 
         const int per_xcd = g.nchunk / 8;
         const long max_slots = max(8L, (256L << 20) / 16 / max(1, range_cap));
         const int groups_max = (int)max(1L, max_slots / 8);
-        const int spx = slots_per_xcd();
+        const int spx = slots_per_xcd(slots);
         g.G = max((per_xcd + groups_max - 1) / groups_max, (per_xcd + spx - 1) / spx);
         g.nslot = 8 * ((per_xcd + g.G - 1) / g.G);
     } else {
@@ -181,7 +182,7 @@ MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, const TileShape &sh) 
     g.kt = sh.pl == 2 ? 2 * g.ka : g.ka;
     g.rpw = 16 * sh.rq;
     const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
-    split_chunks(g, range_cap, ntiles, g.kt, sh.dt, true);
+    split_chunks(g, range_cap, ntiles, g.kt, sh.dt, true, B == 32 ? 8 : 4);
     return g;
 }
 
