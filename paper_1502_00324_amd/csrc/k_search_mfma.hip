@@ -131,7 +131,7 @@ TileShape mfma_pick(int B, bool f16, int choice) {
 // its XCD with one running best over them (about a quarter of the XCD's
 // chunks, and enough to keep the partial results, one per range and slot,
 // under 256 MB).  tile_kib is the fragment size of one domain tile in KiB.
-// Partial-result slots per XCD and range group: measured best at 8 for
+// Partial-result slots per XCD and range group: measured best at 16 for
 // B = 32, 4 otherwise (FIC_SLOTS_PER_XCD overrides both).
 static int slots_per_xcd(int dflt) {
     const char *e = getenv("FIC_SLOTS_PER_XCD");
@@ -182,7 +182,7 @@ MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, const TileShape &sh) 
     g.kt = sh.pl == 2 ? 2 * g.ka : g.ka;
     g.rpw = 16 * sh.rq;
     const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
-    split_chunks(g, range_cap, ntiles, g.kt, sh.dt, true, B == 32 ? 8 : 4);
+    split_chunks(g, range_cap, ntiles, g.kt, sh.dt, true, B == 32 ? 16 : 4);
     return g;
 }
 
