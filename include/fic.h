@@ -265,9 +265,21 @@ int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool,
                      fic_level_codes *out, uint32_t *children_xy, int32_t *n_children,
                      fic_stream stream);
 
-/* Whole encoder for n_images images with one parameter set: pools and codes
- * are arrays of n_images*levels entries, image-major.  codes[i*levels+l].xy
- * and .count hold level l's ranges; capacities as fic_query_capacity. */
+/* Sec. 2, Fig 1 (the quadtree steps), applied to every image of a batch:
+ * level 0 searches every B x B range of each image against that image's
+ * level-0 pool (Sec. 3, Eq 5-6); each later level searches the quarters of
+ * the ranges the previous level split, with B halved and its own pool, step
+ * and contrast set; the last level accepts every range.  Images are
+ * independent: a batch gives the same codes as encoding each image alone.
+ * imgs: n_images device images (n_images >= 0; 0 is a no-op).  pools and
+ * codes are caller arrays of n_images*levels entries, image-major
+ * (entry i*levels + l is image i, level l), each with device buffers of at
+ * least the fic_query_capacity sizes for that image (FIC_E_CAPACITY
+ * otherwise, nothing enqueued); codes[i*levels+l].xy and .count receive
+ * level l's ranges.  Every image is validated against p first
+ * (FIC_E_INVALID).  Scratch comes from the context (FIC_E_NOMEM when it
+ * cannot grow).  With graph replay on (fic_ctx_set_graphs) a repeat of the
+ * exact arguments replays the captured encode. */
 int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_params *p,
                fic_pool *pools, fic_level_codes *codes, fic_stream stream);
 

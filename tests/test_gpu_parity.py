@@ -59,6 +59,55 @@ def assert_levels_equal(got, ref, tag=""):
             np.testing.assert_array_equal(g["codes"][f], r["codes"][f], err_msg="%s level %d %s" % (tag, l, f))
 
 
+def gradient_energy(img, B0):
+    """Per level-0 range: the sum of squared neighbour differences, the ranges
+    most likely to split down to the last level."""
+    H, W = img.shape
+    f = img.astype(np.int64)
+    ge = np.zeros_like(f)
+    ge[:, :-1] += (f[:, 1:] - f[:, :-1]) ** 2
+    ge[:-1, :] += (f[1:, :] - f[:-1, :]) ** 2
+    return ge.reshape(H // B0, B0, W // B0, B0).sum(axis=(1, 3)).ravel()
+
+
+def oracle_subtrees(img, pools, levels, ranges, s_num, s_den, rms):
+    """The oracle's codes of the given level-0 ranges and their whole quadtree
+    subtrees (Sec. 2, Fig 1), against the full pools: [(ranges, codes)] per level."""
+    refs = []
+    for l, (B, L) in enumerate(levels):
+        last = l == len(levels) - 1
+        ref = oracle.encode_level(img, pools[l]["xy"], ranges, B, list(s_num), s_den, rms, last, workers=WORKERS)
+        refs.append((ranges, ref))
+        if last:
+            break
+        ranges = oracle.children(ranges, ref["split"], B)
+        if len(ranges) == 0:
+            break
+    return refs
+
+
+def assert_pools_equal(got, pools, tag):
+    for l, ref_pool in enumerate(pools):
+        for f in ("xy", "key", "sum4", "a"):
+            np.testing.assert_array_equal(got[l]["pool"][f], ref_pool[f], err_msg="%s level %d pool %s" % (tag, l, f))
+
+
+def assert_subtrees_equal(got, refs, tag):
+    """The GPU codes of the sampled ranges (found by position) equal the oracle's."""
+    for l, (ranges, ref) in enumerate(refs):
+        pos = {int(v): i for i, v in enumerate(got[l]["codes"]["xy"])}
+        idx = np.array([pos[int(v)] for v in ranges], np.int64)
+        for f in ("split", "domain", "iso", "s_idx", "offset", "err"):
+            np.testing.assert_array_equal(got[l]["codes"][f][idx], ref[f], err_msg="%s level %d %s" % (tag, l, f))
+
+
+def as_oracle_levels(got):
+    """GPU codes and pools of one image in the oracle's level layout, so that
+    the oracle decoder can rebuild an image from the GPU's own codes."""
+    return [{"B": g["B"], "ranges": g["codes"]["xy"], "pool": g["pool"], "codes": g["codes"],
+             "s_num": g["s_num"], "s_den": g["s_den"]} for g in got]
+
+
 CASES = [
     # name, seed, W, H, n_rect, levels, pct, pool_max, s_num, s_den, split_rms
     ("c1_64", 0, 64, 64, 10, [(8, 4), (4, 4)], (3, 10), 0, K16, 16, (8, 1)),
@@ -177,39 +226,33 @@ def test_config2_512_full_parity(ctx, engine):
     np.testing.assert_array_equal(dec, oracle.decode(W, H, ref, 8))
 
 
-def test_config3_1024_sampled_parity(ctx):
-    """Full-size c3 (L = 1, ~0.7 M domains per level): both pools in full, and
-    the codes of 24 seeded level-0 ranges with their whole quadtree subtrees."""
+@pytest.fixture(scope="module")
+def c3_reference():
+    """Full-size c3 (L = 1, ~0.7 M domains per level): the oracle's pools in
+    full and the codes of 24 seeded level-0 ranges with their whole quadtree
+    subtrees."""
     wl = WORKLOADS["c3_1024"]
     seed, W, H, nrect = wl.images[0]
     img = make_image(seed, W, H, nrect)
-    p = params(wl.levels, wl.pct, wl.pool_max, wl.s_num, wl.s_den, wl.split_rms, fic.ENGINE_MFMA)
-    got, _ = gpu_run(ctx, img, p)
-    s_num = list(wl.s_num)
-    pools = []
-    for l, (B, L) in enumerate(wl.levels):
-        ref_pool = oracle.build_pool(img, B, L, wl.pct, wl.pool_max)
-        for f in ("xy", "key", "sum4", "a"):
-            np.testing.assert_array_equal(got[l]["pool"][f], ref_pool[f], err_msg="c3 level %d pool %s" % (l, f))
-        pools.append(ref_pool)
+    pools = [oracle.build_pool(img, B, L, wl.pct, wl.pool_max, threads=WORKERS) for (B, L) in wl.levels]
+    all0 = oracle.level0_ranges(W, H, wl.levels[0][0])
     rng = np.random.default_rng(2024)
-    B0 = wl.levels[0][0]
-    all0 = oracle.level0_ranges(W, H, B0)
+    ranges = all0[np.sort(rng.choice(len(all0), 24, replace=False))]
+    refs = oracle_subtrees(img, pools, wl.levels, ranges, wl.s_num, wl.s_den, wl.split_rms)
+    return wl, img, all0, pools, refs
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+def test_config3_1024_sampled_parity(ctx, c3_reference, engine):
+    """Every engine on the full-size c3 workload, in the launch configuration
+    the benchmark times: both pools in full, the sampled subtrees exactly."""
+    wl, img, all0, pools, refs = c3_reference
+    print("c3 engine", engine, "subtree ranges per level", [len(r) for r, _ in refs], flush=True)
+    p = params(wl.levels, wl.pct, wl.pool_max, wl.s_num, wl.s_den, wl.split_rms, engine)
+    got, _ = gpu_run(ctx, img, p)
+    assert_pools_equal(got, pools, "c3")
     np.testing.assert_array_equal(got[0]["codes"]["xy"], all0)
-    pick = np.sort(rng.choice(len(all0), 24, replace=False))
-    ranges = all0[pick]
-    for l, (B, L) in enumerate(wl.levels):
-        last = l == len(wl.levels) - 1
-        ref = oracle.encode_level(img, pools[l]["xy"], ranges, B, s_num, wl.s_den, wl.split_rms, last,
-                                  workers=WORKERS)
-        pos = {int(v): i for i, v in enumerate(got[l]["codes"]["xy"])}
-        idx = np.array([pos[int(v)] for v in ranges], np.int64)
-        for f in ("split", "domain", "iso", "s_idx", "offset", "err"):
-            np.testing.assert_array_equal(got[l]["codes"][f][idx], ref[f], err_msg="c3 level %d %s" % (l, f))
-        if not last:
-            ranges = oracle.children(ranges, ref["split"], B)
-            if len(ranges) == 0:
-                break
+    assert_subtrees_equal(got, refs, "c3")
 
 
 @pytest.fixture(scope="module")
@@ -224,43 +267,79 @@ def c5_reference():
     img = make_image(seed, W, H, nrect)
     pools = [oracle.build_pool(img, B, L, wl.pct, wl.pool_max, threads=WORKERS) for (B, L) in wl.levels]
     B0 = wl.levels[0][0]
-    f = img.astype(np.int64)
-    ge = np.zeros_like(f)
-    ge[:, :-1] += (f[:, 1:] - f[:, :-1]) ** 2
-    ge[:-1, :] += (f[1:, :] - f[:-1, :]) ** 2
-    energy = ge.reshape(H // B0, B0, W // B0, B0).sum(axis=(1, 3)).ravel()
+    energy = gradient_energy(img, B0)
     all0 = oracle.level0_ranges(W, H, B0)
     ranges = all0[np.sort(np.argsort(-energy, kind="stable")[:12])]
-    refs = []
-    for l, (B, L) in enumerate(wl.levels):
-        last = l == len(wl.levels) - 1
-        ref = oracle.encode_level(img, pools[l]["xy"], ranges, B, list(wl.s_num), wl.s_den, wl.split_rms, last,
-                                  workers=WORKERS)
-        refs.append((ranges, ref))
-        if last:
-            break
-        ranges = oracle.children(ranges, ref["split"], B)
-        if len(ranges) == 0:
-            break
+    refs = oracle_subtrees(img, pools, wl.levels, ranges, wl.s_num, wl.s_den, wl.split_rms)
     return wl, img, all0, pools, refs
 
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("engine", [fic.ENGINE_MFMA, fic.ENGINE_FP32], ids=["mfma", "fp32"])
 def test_config5_4096_sampled_parity(ctx, c5_reference, engine):
+    """c5 in full size: pools in full, sampled subtrees exactly, and (matrix
+    engine) the GPU's 8-iteration decode of its own codes equal to the
+    oracle decoder's on the same leaves, with equal PSNR (Eq 4)."""
     wl, img, all0, pools, refs = c5_reference
     print("c5 engine", engine, "subtree ranges per level", [len(r) for r, _ in refs], flush=True)
     p = params(wl.levels, wl.pct, wl.pool_max, wl.s_num, wl.s_den, wl.split_rms, engine)
-    got, _ = gpu_run(ctx, img, p)
-    for l, ref_pool in enumerate(pools):
-        for f in ("xy", "key", "sum4", "a"):
-            np.testing.assert_array_equal(got[l]["pool"][f], ref_pool[f], err_msg="c5 level %d pool %s" % (l, f))
+    iters = wl.decode_iters if engine == fic.ENGINE_MFMA else None
+    got, dec = gpu_run(ctx, img, p, iters=iters)
+    assert_pools_equal(got, pools, "c5")
     np.testing.assert_array_equal(got[0]["codes"]["xy"], all0)
-    for l, (ranges, ref) in enumerate(refs):
-        pos = {int(v): i for i, v in enumerate(got[l]["codes"]["xy"])}
-        idx = np.array([pos[int(v)] for v in ranges], np.int64)
-        for f in ("split", "domain", "iso", "s_idx", "offset", "err"):
-            np.testing.assert_array_equal(got[l]["codes"][f][idx], ref[f], err_msg="c5 level %d %s" % (l, f))
+    assert_subtrees_equal(got, refs, "c5")
+    if iters:
+        H, W = img.shape
+        ref_dec = oracle.decode(W, H, as_oracle_levels(got), iters)
+        np.testing.assert_array_equal(dec, ref_dec)
+        assert oracle.psnr(img, dec) == oracle.psnr(img, ref_dec)
+        print("c5 decode: %d iterations, PSNR %.3f dB" % (iters, oracle.psnr(img, dec)), flush=True)
+
+
+@pytest.fixture(scope="module")
+def c4_reference():
+    """The c4 batch (64 images of uneven sizes, B 16 -> 8 -> 4, L = 2): every
+    pool of every image in full from the oracle, and per image the codes of 5
+    level-0 ranges with their whole subtrees (3 seeded at random, 2 of the
+    largest gradient energy)."""
+    wl = WORKLOADS["c4_batch64"]
+    images = [make_image(s, w, h, n) for (s, w, h, n) in wl.images]
+    B0 = wl.levels[0][0]
+    out = []
+    for i, img in enumerate(images):
+        H, W = img.shape
+        pools = [oracle.build_pool(img, B, L, wl.pct, wl.pool_max, threads=WORKERS) for (B, L) in wl.levels]
+        all0 = oracle.level0_ranges(W, H, B0)
+        rng = np.random.default_rng(400 + i)
+        top = np.argsort(-gradient_energy(img, B0), kind="stable")[:2]
+        rest = np.setdiff1d(np.arange(len(all0)), top)
+        pick = np.sort(np.concatenate([top, rng.choice(rest, 3, replace=False)]))
+        refs = oracle_subtrees(img, pools, wl.levels, all0[pick], wl.s_num, wl.s_den, wl.split_rms)
+        out.append((all0, pools, refs))
+    return wl, images, out
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+def test_config4_batch64_parity(ctx, c4_reference, engine):
+    """The whole c4 batch in one fic_encode (one launch set per level over
+    the 64 images, per-image prefix tables, shared scratch), image by image
+    against the oracle: every pool in full, the level-0 range lists, and the
+    sampled subtrees exactly."""
+    wl, images, refs = c4_reference
+    p = params(wl.levels, wl.pct, wl.pool_max, wl.s_num, wl.s_den, wl.split_rms, engine)
+    batch = ctx.encode([torch.from_numpy(im).cuda() for im in images], p)
+    torch.cuda.synchronize()
+    deep = 0
+    for i, ((pools, codes), (all0, ref_pools, sub)) in enumerate(zip(batch, refs)):
+        got = fic.levels_numpy(pools, codes, p)
+        tag = "c4 image %d (%dx%d)" % (i, images[i].shape[1], images[i].shape[0])
+        assert_pools_equal(got, ref_pools, tag)
+        np.testing.assert_array_equal(got[0]["codes"]["xy"], all0, err_msg=tag)
+        assert_subtrees_equal(got, sub, tag)
+        deep += len(sub) == len(wl.levels)
+    print("c4 engine", engine, ": subtrees reaching the last level in", deep, "of 64 images", flush=True)
+    assert deep > 0
 
 
 def test_stepwise_entry_points_match_oracle(ctx):
@@ -294,6 +373,8 @@ def test_determinism_and_batch_independence(ctx):
         alone, _ = gpu_run(ctx, im, p)
         again, _ = gpu_run(ctx, im, p)
         together = fic.levels_numpy(pools, codes, p)
+        ref = oracle_run(im, [(16, 2), (8, 2), (4, 2)], (3, 10), 0, K16, 16, (6, 1))
+        assert_levels_equal(together, ref, "batched %dx%d" % (im.shape[1], im.shape[0]))
         for a, b, c in zip(alone, again, together):
             for f in ("split", "domain", "iso", "s_idx", "offset", "err", "xy"):
                 np.testing.assert_array_equal(a["codes"][f], b["codes"][f])
@@ -357,13 +438,18 @@ def test_graph_replay_matches_eager_encodes(ctx):
     eager = fic.Context(0)
     g = fic.Context(0)
     g.set_graphs(4)
-    imgs = [torch.from_numpy(make_image(40 + i, w, h, 8)).cuda() for i, (w, h) in enumerate(shapes)]
+    host = [make_image(40 + i, w, h, 8) for i, (w, h) in enumerate(shapes)]
+    host2 = [make_image(60 + i, w, h, 12) for i, (w, h) in enumerate(shapes)]
+    lv = [(16, 2), (8, 2), (4, 2)]
+    refs = {id(im): oracle_run(im, lv, (3, 10), 0, K16, 16, (6, 1)) for im in host + host2}
+    imgs = [torch.from_numpy(im).cuda() for im in host]
     bufs = g.alloc_encode(shapes, p, imgs[0].device)
     try:
         for rep in range(4):
             if rep == 2:   # new contents at the same addresses
-                for i, (w, h) in enumerate(shapes):
-                    imgs[i].copy_(torch.from_numpy(make_image(60 + i, w, h, 12)).cuda())
+                for i in range(len(shapes)):
+                    imgs[i].copy_(torch.from_numpy(host2[i]).cuda())
+            cur = host if rep < 2 else host2
             g.encode(imgs, p, bufs)
             torch.cuda.synchronize()
             assert g.graph_count() == 1
@@ -371,9 +457,10 @@ def test_graph_replay_matches_eager_encodes(ctx):
             junk = torch.randn(1 << 16, device=imgs[0].device).sum()   # eager work between replays
             torch.cuda.synchronize()
             del junk
-            for (pools, codes), (rp, rc) in zip(bufs, ref):
+            for (pools, codes), (rp, rc), im in zip(bufs, ref, cur):
                 got = fic.levels_numpy(pools, codes, p)
                 want = fic.levels_numpy(rp, rc, p)
+                assert_levels_equal(got, refs[id(im)], "replay %d" % rep)
                 for a, b in zip(got, want):
                     for f in ("xy", "split", "domain", "iso", "s_idx", "offset", "err"):
                         np.testing.assert_array_equal(a["codes"][f], b["codes"][f], err_msg="replay %d %s" % (rep, f))
