@@ -52,7 +52,9 @@ enum {
                              launch would need 2^31 or more workgroups */
     FIC_E_HIP = -3,       /* a HIP runtime call failed (no device, launch error) */
     FIC_E_CAPACITY = -4,  /* a caller buffer is smaller than the worst case */
-    FIC_E_ARCH = -5       /* the device is not gfx950 */
+    FIC_E_ARCH = -5,      /* the device is not gfx950 */
+    FIC_E_LIMIT = -6      /* the input exceeds the fixed scratch of an
+                             allocation-free entry point */
 };
 
 /* Search engines; all give identical codes.
@@ -290,6 +292,25 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
  * pitch width (device). */
 int fic_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes,
                int32_t width, int32_t height, int32_t iterations, uint8_t *out, fic_stream stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fic_decode
+ * with the same arguments, results and kernels, but its second image buffer
+ * is a fixed array in the library's device memory instead of context
+ * scratch, so the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and records no stage timing.
+ * width * height must be <= FIC_DECODE_NOALLOC_MAX_PIXELS (16 MiB of pixels,
+ * e.g. 4096 x 4096), else FIC_E_LIMIT and nothing is enqueued; other
+ * argument errors as fic_decode.  Each GPU holds one such array for the
+ * life of the process (reserved when the library's code is loaded on it,
+ * its address taken by fic_ctx_create on that device), shared by every
+ * context and call on that GPU: calls that overlap on one GPU (two streams,
+ * two threads) race on it and must be serialised by the caller.  Every
+ * scratch pixel a call reads is written by that call first, so nothing
+ * carries over from an earlier call. */
+#define FIC_DECODE_NOALLOC_MAX_PIXELS (1 << 24)
+int fic_decode_noalloc(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes,
+                       int32_t width, int32_t height, int32_t iterations, uint8_t *out, fic_stream stream);
 
 /* ---- contrast diagnostic (Sec. 3.2, Fig 5; Sec. 3.2.1, Fig 6) ---------- */
 

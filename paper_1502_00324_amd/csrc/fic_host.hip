@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "fic_internal.h"
@@ -48,6 +49,36 @@ void drop_graphs(GraphCache *gc) {
     if (!gc) return;
     for (auto &g : gc->e) free_graph(g);
     gc->e.clear();
+}
+
+// ---------------------------------------------------------------- fixed decoder scratch
+// The second image of fic_decode_noalloc's double buffer.  Every GPU the
+// library runs on holds its own copy, at its own address, until the process
+// ends.  On the host the array's name is only a stand-in: host code uses
+// the per-device address that hipGetSymbolAddress returned, never the name.
+static __device__ __align__(256) uint8_t scratch[FIC_DECODE_NOALLOC_MAX_PIXELS];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Takes the array's address on `device` (which must be current) once per
+// device; fic_ctx_create calls it.
+static int scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return FIC_OK;   // the entry point then refuses this device
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return FIC_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return FIC_E_HIP;
+    g_scratch_ptr[device] = ptr;
+    return FIC_OK;
+}
+
+static void *scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 }  // namespace fic
@@ -623,6 +654,38 @@ bool codes_ok(const fic_level_codes *c) {
 }
 
 
+int check_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes,
+                 int32_t width, int32_t height, int32_t iterations, const uint8_t *out) {
+    if (!ctx || !p || !pools || !codes || !out || iterations < 0) return FIC_E_INVALID;
+    const int st = fic_validate_params(p, width, height);
+    if (st != FIC_OK) return st;
+    for (int l = 0; l < p->levels; ++l)
+        if (!pool_ok(&pools[l]) || !codes_ok(&codes[l])) return FIC_E_INVALID;
+    return FIC_OK;
+}
+
+// X0 then `iterations` synchronous updates, alternating between out and
+// `other` (a width x height buffer, pitch width) so that the last lands in
+// out.  X0 covers every pixel (the accepted ranges tile the image), so
+// nothing is read from `other` before this call writes it.
+int run_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes, int width,
+               int iterations, uint8_t *out, uint8_t *other, bool timed, hipStream_t s) {
+    uint8_t *buf0 = (iterations % 2 == 0) ? out : other;
+    uint8_t *buf1 = (iterations % 2 == 0) ? other : out;
+    for (int l = 0; l < p->levels; ++l)
+        FIC_TRY(launch_decode_init(p->block0 >> l, &codes[l], codes[l].capacity, buf0, width, s));
+    for (int it = 0; it < iterations; ++it) {
+        const uint8_t *cur = (it % 2 == 0) ? buf0 : buf1;
+        uint8_t *nxt = (it % 2 == 0) ? buf1 : buf0;
+        if (timed) mark(ctx, FIC_T_DECODE, 1, s);
+        for (int l = 0; l < p->levels; ++l)
+            FIC_TRY(launch_decode_iter(p->block0 >> l, &codes[l], codes[l].capacity, &pools[l],
+                                       make_sset(p->s_num[l], p->s_count[l], p->s_den[l]), cur, nxt, width, s));
+    }
+    if (timed) mark(ctx, -1, 0, s);
+    return FIC_OK;
+}
+
 }  // namespace
 
 namespace fic {
@@ -748,6 +811,7 @@ const char *fic_strerror(int status) {
         case FIC_E_HIP: return "HIP runtime error";
         case FIC_E_CAPACITY: return "caller buffer too small";
         case FIC_E_ARCH: return "device is not gfx950";
+        case FIC_E_LIMIT: return "input larger than the fixed scratch of the allocation-free entry point";
         default: return "unknown status";
     }
 }
@@ -808,6 +872,7 @@ int fic_ctx_create(fic_ctx **out, int device) {
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FIC_E_HIP;
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FIC_E_ARCH;
     if (hipSetDevice(device) != hipSuccess) return FIC_E_HIP;
+    if (scratch_setup(device) != FIC_OK) return FIC_E_HIP;
     fic_ctx *ctx = new fic_ctx;
     memset(ctx, 0, sizeof(*ctx));
     ctx->device = device;
@@ -1114,33 +1179,28 @@ int fic_encode(fic_ctx *ctx, const fic_image *imgs, int32_t n_images, const fic_
 
 int fic_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes, int32_t width,
                int32_t height, int32_t iterations, uint8_t *out, fic_stream stream) {
-    if (!ctx || !p || !pools || !codes || !out || iterations < 0) return FIC_E_INVALID;
-    int st = fic_validate_params(p, width, height);
+    int st = check_decode(ctx, p, pools, codes, width, height, iterations, out);
     if (st != FIC_OK) return st;
-    for (int l = 0; l < p->levels; ++l)
-        if (!pool_ok(&pools[l]) || !codes_ok(&codes[l])) return FIC_E_INVALID;
     st = enter(ctx);
     if (st != FIC_OK) return st;
     size_t b[S_NUM_SLOTS] = {0};
     b[S_DEC0] = (size_t)width * height;
     st = reserve(ctx, b);
     if (st != FIC_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    uint8_t *scratch = (uint8_t *)sp(ctx, S_DEC0);
-    uint8_t *buf0 = (iterations % 2 == 0) ? out : scratch;
-    uint8_t *buf1 = (iterations % 2 == 0) ? scratch : out;
-    for (int l = 0; l < p->levels; ++l)
-        FIC_TRY(launch_decode_init(p->block0 >> l, &codes[l], codes[l].capacity, buf0, width, s));
-    for (int it = 0; it < iterations; ++it) {
-        const uint8_t *cur = (it % 2 == 0) ? buf0 : buf1;
-        uint8_t *nxt = (it % 2 == 0) ? buf1 : buf0;
-        mark(ctx, FIC_T_DECODE, 1, s);
-        for (int l = 0; l < p->levels; ++l)
-            FIC_TRY(launch_decode_iter(p->block0 >> l, &codes[l], codes[l].capacity, &pools[l],
-                                       make_sset(p->s_num[l], p->s_count[l], p->s_den[l]), cur, nxt, width, s));
-    }
-    mark(ctx, -1, 0, s);
-    return FIC_OK;
+    return run_decode(ctx, p, pools, codes, width, iterations, out, (uint8_t *)sp(ctx, S_DEC0), true,
+                      (hipStream_t)stream);
+}
+
+int fic_decode_noalloc(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const fic_level_codes *codes,
+                       int32_t width, int32_t height, int32_t iterations, uint8_t *out, fic_stream stream) {
+    int st = check_decode(ctx, p, pools, codes, width, height, iterations, out);
+    if (st != FIC_OK) return st;
+    if ((int64_t)width * height > FIC_DECODE_NOALLOC_MAX_PIXELS) return FIC_E_LIMIT;
+    st = enter(ctx);
+    if (st != FIC_OK) return st;
+    uint8_t *fixed = (uint8_t *)scratch_of(ctx->device);
+    if (!fixed) return FIC_E_HIP;
+    return run_decode(ctx, p, pools, codes, width, iterations, out, fixed, false, (hipStream_t)stream);
 }
 
 }  // extern "C"

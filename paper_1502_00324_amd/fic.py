@@ -16,7 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfic.so")
 
-FIC_OK, FIC_E_INVALID, FIC_E_NOMEM, FIC_E_HIP, FIC_E_CAPACITY, FIC_E_ARCH = 0, -1, -2, -3, -4, -5
+FIC_OK, FIC_E_INVALID, FIC_E_NOMEM, FIC_E_HIP, FIC_E_CAPACITY, FIC_E_ARCH, FIC_E_LIMIT = 0, -1, -2, -3, -4, -5, -6
+DECODE_NOALLOC_MAX_PIXELS = 1 << 24
 ENGINE_MFMA, ENGINE_FP32, ENGINE_MFMA_I8, ENGINE_MFMA_F16, ENGINE_MFMA_F16_16X16 = 0, 1, 2, 3, 4
 POOL_ENTROPY, POOL_VARIANCE = 0, 1
 MAX_LEVELS, MAX_S = 4, 32
@@ -111,6 +112,8 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(CodesC), vp]
         L.fic_decode.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(PoolC), ctypes.POINTER(CodesC), i32, i32,
                                  i32, vp, vp]
+        L.fic_decode_noalloc.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(PoolC), ctypes.POINTER(CodesC),
+                                         i32, i32, i32, vp, vp]
         L.fic_shape_count.argtypes = [i32, i32]
         L.fic_shape_describe.argtypes = [i32, i32, i32, vp]
         L.fic_ctx_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -126,7 +129,7 @@ EXPORTED = ("fic_ctx_create", "fic_ctx_destroy", "fic_ctx_set_scratch_limit", "f
             "fic_ctx_read_timing", "fic_strerror",
             "fic_validate_params", "fic_query_capacity", "fic_level_engine", "fic_entropy_table",
             "fic_build_domain_pool",
-            "fic_encode_level", "fic_encode", "fic_decode", "fic_pack_capacity", "fic_pack", "fic_unpack_header",
+            "fic_encode_level", "fic_encode", "fic_decode", "fic_decode_noalloc", "fic_pack_capacity", "fic_pack", "fic_unpack_header",
             "fic_unpack", "fic_s_histogram", "fic_shape_count", "fic_shape_describe", "fic_ctx_get_tuning",
             "fic_ctx_set_tuning", "fic_autotune")
 
@@ -513,6 +516,15 @@ class Context:
         cc = (CodesC * p.levels)(*[cd.c() for cd in codes])
         _check(lib().fic_decode(self.h, ctypes.byref(p), pc, cc, width, height, iterations, out.data_ptr(),
                                 _stream()), "fic_decode")
+        return out
+
+    def decode_noalloc(self, p: Params, pools, codes, width: int, height: int, iterations: int, out):
+        """fic_decode through the allocation-free entry point: `out` must be a
+        caller-allocated height x width uint8 device tensor."""
+        pc = (PoolC * p.levels)(*[pl.c() for pl in pools])
+        cc = (CodesC * p.levels)(*[cd.c() for cd in codes])
+        _check(lib().fic_decode_noalloc(self.h, ctypes.byref(p), pc, cc, width, height, iterations,
+                                        out.data_ptr(), _stream()), "fic_decode_noalloc")
         return out
 
 

@@ -229,6 +229,36 @@ def main():
 
     scenario("tuning_forced", forced)
     out["tuning_forced"].update({k: log[k] for k in ("bad_set", "after_bad", "before")})
+    # the allocation-free decoder: launches its kernels, allocates nothing
+    # (timing on, so the ordinary decoder would create events), and refuses
+    # an image above its fixed scratch before launching anything
+    L.mock_allocs.restype = ctypes.c_long
+
+    def decode_noalloc():
+        keep = []
+        p = fic.make_params([(8, 1), (4, 1)])
+        W = H = 64
+        pc, rc = np.zeros(4, np.int64), np.zeros(4, np.int64)
+        L.fic_query_capacity(ctypes.byref(p), W, H, pc.ctypes.data, rc.ctypes.data)
+        pools, codes = (fic.PoolC * 2)(), (fic.CodesC * 2)()
+        for l in range(2):
+            pools[l], codes[l], _ = buffers(keep, (int(pc[l]), int(rc[l])))
+        out = np.zeros((H, W), np.uint8)
+        L.fic_ctx_set_timing(h, 1)
+        a0, k0 = L.mock_allocs(), len(log["launches"])
+        st = [L.fic_decode_noalloc(h, ctypes.byref(p), pools, codes, W, H, 5, out.ctypes.data, None)]
+        a1, k1 = L.mock_allocs(), len(log["launches"])
+        st.append(L.fic_decode_noalloc(h, ctypes.byref(p), pools, codes, 8192, 4096, 5, out.ctypes.data, None))
+        a2, k2 = L.mock_allocs(), len(log["launches"])
+        st.append(L.fic_decode(h, ctypes.byref(p), pools, codes, W, H, 5, out.ctypes.data, None))
+        a3 = L.mock_allocs()
+        L.fic_ctx_set_timing(h, 0)
+        log["noalloc"] = {"allocs": a1 - a0, "launches": k1 - k0, "over_allocs": a2 - a1,
+                          "over_launches": k2 - k1, "decode_allocs": a3 - a2}
+        return st
+
+    scenario("decode_noalloc", decode_noalloc)
+    out["decode_noalloc"]["noalloc"] = log["noalloc"]
     L.fic_ctx_set_scratch_limit(h, 1 << 10)
     scenario("over_limit", lambda: encode_case(L, h, [(1024, 1024)], [(8, 1), (4, 1)], M, reps=1))
     L.fic_ctx_set_scratch_limit(h, 0)

@@ -36,6 +36,22 @@ void __hipRegisterFunction(void **, const void *host_fn, char *device_fn, const 
     (*g_names)[host_fn] = device_fn;
 }
 void __hipUnregisterFatBinary(void **) {}
+// A __device__ variable: the host shadow the runtime registers stands in for
+// the device copy (device memory is host memory here).
+static std::map<const void *, size_t> *g_vars;
+void __hipRegisterVar(void **, void *var, char *, char *, int, size_t size, int, int) {
+    if (!g_vars) g_vars = new std::map<const void *, size_t>();
+    (*g_vars)[var] = size;
+}
+hipError_t hipGetSymbolAddress(void **dev, const void *symbol) {
+    if (!g_vars || !g_vars->count(symbol)) return hipErrorInvalidSymbol;
+    *dev = const_cast<void *>(symbol);
+    return hipSuccess;
+}
+// Calls that allocate memory or runtime objects, counted for the tests of the
+// allocation-free entry point.
+static long g_allocs;
+long mock_allocs() { return g_allocs; }
 hipError_t __hipPushCallConfiguration(dim3 grid, dim3 block, size_t shm, hipStream_t st) {
     g_grid = grid;
     g_block = block;
@@ -63,10 +79,12 @@ hipError_t hipLaunchKernel(const void *f, dim3 grid, dim3 block, void **args, si
 }
 hipError_t hipDeviceSynchronize() { return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t *e) {
+    ++g_allocs;
     *e = (hipEvent_t)malloc(16);
     return hipSuccess;
 }
 hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) {
+    ++g_allocs;
     *e = (hipEvent_t)malloc(16);
     return hipSuccess;
 }
@@ -81,6 +99,7 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) {
 hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 hipError_t hipFree(void *p) {
+    ++g_allocs;
     free(p);
     return hipSuccess;
 }
@@ -96,14 +115,17 @@ hipError_t hipGetDevicePropertiesR0600(hipDeviceProp_tR0600 *p, int) {
 }
 hipError_t hipGetLastError() { return hipSuccess; }
 hipError_t hipHostFree(void *p) {
+    ++g_allocs;
     free(p);
     return hipSuccess;
 }
 hipError_t hipHostMalloc(void **p, size_t n, unsigned) {
+    ++g_allocs;
     *p = malloc(n ? n : 1);
     return *p ? hipSuccess : hipErrorOutOfMemory;
 }
 hipError_t hipMalloc(void **p, size_t n) {
+    ++g_allocs;
     *p = aligned_alloc(256, (n + 255) / 256 * 256 + 256);
     if (*p) memset(*p, 0xA5, n);  // device memory starts as garbage
     return *p ? hipSuccess : hipErrorOutOfMemory;
@@ -123,6 +145,7 @@ hipError_t hipSetDevice(int) { return hipSuccess; }
 long mock_captured() { return g_captured; }
 long mock_replays() { return g_replays; }
 hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
+    ++g_allocs;
     *s = (hipStream_t)malloc(16);
     return hipSuccess;
 }

@@ -36,7 +36,7 @@ def test_entropy_table_matches_oracle(orc):
 
 def test_strerror():
     assert fic.strerror(fic.FIC_OK) == "ok"
-    for st in (fic.FIC_E_INVALID, fic.FIC_E_NOMEM, fic.FIC_E_HIP, fic.FIC_E_CAPACITY, fic.FIC_E_ARCH):
+    for st in (fic.FIC_E_INVALID, fic.FIC_E_NOMEM, fic.FIC_E_HIP, fic.FIC_E_CAPACITY, fic.FIC_E_ARCH, fic.FIC_E_LIMIT):
         assert fic.strerror(st) not in ("ok", "unknown status")
 
 

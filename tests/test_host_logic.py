@@ -161,3 +161,15 @@ def test_forced_tuning_is_used_and_validated(runs):
     assert s["bad_set"] == -1
     after = s["after_bad"]
     assert after[0][4] == 2 and after[0][3] == 1   # the rejected call changed nothing
+
+
+def test_decode_noalloc_allocates_nothing(runs):
+    s = runs["decode_noalloc"]
+    # status: the call, the oversized call (FIC_E_LIMIT), the ordinary decoder
+    assert s["status"] == [0, -6, 0]
+    n = s["noalloc"]
+    # X0 per level, then 5 iterations x 2 levels, and not one allocation
+    assert n["launches"] == 2 + 5 * 2 and n["allocs"] == 0
+    assert n["over_launches"] == 0 and n["over_allocs"] == 0
+    # the ordinary decoder grows its scratch and records timing events
+    assert n["decode_allocs"] > 0
