@@ -394,7 +394,11 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
                             : mfma_geometry(d.B, d.range_cap, (int)pexp, pl.bh.shape);
                 const int nquads = d.geo.nrg * (d.geo.rpw / 4);
                 const int tile = f16 ? kDomTile32 : kDomTile;
-                const int ntiles = (int)cdiv(d.pool_cap, tile);
+                // a search stage may read up to a stage past a chunk's end: the
+                // operands carry that many zero tiles
+                const int ntiles = f16 ? f16_tiles(d.pool_cap) : mfma_tiles(d.pool_cap);
+                // ... and a chunk is addressed with 32-bit offsets
+                if (((long)cdiv(ntiles, d.geo.nchunk) + kF16PadTiles) * d.geo.kt * 1024 >= (1L << 31)) fits = false;
                 const long afr = (long)nquads * (f16 ? 1 : 2) * d.geo.ka;   // 1 KiB fragments
                 blk[K_AFRAG] = cdiv(afr * 64, 256);
                 // int8 planes: one thread writes both planes of a K-step
@@ -402,7 +406,8 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
                 blk[K_SEARCH] = cdiv(d.geo.nwg, 8) * 8;  // image blocks start at multiples of 8
                 d.nslot = d.geo.nslot;
                 d.afrag = (uint4 *)take(S_AFRAG, (size_t)afr * 1024);
-                d.bfrag = (uint4 *)take(S_BFRAG, (size_t)ntiles * d.geo.kt * 1024);
+                // the f16 form at B <= 4 keeps a second, exact copy of the tiles
+                d.bfrag = (uint4 *)take(S_BFRAG, (size_t)ntiles * d.geo.kt * 1024 * (f16 && d.B <= 4 ? 2 : 1));
                 d.dinfo = (float2 *)take(S_DINFO, (size_t)ntiles * tile * sizeof(float2));
             } else {
                 fp32_geometry(d.B, d.range_cap, d.pool_cap, &d.fnchunk, &d.ftpc);
@@ -425,6 +430,7 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
         }
     }
     for (int k = 0; k < K_NUM; ++k) pl.bh.blocks[k] = pl.pre[(size_t)k * (n + 1) + n];
+    if (do_search && eng != E_FP32) off[S_QUEUE] = al(sizeof(int) * queue_ints(n));
     for (int s = 0; s < S_NUM_SLOTS; ++s) pl.slot_bytes[s] = off[s];
     pl.bh.dev.n = n;
     return fits;
@@ -471,6 +477,7 @@ void bind(fic_ctx *ctx, LevelPlan &pl, void *tables = nullptr) {
         }
     }
     char *base = (char *)(tables ? tables : ctx->slot[S_TABLES].ptr) + pl.table_off;
+    pl.bh.dev.queue = pl.slot_bytes[S_QUEUE] ? (int *)ctx->slot[S_QUEUE].ptr : nullptr;
     pl.bh.dev.d = (const ImgLvl *)base;
     pl.bh.dev.pre = (const int *)(base + al(sizeof(ImgLvl) * pl.h.size()));
 }
@@ -540,6 +547,7 @@ int run_search(fic_ctx *ctx, LevelPlan &pl, hipStream_t st) {
     if (b.eng == E_F16) FIC_TRY(launch_f16_prep_b(b, st));
     else if (b.eng == E_I8 || b.eng == E_H16) FIC_TRY(launch_mfma_prep_b(b, st));
     else FIC_TRY(launch_fp32_prep_b(b, st));
+    if (b.eng != E_FP32) FIC_TRY(launch_search_plan_b(b, st));
     mark(ctx, FIC_T_SEARCH, b.B, st);
     if (b.eng == E_F16) FIC_TRY(launch_f16_search_b(b, st));
     else if (b.eng == E_I8 || b.eng == E_H16) FIC_TRY(launch_mfma_search_b(b, st));
@@ -691,6 +699,33 @@ int run_decode(fic_ctx *ctx, const fic_params *p, const fic_pool *pools, const f
 namespace fic {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? FIC_OK : (e == hipErrorOutOfMemory ? FIC_E_NOMEM : FIC_E_HIP); }
+
+int persistent_grid(const void *kernel, int static_blocks) {
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, int>> per_cu;   // resident workgroups per CU, per kernel
+    static int cus[kMaxDevices];
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int resident = 0, ncu = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (auto &e : per_cu)
+            if (e.first == kernel) resident = e.second;
+        if (resident == 0) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kernel, 256, 0) != hipSuccess || resident < 1)
+                resident = 1;
+            per_cu.push_back({kernel, resident});
+        }
+        if (dev >= 0 && dev < kMaxDevices) {
+            if (cus[dev] == 0 && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                cus[dev] = 0;
+            ncu = cus[dev];
+        }
+    }
+    if (ncu < 1) ncu = 256;
+    const long cap = max(8L, (long)resident * ncu / 8 * 8);
+    return (int)min((long)static_blocks, cap);
+}
 
 int enter(fic_ctx *ctx) {
     if (!ctx) return FIC_E_INVALID;

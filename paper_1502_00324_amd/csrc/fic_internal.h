@@ -16,7 +16,14 @@ constexpr int kTableSize = 4097;       // entropy table entries, q = 0..4096
 constexpr int kScanBlock = 1024;       // items per block in stable compaction
 constexpr int kDomTile = 16;           // domains per column tile of the int8 engine
 constexpr int kDomTile32 = 32;         // domains per column tile of the f16 engine
+constexpr int kF16PadTiles = 16;       // zero tiles after the matrix engines' operands (>= tiles per LDS stage)
 constexpr int kFusedSelMax = 131072;   // candidates per image for the one-workgroup selection
+
+// Tiles of the matrix engines' domain operands for a pool capacity, padding
+// included (kF16PadTiles zero tiles: a search stage may read up to a stage
+// past a chunk's end without a bound check).
+__host__ __device__ inline int f16_tiles(int pool_cap) { return (pool_cap + kDomTile32 - 1) / kDomTile32 + kF16PadTiles; }
+__host__ __device__ inline int mfma_tiles(int pool_cap) { return (pool_cap + kDomTile - 1) / kDomTile + kF16PadTiles; }
 
 // ---------------------------------------------------------------- small PODs
 // Contrast set of one level, passed by value to kernels.
@@ -98,7 +105,7 @@ __host__ __device__ inline int iso_inv(int t) { return t == 1 ? 3 : (t == 3 ? 1 
 // Scratch slots owned by a context; each grows on demand.
 enum Slot {
     S_KEYS, S_SEL, S_PBLOCK, S_CBLOCK, S_RINFO, S_AFRAG, S_BFRAG, S_DINFO, S_PARTIAL,
-    S_VF32, S_DF32, S_DEC0, S_TABLES, S_INTEG, S_ITMP, S_PACK, S_NUM_SLOTS
+    S_VF32, S_DF32, S_DEC0, S_TABLES, S_INTEG, S_ITMP, S_PACK, S_QUEUE, S_NUM_SLOTS
 };
 
 struct Buf { void *ptr; size_t bytes; };
@@ -165,29 +172,12 @@ MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, const TileShape &sh);
 MfmaGeom f16_geometry(int B, int range_cap, int pool_cap, const TileShape &sh);    // 32x32 f16 engine
 void split_chunks(MfmaGeom &g, int range_cap, int ntiles, int tile_kib, int dt, bool rows16, int slots);
 
-// Range group, chunk walk and partial-result slot of search workgroup lb.
-__device__ inline void chunk_walk(const MfmaGeom &geo, int lb, int &rg, int &cfirst, int &cstep, int &ncs,
-                                  int &slot) {
-    if (geo.xcd) {  // XCD-aware: workgroup w runs on XCD w % 8
-        const int xcd = lb & 7, k = lb >> 3, grp = k / geo.nrg;
-        rg = k % geo.nrg;
-        cfirst = xcd + 8 * grp * geo.G;
-        cstep = 8;
-        ncs = geo.G;
-        slot = xcd + 8 * grp;
-    } else {
-        rg = lb % geo.nrg;
-        cfirst = slot = lb / geo.nrg;
-        cstep = 1;
-        ncs = 1;
-    }
-}
-
 // ---------------------------------------------------------------- batched levels
-// One quadtree level of a batch of images runs as ~25 launches whatever the
-// number of images: every kernel takes the device table of per-image level
-// state below, and a launch of kind k gives image i the workgroups
-// [pre[k][i], pre[k][i+1]) (found by binary search on the prefix table).
+// One quadtree level of a batch of images runs as one launch set whatever
+// the number of images: every kernel takes the device table of per-image
+// level state below, and a launch of kind k gives image i the workgroups
+// [pre[k][i], pre[k][i+1]) (found by binary search on the prefix table); the
+// matrix searches are persistent and take their work from device queues.
 // Search engine of a level: every image of a level uses the same one.
 enum Engine { E_FP32 = 0, E_I8 = 1, E_F16 = 2, E_H16 = 3 };
 
@@ -276,7 +266,46 @@ struct BatchDev {
     const ImgLvl *d;     // device table, n entries
     const int *pre;      // device prefixes, K_NUM x (n + 1)
     int n;
+    // work queue of the persistent search: kQueueHeads counters (one per
+    // XCD), then per XCD the prefix over images of their item counts, n + 1
+    // entries each (k_search_plan fills it)
+    int *queue;
 };
+constexpr int kQueueHeads = 16;
+inline size_t queue_ints(int n) { return kQueueHeads + 8 * (size_t)(n + 1); }
+
+// Items of one image in XCD x's queue of a persistent search: the live range
+// groups (those holding a range of the search list) times the partial-result
+// slots, split over the XCDs as the static chunk walk splits them.
+__device__ inline int search_items(const ImgLvl &d, int x) {
+    const MfmaGeom &g = d.geo;
+    const int R = min(*d.ns, d.range_cap);
+    const int nrg = (R + g.rpw - 1) / g.rpw;
+    if (g.xcd) return nrg * (g.nslot / 8);
+    const long N = (long)nrg * g.nslot;
+    return N > x ? (int)((N - x + 7) / 8) : 0;
+}
+
+// Range group, chunk walk and partial-result slot of item k of XCD x's queue
+// within image d (R ranges in its search list).
+__device__ inline void item_walk(const MfmaGeom &g, int R, int x, int k, int &rg, int &cfirst, int &cstep, int &ncs,
+                                 int &slot) {
+    const int nrg = (R + g.rpw - 1) / g.rpw;
+    if (g.xcd) {   // XCD x owns chunks x, x + 8, ...: groups of G of them
+        const int grp = k / nrg;
+        rg = k - grp * nrg;
+        cfirst = x + 8 * grp * g.G;
+        cstep = 8;
+        ncs = g.G;
+        slot = x + 8 * grp;
+    } else {       // one chunk per item, items dealt round-robin over the queues
+        const int j = 8 * k + x;
+        rg = j % nrg;
+        cfirst = slot = j / nrg;
+        cstep = 1;
+        ncs = 1;
+    }
+}
 
 struct ImgLvl;
 __device__ inline IntegGeom integ_geom(int W, int H) {
@@ -312,12 +341,18 @@ struct BatchHost {
     int is_last;
 };
 
+// Grid of a persistent search launch: the kernel's resident workgroups over
+// the whole GPU (a multiple of 8, so workgroup w runs on XCD w % 8), at most
+// the static count.
+int persistent_grid(const void *kernel, int static_blocks);
+
 // pool
 hipError_t launch_pool_b(const BatchHost &b, const int64_t *table, hipStream_t st);
 // levels
 hipError_t launch_level0_b(const BatchHost &b, hipStream_t st);
 hipError_t launch_range_info_b(const BatchHost &b, hipStream_t st);
 hipError_t launch_finalize_b(const BatchHost &b, hipStream_t st);
+hipError_t launch_search_plan_b(const BatchHost &b, hipStream_t st);
 hipError_t launch_children_b(const BatchHost &b, hipStream_t st);
 // MFMA engine
 hipError_t launch_integ_b(const BatchHost &b, hipStream_t st);

@@ -89,6 +89,28 @@ hipError_t launch_range_info_b(const BatchHost &b, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- search queue
+// The work items of a level's persistent search, from the search lists the
+// range moments just built: per XCD queue x, the prefix over images of their
+// item counts; every queue head back to 0.
+__global__ __launch_bounds__(64) void k_search_plan(BatchDev b) {
+    const int x = threadIdx.x;
+    if (x >= 8) return;
+    int *pre = b.queue + kQueueHeads + x * (b.n + 1);
+    int acc = 0;
+    pre[0] = 0;
+    for (int i = 0; i < b.n; ++i) {
+        acc += search_items(b.d[i], x);
+        pre[i + 1] = acc;
+    }
+    b.queue[x] = 0;
+}
+
+hipError_t launch_search_plan_b(const BatchHost &b, hipStream_t st) {
+    if (b.blocks[K_SEARCH] > 0) k_search_plan<<<1, 64, 0, st>>>(b.dev);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- finalize
 __device__ inline bool lex_less(int64_t va, int pa, int64_t vb, int pb) { return va < vb || (va == vb && pa < pb); }
 

@@ -49,6 +49,9 @@ bool f16_supported(int B) { return B == 2 || B == 4 || B == 8 || B == 16; }
 
 // Mean-centred operands (the header describes them): every size up to 8.
 __host__ __device__ inline bool f16_centred(int B) { return B <= 8; }
+// Normalised domain operands with the threshold in the accumulator input
+// (one K-step: B = 2 and 4).
+__host__ __device__ inline bool f16_normalised(int B) { return B <= 4; }
 
 // Range quads per wave (RQ), domain tiles per LDS stage (DT) and the
 // occupancy the register allocation aims at (waves per SIMD); the first entry
@@ -56,8 +59,8 @@ __host__ __device__ inline bool f16_centred(int B) { return B <= 8; }
 // compiled one.
 struct F16Shape { int B, rq, dt, wpe; };
 static const F16Shape kF16Shapes[] = {
-    {2, 1, 8, 4},
-    {4, 1, 8, 4}, {4, 2, 8, 2}, {4, 1, 16, 3}, {4, 2, 4, 3}, {4, 1, 8, 3},
+    {2, 1, 8, 3},
+    {4, 1, 8, 3}, {4, 1, 16, 3}, {4, 2, 8, 2}, {4, 1, 4, 3},
     {8, 2, 4, 2}, {8, 1, 4, 3}, {8, 1, 8, 2}, {8, 2, 2, 2},
     {16, 1, 1, 3}, {16, 1, 2, 2},
 };
@@ -100,13 +103,13 @@ MfmaGeom f16_geometry(int B, int range_cap, int pool_cap, const TileShape &sh) {
 }
 
 // ---------------------------------------------------------------- operands
-__global__ __launch_bounds__(256) void k_f16_afrag(BatchDev b) {
+__device__ __forceinline__ void k_f16_afrag(const BatchDev &b, const int bid) {
     const int *pre = b.pre + K_AFRAG * (b.n + 1);
-    const int im = find_img(pre, b.n, blockIdx.x);
+    const int im = find_img(pre, b.n, bid);
     const ImgLvl &d = b.d[im];
     const int B = d.B, KS = d.geo.ka;
     const int nquads = d.geo.nrg * (d.geo.rpw / 4);
-    const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    const int64_t slot = (int64_t)(bid - pre[im]) * 256 + threadIdx.x;
     if (slot >= (int64_t)nquads * KS * 64) return;
     const int lane = (int)(slot & 63);
     const int rest = (int)(slot >> 6);
@@ -141,13 +144,18 @@ __global__ __launch_bounds__(256) void k_f16_afrag(BatchDev b) {
     ((h8 *)d.afrag)[slot] = w;
 }
 
-__global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
+// Domain operands: f16_tiles(pool_cap) tiles, the last kF16PadTiles of them
+// zero, so that a stage may read past a chunk's end without a bound check.
+// Per domain, structure of arrays in dinfo: Sd4 for all the tiles' domains,
+// then sqrt(A) rounded down; NaN past the pool (no pair on them passes the
+// test).
+__device__ __forceinline__ void k_f16_bfrag(const BatchDev &b, const int bid) {
     const int *pre = b.pre + K_BFRAG * (b.n + 1);
-    const int im = find_img(pre, b.n, blockIdx.x);
+    const int im = find_img(pre, b.n, bid);
     const ImgLvl &d = b.d[im];
     const int B = d.B, KS = d.geo.kt;
-    const int ntiles = (d.pool_cap + kDomTile32 - 1) / kDomTile32;
-    const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;   // can pass 2^31
+    const int ntiles = f16_tiles(d.pool_cap);
+    const int64_t slot = (int64_t)(bid - pre[im]) * 256 + threadIdx.x;   // can pass 2^31
     if (slot >= (int64_t)ntiles * KS * 64) return;
     const int lane = (int)(slot & 63);
     const int rest = (int)(slot >> 6);
@@ -175,59 +183,107 @@ __global__ __launch_bounds__(256) void k_f16_bfrag(BatchDev b) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) w[e] = (_Float16)0;
     }
+    if (f16_normalised(B)) {
+        // the exact tile goes to the second array (the confirm reads it); the
+        // searched one holds 2^16 (D4 - Sd4/n) / sqrt(A): 0 when A = 0, NaN
+        // past the pool (a NaN column fails every test)
+        ((h8 *)d.bfrag)[(size_t)ntiles * KS * 64 + slot] = w;
+        h8 z;
+        if (valid) {
+            const int n = B * B;
+            const float mu = (float)d.psum4[p] / (float)n;   // exact: Sd4 < 2^24, n a power of 2
+            const int64_t A = d.pa[p];
+            const float inv = A > 0 ? 65536.0f / sqrtf((float)A) : 0.0f;
+            const uint32_t v = d.pxy[p];
+            const int x0 = v & 0xffff, y0 = v >> 16, pitch = d.pitch;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 16 * s + 8 * kb + e;
+                if (k >= n) {
+                    z[e] = (_Float16)0;
+                    continue;
+                }
+                const int cy = k / B, cx = k - cy * B;
+                const uint8_t *q = d.pix + (size_t)(y0 + 2 * cy) * pitch + x0 + 2 * cx;
+                z[e] = (_Float16)(((float)(q[0] + q[1] + q[pitch] + q[pitch + 1]) - mu) * inv);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) z[e] = (_Float16)__builtin_nanf("");
+        }
+        w = z;
+    }
     ((h8 *)d.bfrag)[slot] = w;
-    if (s == 0 && kb == 0)
-        d.dinfo[p] = valid ? make_float2((float)d.psum4[p], sqrt_down((double)d.pa[p]))
-                           : make_float2(__builtin_nanf(""), __builtin_nanf(""));  // never passes
+    if (s == 0 && kb == 0) {
+        float *dsd = (float *)d.dinfo, *dsa = dsd + (size_t)ntiles * kDomTile32;
+        dsd[p] = valid ? (float)d.psum4[p] : __builtin_nanf("");
+        dsa[p] = valid ? sqrt_down((double)d.pa[p]) : __builtin_nanf("");
+    }
 }
 
 // ---------------------------------------------------------------- search
 // A workgroup of 4 waves owns 16 RQ ranges (each wave RQ quads) and the
-// domain tiles of its chunks.  Domain fragments go straight from global
-// memory into LDS in stages of DT tiles, double-buffered (the loads of stage
-// s+1 are issued before the MFMAs of stage s); the per-domain moments pass
-// through registers.  The MFMAs of tile t+1 are issued before the prune test
-// of tile t.
+// domain tiles of its chunks.  Domain fragments and the per-domain sqrt(A)
+// (Sd4 as well without centring) go straight from global memory into LDS in
+// stages of DT tiles, double-buffered (the loads of stage s+1 are issued
+// before the MFMAs of stage s), through buffer resources based at the
+// chunk's first tile: a stage's loads differ only by a scalar offset, so
+// they take no vector instructions.  A chunk's last stage may read up to
+// DT - 1 tiles past its end: the next chunk's domains (evaluated twice,
+// harmless: the partials merge by (val, domain)) or the zero padding tiles,
+// whose NaN sqrt(A) never passes.  The MFMAs of tile t+1 are issued before
+// the prune test of tile t.
 template <int KS, int RQ, int DT, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_f16_search(BatchDev bt, SSet ss) {
     constexpr bool CEN = KS <= 4;                // mean-centred operands (B <= 8)
+    constexpr bool NORM = KS == 1;               // normalised domains, threshold in the accumulator (B <= 4)
     constexpr int STAGE = DT * KS * 64;          // uint4 per stage
+    constexpr int ND = NORM ? 1 : DT * kDomTile32;   // per-domain values staged per stage (none when NORM)
     // share range bests across workgroups only when a stage is long enough
     // (>= 4 tiles) to hide the coherent load of the shared values
     constexpr bool SHARE = DT >= 4;
     constexpr int PER_T = STAGE / 256;
+    constexpr int PER_D = (ND + 255) / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
-    // the two stage buffers of fragments, separate arrays: a stage's
-    // direct-to-LDS loads into one are then known not to touch the other
+    static_assert(DT <= kF16PadTiles, "a stage reads at most DT - 1 tiles past a chunk");
+    // the two stage buffers, separate arrays: a stage's direct-to-LDS loads
+    // into one are then known not to touch the other
     __shared__ uint4 bl0[STAGE];
     __shared__ uint4 bl1[STAGE];
-    __shared__ float2 dl[2][DT * kDomTile32];     // (Sd4, sqrt A) per domain
-    __shared__ int64_t dla[2][DT * kDomTile32];   // exact A per domain
+    __shared__ float sa0[ND], sa1[ND];                          // sqrt(A) rounded down
+    __shared__ float sd0[CEN ? 1 : ND], sd1[CEN ? 1 : ND];      // Sd4 (the uncentred test only)
     __shared__ SLds sl;
+    __shared__ int s_item;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
     const SConst sc = make_sconst(ss);
-    const int *bpre = bt.pre + K_SEARCH * (bt.n + 1);
-    const int im = find_img(bpre, bt.n, blockIdx.x);
+    // Persistent: the workgroup takes items (image, range group, chunk walk)
+    // from its XCD's queue until it is empty.  Workgroup w runs on XCD w % 8,
+    // and the items of XCD x walk the chunks x, x + 8, ..., so the concurrent
+    // workgroups of one XCD read the same chunks from its L2.
+    const int xcd = blockIdx.x & 7;
+    const int *qpre = bt.queue + kQueueHeads + xcd * (bt.n + 1);
+    const int total = qpre[bt.n];
+  auto run_item = [&](const int im, const int k) {
     const ImgLvl &dsc = bt.d[im];
     const MfmaGeom geo = dsc.geo;
-    const int lb = blockIdx.x - bpre[im];   // image blocks start at multiples of 8
-    if (lb >= geo.nwg) return;
     const gptr<h8> afrag = as_global((const h8 *)dsc.afrag);
-    const gptr<uint4> bfrag = as_global(dsc.bfrag);
-    const gptr<float2> dinfo = as_global(dsc.dinfo);
     RInfo *__restrict__ ri = dsc.ri;
     const gptr<int64_t> pa = as_global(dsc.pa);
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
+    const int nalloc = f16_tiles(pool_cap);
+    const float *dsd = (const float *)dsc.dinfo, *dsa = dsd + (size_t)nalloc * kDomTile32;
+    const gptr<float> dsd_g = as_global(dsd), dsa_g = as_global(dsa);
+    // the exact copy of the tiles (normalised form), after the searched ones
+    const gptr<h8> bfx = as_global((const h8 *)(dsc.bfrag + (size_t)nalloc * KS * 64));
     const float tfac = tn_factor(n);
     const float cmargin = (float)(n / 2 + 4);   // centred test: n/4 centring + n/4 + 4 float margin
-    int rg, cfirst, cstep, ncs, slot;
-    chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
     // R: the length of the search list (constant ranges are coded already)
     const int R = min(*dsc.ns, range_cap), P = min(*dsc.pcount, pool_cap);
+    int rg, cfirst, cstep, ncs, slot;
+    item_walk(geo, R, xcd, k, rg, cfirst, cstep, ncs, slot);
     const gptr<int32_t> sidx = as_global(dsc.sidx);
-    if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
     const int ntiles = (P + kDomTile32 - 1) / kDomTile32;
     const int q0 = (rg * 4 + wave) * RQ;
     const bool wave_on = q0 * 4 < R;
@@ -236,8 +292,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // per lane: two ranges per quad, 4 q + 2 hh + u for u = 0, 1
     h8 A[RQ][KS];
     float tn[RQ][2], bn[RQ][2], an[RQ][2];
+    // normalised form: the accumulator input of every tile, -(threshold) of
+    // the lane's two ranges (values 0..7 and 8..15), and its error margin
+    f16x cth[NORM ? RQ : 1];
+    float marg[RQ][2];
     int64_t best[RQ][2], cr[RQ][2], tb[RQ][2];  // tb: the best value tn reflects
     int bp[RQ][2], bk[RQ][2], rr[RQ][2], sr[RQ][2];
+    // The normalised test: acc' = sum (r - m_r) 2^16 (D4 - Sd4/n)/sqrt(A) + c is
+    // 2^16 Bx/(n sqrt A) + c up to the range's margin, and a pair can reach
+    // the best only if Bx/(n sqrt A) > tn, so with c = margin - 2^16 tn (1 -
+    // 2^-20) (the 2^-20 covers the float roundings of c and of the sum) it
+    // passes only if acc' > 0.  No best yet: c = 1e30, every pair passes; a
+    // row without a range, or a range whose walk found val 0: -inf, none.
+    auto build_cth = [&](int qi) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const float t = tn[qi][u];
+            const float c = (rr[qi][u] < 0 || __builtin_isnan(t)) ? -__builtin_inff()
+                          : t < -1e29f ? 1e30f
+                                       : marg[qi][u] - 65536.0f * t * (1.0f - 1.0f / 1048576.0f);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) cth[NORM ? qi : 0][8 * u + e] = c;
+        }
+    };
 #pragma unroll
     for (int qi = 0; qi < RQ; ++qi) {
 #pragma unroll
@@ -254,60 +331,58 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             cr[qi][u] = x.cr;
             tn[qi][u] = r >= 0 ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
             tb[qi][u] = INT64_MAX;
+            // start from the best other walks of this range have shared (a
+            // stale copy only loosens the test)
+            if (r >= 0 && x.gbest < INT64_MAX) {
+                tb[qi][u] = x.gbest;
+                tn[qi][u] = tn_shared(x.gbest, x.cr, sc, tfac);
+            }
             best[qi][u] = INT64_MAX;
             bp[qi][u] = INT32_MAX;
             bk[qi][u] = 0;
+            // |sum a_i (w~_i - w_i)| <= 2^-10 |a| |w| with a = r - m_r and |w| = 2^16/sqrt(n):
+            // |a|^2 = Cr/n + n (mean - m_r)^2 <= Cr/n + n/4 (rounded up here)
+            marg[qi][u] = NORM ? 64.0f * sqrtf((float)x.cr / (float)n + 0.25f * (float)n + 1.0f) * (1.0f + 1.0f / 1024.0f) /
+                                     sqrtf((float)n)
+                               : 0.f;
         }
+        if constexpr (NORM) build_cth(qi);
     }
     // drain the one-time loads: vmcnt is in-order, so a wait for them inside
     // the tile loop would also wait for the stage prefetch
     __builtin_amdgcn_s_waitcnt(0);
 
-    // per-domain moments of a stage: DT * kDomTile32 entries over the 256 threads
-    constexpr int PER_D = (DT * kDomTile32 + 255) / 256;
-    float2 dpre[PER_D];
-    int64_t apre[PER_D];
-    int t0 = 0, t1 = 0;
-    // Fragments go straight from global memory to LDS (one 16-byte load per
-    // lane into 1 KiB per wave, no registers); indexes are clamped to the
-    // chunk's last tile, so the tiles past its end hold copies, harmless
-    // under their NaN moments.
-    auto gload = [&](uint4 *dst, int stg) {
-        const int tbase = t0 + stg * DT;
-        const size_t fend = (size_t)t1 * KS * 64 - 1;
+    typedef __attribute__((address_space(3))) void *lds_t;
+    // the wave index as a scalar: the LDS destination of a direct load is a
+    // per-wave base in M0
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    int t0 = 0;
+    __amdgpu_buffer_rsrc_t rfrag, rsa, rsd;
+    // one stage of the current chunk into the LDS buffers given: fragments,
+    // then per-domain values; wave w fills its own 64-slot blocks
+    auto gload = [&](uint4 *fdst, float *adst, float *ddst, int stg) {
 #pragma unroll
-        for (int i = 0; i < PER_T; ++i) {
-            const size_t e = min((size_t)tbase * KS * 64 + tid + 256 * i, fend);
-            __builtin_amdgcn_global_load_lds((gptr<void>)(bfrag + e),
-                                             (__attribute__((address_space(3))) void *)(dst + 64 * wave + 256 * i),
-                                             16, 0, 0);
-        }
-        // tiles past the chunk end get NaN moments: no pair on them passes
+        for (int i = 0; i < PER_T; ++i)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rfrag, (lds_t)(fdst + 64 * wv + 256 * i), 16,
+                                                     (unsigned)(tid + 256 * i) * 16u, (unsigned)stg * STAGE * 16u, 0,
+                                                     0);
 #pragma unroll
-        for (int i = 0; i < PER_D; ++i) {
-            const int e = tid + 256 * i;
-            if (e < DT * kDomTile32) {
-                const int p = tbase * kDomTile32 + e;
-                dpre[i] = tbase + e / kDomTile32 < t1 ? ldg(dinfo, p) : make_float2(__builtin_nanf(""), __builtin_nanf(""));
-                apre[i] = p < P ? pa[p] : 0;
+        for (int i = 0; i < (NORM ? 0 : PER_D); ++i) {
+            if (ND % 256 == 0 || tid + 256 * i < ND) {
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsa, (lds_t)(adst + 64 * wv + 256 * i), 4,
+                                                         (unsigned)(tid + 256 * i) * 4u, (unsigned)stg * ND * 4u, 0,
+                                                         0);
+                if constexpr (!CEN)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsd, (lds_t)(ddst + 64 * wv + 256 * i), 4,
+                                                             (unsigned)(tid + 256 * i) * 4u, (unsigned)stg * ND * 4u,
+                                                             0, 0);
             }
         }
     };
-    auto swrite = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < PER_D; ++i) {
-            const int e = tid + 256 * i;
-            if (e < DT * kDomTile32) {
-                dl[buf][e] = dpre[i];
-                dla[buf][e] = apre[i];
-            }
-        }
-    };
-    // the tile's fragments are read up front (in groups of up to 8 K-steps),
-    // so one LDS wait covers a group rather than every MFMA
     // With up to 4 K-steps a tile's fragments are read into registers one
     // tile ahead of its MFMAs (two sets alternate), so the LDS latency is
-    // covered by the previous tile; longer tiles read them in groups of 8.
+    // covered by the previous tile; longer tiles read them in groups of 8, so
+    // one LDS wait covers a group rather than every MFMA.
     constexpr bool PREF = KS <= 4;
     constexpr int KG = PREF ? KS : 8;
     auto read_tile = [&](h8 (&bf)[KG], const uint4 *Bs, int dt, int s0) {
@@ -319,7 +394,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     };
     auto mfma_tile = [&](f16x (&acc)[RQ], const uint4 *Bs, int dt, h8 (&bq)[KG]) {
 #pragma unroll
-        for (int qi = 0; qi < RQ; ++qi) acc[qi] = f16x{0.f};
+        for (int qi = 0; qi < RQ; ++qi) acc[qi] = NORM ? cth[NORM ? qi : 0] : f16x{0.f};
 #pragma unroll
         for (int s0 = 0; s0 < KS; s0 += KG) {
             if constexpr (!PREF) read_tile(bq, Bs, dt, s0);
@@ -336,12 +411,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         // plan, the pool size only known here)
         const int tpc = (ntiles + geo.nchunk - 1) / geo.nchunk;
         t0 = chunk * tpc;
-        t1 = min(ntiles, t0 + tpc);
+        const int t1 = min(ntiles, t0 + tpc);
         const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
-        if (nstage > 0) {
-            gload(bl0, 0);
-            swrite(0);
-        }
+        if (nstage == 0) continue;   // uniform over the workgroup
+        // resources over [t0, nalloc): a chunk's offsets stay below 2^31 (the plan checks)
+        const int left = uniform((int)min((long)(nalloc - t0) * kDomTile32 * 4, (long)INT32_MAX));
+        rfrag = buffer_rsrc(dsc.bfrag + (size_t)t0 * KS * 64, uniform((int)min((long)(nalloc - t0) * KS * 1024,
+                                                                               (long)INT32_MAX)));
+        rsa = buffer_rsrc(dsa + (size_t)t0 * kDomTile32, left);
+        rsd = buffer_rsrc(dsd + (size_t)t0 * kDomTile32, left);
+        gload(bl0, sa0, sd0, 0);
         // the direct-to-LDS loads count on vmcnt only: every wave drains its
         // own before the barrier that publishes the stage
         __builtin_amdgcn_s_waitcnt(0);
@@ -350,7 +429,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         auto stage = [&](auto bc, int stg) {
             constexpr int buf = decltype(bc)::value;
             uint4 *const Bs = buf ? bl1 : bl0;
-            if (stg + 1 < nstage) gload(buf ? bl0 : bl1, stg + 1);
+            const float *const As = buf ? sa1 : sa0;
+            const float *const Ds = buf ? sd1 : sd0;
+            if (stg + 1 < nstage) {
+                if constexpr (buf) gload(bl0, sa0, sd0, stg + 1);
+                else gload(bl1, sa1, sd1, stg + 1);
+            }
             // the range bests of other workgroups: issued after the stage
             // prefetch (so its wait does not include them), applied at the end
             int64_t gl[RQ][2];
@@ -363,45 +447,88 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 const int tbase = t0 + stg * DT;
                 f16x acc[2][RQ];
                 h8 bq[2][KG];
+                // the per-domain values are read one tile ahead of their test,
+                // so the test never waits for LDS
+                float sq_n = NORM ? 0.f : As[lane & 31], sd_n = CEN ? 0.f : Ds[lane & 31];
                 if constexpr (PREF) read_tile(bq[0], Bs, 0, 0);
                 mfma_tile(acc[0], Bs, 0, bq[0]);
                 if (PREF && DT > 1) read_tile(bq[1], Bs, 1, 0);
 #pragma unroll
                 for (int dt = 0; dt < DT; ++dt) {
                     const int cur = dt & 1;
+                    const int col = dt * kDomTile32 + (lane & 31);
+                    const float sqa = sq_n, sd4f = sd_n;
                     if (dt + 1 < DT) {
+                        if constexpr (!NORM) sq_n = As[col + kDomTile32];
+                        if constexpr (!CEN) sd_n = Ds[col + kDomTile32];
                         mfma_tile(acc[cur ^ 1], Bs, dt + 1, bq[(dt + 1) & 1]);
                         // the set of tile dt is free once tile dt's MFMAs were issued
                         if (PREF && dt + 2 < DT) read_tile(bq[dt & 1], Bs, dt + 2, 0);
                     }
-                    const float2 di = dl[buf][dt * kDomTile32 + (lane & 31)];
                     bool pass[RQ][2];
                     float mx[RQ][2];
                     bool any = false;
+                    if constexpr (NORM) {
+                        // the threshold is in the accumulators: the largest of the
+                        // lane's 16 values (both ranges, 8 isometries) against 0;
+                        // false on NaN (a column past the pool)
 #pragma unroll
-                    for (int qi = 0; qi < RQ; ++qi)
-#pragma unroll
-                        for (int u = 0; u < 2; ++u) {
+                        for (int qi = 0; qi < RQ; ++qi) {
                             const f16x &a = acc[cur][qi];
-                            const int o = 8 * u;
-                            mx[qi][u] = max8f(a[o], a[o + 1], a[o + 2], a[o + 3], a[o + 4], a[o + 5], a[o + 6], a[o + 7]);
-                            const float rhs = CEN ? fmaf(tn[qi][u], di.y, -cmargin)
-                                                  : fmaf(tn[qi][u], di.y, fmaf(-bn[qi][u], di.x, -an[qi][u]));
-                            // false on NaN: rows past the ranges, domains past the
-                            // pool or the chunk, and ranges already at val 0
-                            pass[qi][u] = mx[qi][u] > rhs;
-                            any |= pass[qi][u];
+                            const float m = FIC_MAX3(FIC_MAX3(max8f(a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7]),
+                                                              a[8], a[9]),
+                                                     FIC_MAX3(a[10], a[11], a[12]), FIC_MAX3(a[13], a[14], a[15]));
+                            pass[qi][0] = pass[qi][1] = m > 0.f;
+                            any |= pass[qi][0];
                         }
+                    } else {
+#pragma unroll
+                        for (int qi = 0; qi < RQ; ++qi)
+#pragma unroll
+                            for (int u = 0; u < 2; ++u) {
+                                const f16x &a = acc[cur][qi];
+                                const int o = 8 * u;
+                                mx[qi][u] = max8f(a[o], a[o + 1], a[o + 2], a[o + 3], a[o + 4], a[o + 5], a[o + 6], a[o + 7]);
+                                const float rhs = CEN ? fmaf(tn[qi][u], sqa, -cmargin)
+                                                      : fmaf(tn[qi][u], sqa, fmaf(-bn[qi][u], sd4f, -an[qi][u]));
+                                // false on NaN: rows past the ranges, domains past the
+                                // pool, and ranges already at val 0
+                                pass[qi][u] = mx[qi][u] > rhs;
+                                any |= pass[qi][u];
+                            }
+                    }
                     if (__builtin_amdgcn_ballot_w64(any)) {  // rare: exact evaluation, then share the best
-                        const int col = dt * kDomTile32 + (lane & 31);
                         const int p = tbase * kDomTile32 + col;
-                        const int64_t sd4 = (int64_t)di.x, A = dla[buf][col];  // Sd4 < 2^24: exact in float
+                        // a passing pair has a finite sqrt(A): p is a pool domain
+                        const int64_t sd4 = (int64_t)(CEN ? dsd_g[p] : sd4f);   // Sd4 < 2^24: exact in float
+                        if constexpr (NORM) {
+                            // the exact cross terms of the tile (every lane: the MFMA is
+                            // wave-wide), from the exact copy of its fragment
+                            const h8 bx = bfx[(size_t)(tbase + dt) * 64 + lane];
+#pragma unroll
+                            for (int qi = 0; qi < RQ; ++qi) {
+                                const f16x ex = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[qi][0], bx, f16x{0.f}, 0, 0, 0);
+#pragma unroll
+                                for (int u = 0; u < 2; ++u) {
+                                    const int o = 8 * u;
+                                    mx[qi][u] = max8f(ex[o], ex[o + 1], ex[o + 2], ex[o + 3], ex[o + 4], ex[o + 5],
+                                                      ex[o + 6], ex[o + 7]);
+                                    pass[qi][u] = pass[qi][u] && rr[qi][u] >= 0;
+                                }
+                            }
+                        }
 #pragma unroll
                         for (int qi = 0; qi < RQ; ++qi)
 #pragma unroll
                             for (int u = 0; u < 2; ++u) {
                                 bool imp = false;
+                                if (NORM && pass[qi][u]) {
+                                    // the centred test on the exact cross term first: the
+                                    // normalised one passes a few more pairs
+                                    pass[qi][u] = mx[qi][u] > fmaf(tn[qi][u], dsa_g[p], -cmargin);
+                                }
                                 if (pass[qi][u]) {
+                                    const int64_t A = pa[p];
                                     if (CEN) {
                                         const int64_t er = (int64_t)sr[qi][u] - (int64_t)n * round_mean(sr[qi][u], n);
                                         const int64_t ed = sd4 - (int64_t)n * round_mean(sd4, n);
@@ -412,6 +539,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                                            best[qi][u], bp[qi][u], bk[qi][u]);
                                     }
                                 }
+                                // only a lane best that tightens the shared one is worth sharing
+                                // (or a walk's own 0, which ends the walk for the range)
+                                imp = imp && (best[qi][u] < tb[qi][u] || best[qi][u] == 0);
                                 if (__builtin_amdgcn_ballot_w64(imp)) {
                                     // the 32 lanes holding this range share their best: a
                                     // pair is only rejected when it cannot even tie it
@@ -421,20 +551,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                         tn[qi][u] = tn_from(gb, cr[qi][u], sc, tfac);
                                         if (SHARE && (lane & 31) == 0) gbest_push(&ri[rr[qi][u]].gbest, gb);
                                     }
+                                    if constexpr (NORM) build_cth(qi);   // uniform: inside a ballot
                                 }
                             }
                     }
                 }
             }
-            if (stg + 1 < nstage) swrite(buf ^ 1);
 #pragma unroll
-            for (int qi = 0; qi < RQ; ++qi)
+            for (int qi = 0; qi < RQ; ++qi) {
+                bool changed = false;
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
                     if (gl[qi][u] < tb[qi][u]) {
                         tb[qi][u] = gl[qi][u];
                         tn[qi][u] = tn_shared(gl[qi][u], cr[qi][u], sc, tfac);
+                        changed = true;
                     }
+                if (NORM && __builtin_amdgcn_ballot_w64(changed)) build_cth(qi);
+            }
             __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the next stage
             __syncthreads();
         };
@@ -450,28 +584,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             int64_t v = best[qi][u];
-            int p = bp[qi][u], k = bk[qi][u];
-            group_min<32>(v, p, k);
+            int p = bp[qi][u], kk = bk[qi][u];
+            group_min<32>(v, p, kk);
             if ((lane & 31) == 0 && rr[qi][u] >= 0) {
                 Partial o;
                 o.val = v;
                 o.p = p == INT32_MAX ? -1 : p;
-                o.k = k;
+                o.k = kk;
                 part[(size_t)rr[qi][u] * geo.nslot + slot] = o;
             }
         }
+  };
+    for (;;) {
+        __syncthreads();   // every thread is done with the previous item (LDS, s_item)
+        if (tid == 0) s_item = atomicAdd(bt.queue + xcd, 1);
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(s_item);
+        if (idx >= total) break;   // uniform: every wave leaves
+        const int im = find_img(qpre, bt.n, idx);
+        run_item(im, idx - qpre[im]);
+    }
 }
 
 // ---------------------------------------------------------------- launchers
+// Both operand builders in one launch: the range fragments' workgroups
+// first, then the domain tiles'.
+__global__ __launch_bounds__(256) void k_f16_prep(BatchDev b, int na) {
+    if ((int)blockIdx.x < na) k_f16_afrag(b, blockIdx.x);
+    else k_f16_bfrag(b, blockIdx.x - na);
+}
+
 hipError_t launch_f16_prep_b(const BatchHost &b, hipStream_t st) {
-    if (b.blocks[K_AFRAG] > 0) k_f16_afrag<<<b.blocks[K_AFRAG], 256, 0, st>>>(b.dev);
-    if (b.blocks[K_BFRAG] > 0) k_f16_bfrag<<<b.blocks[K_BFRAG], 256, 0, st>>>(b.dev);
+    const int na = b.blocks[K_AFRAG], nt = na + b.blocks[K_BFRAG];
+    if (nt > 0) k_f16_prep<<<nt, 256, 0, st>>>(b.dev, na);
     return hipGetLastError();
 }
 
 template <int KS, int RQ, int DT, int WPE>
 static hipError_t launch_f16_t(const BatchHost &b, hipStream_t st) {
-    k_f16_search<KS, RQ, DT, WPE><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
+    const int grid = persistent_grid((const void *)k_f16_search<KS, RQ, DT, WPE>, b.blocks[K_SEARCH]);
+    k_f16_search<KS, RQ, DT, WPE><<<grid, 256, 0, st>>>(b.dev, b.ss);
     return hipGetLastError();
 }
 
@@ -482,13 +634,12 @@ hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st) {
 #define FIC_F16(KS, RQ, DT, WPE) \
     if (sh.rq == RQ && sh.dt == DT && sh.wpe == WPE) return launch_f16_t<KS, RQ, DT, WPE>(b, st)
     if (B == 2) {
-        FIC_F16(1, 1, 8, 4);
-    } else if (B == 4) {
-        FIC_F16(1, 1, 8, 4);
-        FIC_F16(1, 2, 8, 2);
-        FIC_F16(1, 1, 16, 3);
-        FIC_F16(1, 2, 4, 3);
         FIC_F16(1, 1, 8, 3);
+    } else if (B == 4) {
+        FIC_F16(1, 1, 8, 3);
+        FIC_F16(1, 1, 16, 3);
+        FIC_F16(1, 2, 8, 2);
+        FIC_F16(1, 1, 4, 3);
     } else if (B == 8) {
         FIC_F16(4, 2, 4, 2);
         FIC_F16(4, 1, 4, 3);

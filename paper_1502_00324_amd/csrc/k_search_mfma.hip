@@ -187,13 +187,13 @@ MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, const TileShape &sh) 
 }
 
 // ---------------------------------------------------------------- operands
-__global__ __launch_bounds__(256) void k_mfma_afrag(BatchDev b) {
+__device__ __forceinline__ void k_mfma_afrag(const BatchDev &b, const int bid) {
     const int *pre = b.pre + K_AFRAG * (b.n + 1);
-    const int im = find_img(pre, b.n, blockIdx.x);
+    const int im = find_img(pre, b.n, bid);
     const ImgLvl &d = b.d[im];
     const int B = d.B, KA = d.geo.ka, planes = d.geo.pl == 2, f16 = d.geo.pl == 3, ft = d.geo.pl == 4;
     const int nquads = d.geo.nrg * (d.geo.rpw / 4);
-    const int64_t slot = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;
+    const int64_t slot = (int64_t)(bid - pre[im]) * 256 + threadIdx.x;
     if (slot >= (int64_t)nquads * 2 * KA * 64) return;
     const int lane = (int)(slot & 63);
     int rest = (int)(slot >> 6);
@@ -280,17 +280,18 @@ __device__ __forceinline__ void d4_row8(gptr<uint8_t> pix, int pitch, int x0, in
     }
 }
 
-__global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
+__device__ __forceinline__ void k_mfma_bfrag(const BatchDev &b, const int bid) {
     const int *pre = b.pre + K_BFRAG * (b.n + 1);
-    const int im = find_img(pre, b.n, blockIdx.x);
+    const int im = find_img(pre, b.n, bid);
     const ImgLvl &d = b.d[im];
     const int B = d.B, KA = d.geo.ka, KT = d.geo.kt, planes = d.geo.pl == 2, f16 = d.geo.pl == 3,
               ft = d.geo.pl == 4;
-    const int ntiles = (d.pool_cap + kDomTile - 1) / kDomTile;
+    const int ntiles = mfma_tiles(d.pool_cap);
+    float *dsd = (float *)d.dinfo, *dsa = dsd + (size_t)ntiles * kDomTile;
     // one thread per (tile, K-step, lane) of the output; in the planes form
     // one per K-step of the hi plane, writing both planes
     const int KS = planes ? KA : KT;
-    const int64_t gid = (int64_t)(blockIdx.x - pre[im]) * 256 + threadIdx.x;   // can pass 2^31
+    const int64_t gid = (int64_t)(bid - pre[im]) * 256 + threadIdx.x;   // can pass 2^31
     if (gid >= (int64_t)ntiles * KS * 64) return;
     const int lane = (int)(gid & 63);
     const int rest = (int)(gid >> 6);
@@ -321,9 +322,10 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
         }
         d.bfrag[slot] = make_uint4(wh[0], wh[1], wh[2], wh[3]);
         d.bfrag[slot + (int64_t)KA * 64] = make_uint4(wl[0], wl[1], wl[2], wl[3]);
-        if (s == 0 && kg == 0)
-            d.dinfo[p] = valid ? make_float2((float)d.psum4[p], sqrt_down((double)d.pa[p]))
-                               : make_float2(__builtin_nanf(""), __builtin_nanf(""));  // never passes
+        if (s == 0 && kg == 0) {   // NaN past the pool: no pair there passes
+            dsd[p] = valid ? (float)d.psum4[p] : __builtin_nanf("");
+            dsa[p] = valid ? sqrt_down((double)d.pa[p]) : __builtin_nanf("");
+        }
         return;
     }
     uint32_t w[4] = {0u, 0u, 0u, 0u};
@@ -381,17 +383,22 @@ __global__ __launch_bounds__(256) void k_mfma_bfrag(BatchDev b) {
         }
     }
     d.bfrag[slot] = make_uint4(w[0], w[1], w[2], w[3]);
-    if (s == 0 && kg == 0)
-        d.dinfo[p] = valid ? make_float2((float)d.psum4[p], sqrt_down((double)d.pa[p]))
-                           : make_float2(__builtin_nanf(""), __builtin_nanf(""));  // never passes
+    if (s == 0 && kg == 0) {   // NaN past the pool: no pair there passes
+        dsd[p] = valid ? (float)d.psum4[p] : __builtin_nanf("");
+        dsa[p] = valid ? sqrt_down((double)d.pa[p]) : __builtin_nanf("");
+    }
 }
 
 // ---------------------------------------------------------------- search
-// A workgroup of 4 waves owns 16 RQ ranges (each wave RQ quads) and one chunk
-// of domain tiles.  Domain fragments go straight from global memory into
-// LDS in stages of DT tiles, double-buffered: the loads of stage s+1 into the
-// other buffer are issued before the MFMAs of stage s; the per-domain moments
-// pass through registers and are written after them.
+// A workgroup of 4 waves owns 16 RQ ranges (each wave RQ quads) and the
+// domain tiles of its chunks.  Domain fragments and the per-domain Sd4 and
+// sqrt(A) go straight from global memory into LDS in stages of DT tiles,
+// double-buffered (the loads of stage s+1 are issued before the MFMAs of
+// stage s), through buffer resources based at the chunk's first tile, so a
+// stage's loads differ only by a scalar offset.  A chunk's last stage may
+// read up to DT - 1 tiles past its end: the next chunk's domains (evaluated
+// twice, harmless: the partials merge by (val, domain)) or the zero padding
+// tiles, whose NaN moments never pass.
 template <int PL> struct AccOf { typedef v4i type; typedef int max_type; };   // int32 accumulators
 template <> struct AccOf<3> { typedef v4f type; typedef float max_type; };  // f16 form: f32 accumulators
 template <> struct AccOf<4> { typedef v4f type; typedef float max_type; };  // f16, fused threshold
@@ -412,35 +419,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
     // the two stage buffers of fragments, separate arrays: a stage's
     // direct-to-LDS loads into one are then known not to touch the other
+    constexpr int ND = DT * kDomTile;            // domains per stage
+    constexpr int NDL = FT ? 1 : ND;             // the fused threshold needs no per-domain values
+    static_assert(DT <= kF16PadTiles, "a stage reads at most DT - 1 tiles past a chunk");
     __shared__ uint4 bl0[STAGE];
     __shared__ uint4 bl1[STAGE];
-    __shared__ float2 dl[2][DT * kDomTile];     // (Sd4, sqrt A) per domain
-    __shared__ int64_t dla[2][DT * kDomTile];   // exact A per domain
+    __shared__ float sa0[NDL], sa1[NDL], sd0[NDL], sd1[NDL];   // sqrt(A) rounded down, Sd4
     __shared__ SLds sl;
+    __shared__ int s_item;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
     const SConst sc = make_sconst(ss);
-    const int *bpre = bt.pre + K_SEARCH * (bt.n + 1);
-    const int im = find_img(bpre, bt.n, blockIdx.x);
+    // Persistent: the workgroup takes items (image, range group, chunk walk)
+    // from its XCD's queue until it is empty.  Workgroup w runs on XCD w % 8,
+    // and the items of XCD x walk the chunks x, x + 8, ..., so the concurrent
+    // workgroups of one XCD read the same chunks from its L2.
+    const int xcd = blockIdx.x & 7;
+    const int *qpre = bt.queue + kQueueHeads + xcd * (bt.n + 1);
+    const int total = qpre[bt.n];
+  auto run_item = [&](const int im, const int k) {
     const ImgLvl &dsc = bt.d[im];
     const MfmaGeom geo = dsc.geo;
-    const int lb = blockIdx.x - bpre[im];   // image blocks start at multiples of 8
-    if (lb >= geo.nwg) return;
     const gptr<v4i> afrag = as_global((const v4i *)dsc.afrag);
-    const gptr<uint4> bfrag = as_global(dsc.bfrag);
-    const gptr<float2> dinfo = as_global(dsc.dinfo);
     RInfo *__restrict__ ri = dsc.ri;
     const gptr<int64_t> pa = as_global(dsc.pa);
     Partial *__restrict__ part = dsc.part;
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
+    const int nalloc = mfma_tiles(pool_cap);
+    const float *dsd = (const float *)dsc.dinfo, *dsa = dsd + (size_t)nalloc * kDomTile;
+    const gptr<float> dsd_g = as_global(dsd);
     const float tfac = tn_factor(n);
     const int32_t *np = dsc.pcount;
-    int rg, cfirst, cstep, ncs, slot;
-    chunk_walk(geo, lb, rg, cfirst, cstep, ncs, slot);
     // R: the length of the search list (constant ranges are coded already)
     const int R = min(*dsc.ns, range_cap), P = min(*np, pool_cap);
+    int rg, cfirst, cstep, ncs, slot;
+    item_walk(geo, R, xcd, k, rg, cfirst, cstep, ncs, slot);
     const gptr<int32_t> sidx = as_global(dsc.sidx);
-    if (rg * 16 * RQ >= R) return;  // uniform over the workgroup, before any barrier
     const int ntiles = (P + kDomTile - 1) / kDomTile;
     const int q0 = (rg * 4 + wave) * RQ;
     const bool wave_on = q0 * 4 < R;
@@ -466,6 +480,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         cr[qi] = x.cr;
         tn[qi] = r >= 0 ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
         tb[qi] = INT64_MAX;
+        // start from the best other walks of this range have shared (a stale
+        // copy only loosens the test)
+        if (r >= 0 && x.gbest < INT64_MAX) {
+            tb[qi] = x.gbest;
+            tn[qi] = tn_shared(x.gbest, x.cr, sc, tfac);
+        }
         best[qi] = INT64_MAX;
         bp[qi] = INT32_MAX;
         bk[qi] = 0;
@@ -509,43 +529,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // them inside the tile loop would also wait for the stage prefetch.
     __builtin_amdgcn_s_waitcnt(0);
 
-    // per-domain moments of a stage: DT * kDomTile entries over the 256 threads
-    constexpr int PER_D = (DT * kDomTile + 255) / 256;
-    float2 dpre[PER_D];
-    int64_t apre[PER_D];
-    int t0 = 0, t1 = 0;  // tile range of the chunk being streamed
-    // Fragments go straight from global memory to LDS (one 16-byte load per
-    // lane into 1 KiB per wave, no registers); indexes are clamped to the
-    // chunk's last tile, so the tiles past its end hold copies, harmless
-    // under their NaN moments.
-    auto gload = [&](uint4 *dst, int stg) {
-        const int tbase = t0 + stg * DT;
-        const size_t fend = (size_t)t1 * KB * 64 - 1;
+    typedef __attribute__((address_space(3))) void *lds_t;
+    // the wave index as a scalar: the LDS destination of a direct load is a
+    // per-wave base in M0
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    constexpr int PER_D = (ND + 255) / 256;
+    int t0 = 0;  // first tile of the chunk being streamed
+    __amdgpu_buffer_rsrc_t rfrag, rsa, rsd;
+    // one stage of the current chunk into the LDS buffers given: fragments,
+    // then per-domain values; wave w fills its own 64-slot blocks
+    auto gload = [&](uint4 *fdst, float *adst, float *ddst, int stg) {
 #pragma unroll
-        for (int i = 0; i < PER_T; ++i) {
-            const size_t e = min((size_t)tbase * KB * 64 + tid + 256 * i, fend);
-            __builtin_amdgcn_global_load_lds((gptr<void>)(bfrag + e),
-                                             (__attribute__((address_space(3))) void *)(dst + 64 * wave + 256 * i),
-                                             16, 0, 0);
-        }
-        // tiles past the chunk end get NaN moments: no pair on them passes
+        for (int i = 0; i < PER_T; ++i)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rfrag, (lds_t)(fdst + 64 * wv + 256 * i), 16,
+                                                     (unsigned)(tid + 256 * i) * 16u, (unsigned)stg * STAGE * 16u, 0,
+                                                     0);
+        if constexpr (!FT) {
 #pragma unroll
-        for (int i = 0; i < PER_D; ++i) {
-            const int e = tid + 256 * i;
-            if (e < DT * kDomTile) {
-                const int p = tbase * kDomTile + e;
-                dpre[i] = tbase + e / kDomTile < t1 ? ldg(dinfo, p) : make_float2(__builtin_nanf(""), __builtin_nanf(""));
-                apre[i] = p < P ? pa[p] : 0;
-            }
-        }
-    };
-    auto swrite = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < PER_D; ++i) {
-            const int e = tid + 256 * i;
-            if (e < DT * kDomTile) {
-                dl[buf][e] = dpre[i];
-                dla[buf][e] = apre[i];
+            for (int i = 0; i < PER_D; ++i) {
+                if (ND % 256 == 0 || tid + 256 * i < ND) {
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsa, (lds_t)(adst + 64 * wv + 256 * i), 4,
+                                                             (unsigned)(tid + 256 * i) * 4u, (unsigned)stg * ND * 4u,
+                                                             0, 0);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsd, (lds_t)(ddst + 64 * wv + 256 * i), 4,
+                                                             (unsigned)(tid + 256 * i) * 4u, (unsigned)stg * ND * 4u,
+                                                             0, 0);
+                }
             }
         }
     };
@@ -627,12 +636,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // plan, the pool size only known here)
     const int tpc = (ntiles + geo.nchunk - 1) / geo.nchunk;
     t0 = chunk * tpc;
-    t1 = min(ntiles, t0 + tpc);
+    const int t1 = min(ntiles, t0 + tpc);
     const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
-    if (nstage > 0) {
-        gload(bl0, 0);
-        swrite(0);
-    }
+    if (nstage == 0) continue;   // uniform over the workgroup
+    // resources over [t0, nalloc): a chunk's offsets stay below 2^31 (the plan checks)
+    const int left = uniform((int)min((long)(nalloc - t0) * kDomTile * 4, (long)INT32_MAX));
+    rfrag = buffer_rsrc(dsc.bfrag + (size_t)t0 * KB * 64,
+                        uniform((int)min((long)(nalloc - t0) * KB * 1024, (long)INT32_MAX)));
+    rsa = buffer_rsrc(dsa + (size_t)t0 * kDomTile, left);
+    rsd = buffer_rsrc(dsd + (size_t)t0 * kDomTile, left);
+    gload(bl0, sa0, sd0, 0);
     // the direct-to-LDS loads count on vmcnt only: every wave drains its own
     // before the barrier that publishes the stage
     __builtin_amdgcn_s_waitcnt(0);
@@ -641,7 +654,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     auto stage = [&](auto bc, int stg) {
         constexpr int buf = decltype(bc)::value;
         uint4 *const Bs = buf ? bl1 : bl0;
-        if (stg + 1 < nstage) gload(buf ? bl0 : bl1, stg + 1);
+        const float *const As = buf ? sa1 : sa0;
+        const float *const Ds = buf ? sd1 : sd0;
+        if (stg + 1 < nstage) {
+            if constexpr (buf) gload(bl0, sa0, sd0, stg + 1);
+            else gload(bl1, sa1, sd1, stg + 1);
+        }
         // the range bests of other workgroups: issued after the stage prefetch
         // (so its wait does not include them) and applied at the stage end
         int64_t gl[RQ];
@@ -653,13 +671,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             // prune test of tile dt, in the same basic block
             Acc acc[2][RQ][2][NP];
             v4i Bq[2][KR];
+            // the per-domain values are read one tile ahead of their test, so
+            // the test never waits for LDS
+            float sq_n = FT ? 0.f : As[lane & 15], sd_n = FT ? 0.f : Ds[lane & 15];
             if constexpr (PREF) read_tile(Bq[0], Bs, 0);
             mfma_tile(acc[0], Bs, 0, Bq[0]);
             if (PREF && DT > 1) read_tile(Bq[1], Bs, 1);
 #pragma unroll
             for (int dt = 0; dt < DT; ++dt) {
                 const int cur = dt & 1;
+                const int col = dt * kDomTile + (lane & 15);
+                const float sqa = sq_n;
+                float sd4f = sd_n;
                 if (dt + 1 < DT) {
+                    if constexpr (!FT) {
+                        sq_n = As[col + kDomTile];
+                        sd_n = Ds[col + kDomTile];
+                    }
                     mfma_tile(acc[cur ^ 1], Bs, dt + 1, Bq[(dt + 1) & 1]);
                     // the set of tile dt is free once tile dt's MFMAs were issued
                     if (PREF && dt + 2 < DT) read_tile(Bq[dt & 1], Bs, dt + 2);
@@ -667,7 +695,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 bool pass[RQ];
                 bool any = false;
                 MaxT mx[RQ];
-                float2 di = make_float2(0.f, 0.f);
                 if constexpr (FT) {
                     // the threshold is in the accumulators: max over the 8 isometries > 0
 #pragma unroll
@@ -677,11 +704,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                         any |= pass[qi];
                     }
                 } else {
-                    di = dl[buf][dt * kDomTile + (lane & 15)];
 #pragma unroll
                     for (int qi = 0; qi < RQ; ++qi) {
                         mx[qi] = cmax(acc[cur][qi][0], acc[cur][qi][1]);
-                        const float rhs = fmaf(tn[qi], di.y, fmaf(-bn[qi], di.x, -an[qi]));
+                        const float rhs = fmaf(tn[qi], sqa, fmaf(-bn[qi], sd4f, -an[qi]));
                         // false on NaN: rows past the ranges, domains past the
                         // pool or the chunk, and ranges already at val 0
                         pass[qi] = (float)mx[qi] > rhs;
@@ -698,10 +724,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                     }
                 }
                 if (__builtin_amdgcn_ballot_w64(any)) {  // rare: exact evaluation, then share the best
-                    const int col = dt * kDomTile + (lane & 15);
                     const int p = tbase * kDomTile + col;
-                    if constexpr (FT) di = dl[buf][col];
-                    const int64_t sd4 = (int64_t)di.x, Ad = dla[buf][col];  // Sd4 < 2^24: exact in float
+                    // Sd4 < 2^24: exact in float.  A passing pair is a pool domain
+                    // (p < P), except in the fused form, whose confirm runs in every
+                    // lane: there a domain past the pool reads padding (NaN, no pair
+                    // of it passes) and no A
+                    const int64_t sd4 = (int64_t)(FT ? dsd_g[p] : sd4f);
+                    const int64_t Ad = p < P ? pa[p] : 0;
                     // FT: the domain tile's fragment again, for acc1 without the threshold
                     v4i bt1 = v4i{0, 0, 0, 0};
                     int64_t ed = 0;
@@ -728,6 +757,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                         } else if (pass[qi]) {
                             imp = confirm_pair((int)mx[qi], p, sd4, Ad, sr[qi], cr[qi], n, sl, sc, best[qi], bp[qi], bk[qi]);
                         }
+                        // only a lane best that tightens the shared one is worth sharing
+                        // (or a walk's own 0, which ends the walk for the range)
+                        imp = imp && (best[qi] < tb[qi] || best[qi] == 0);
                         if (__builtin_amdgcn_ballot_w64(imp)) {
                             // the 16 lanes holding this range share their best: the
                             // threshold may use it because a pair is only rejected
@@ -744,7 +776,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 }
             }
         }
-        if (stg + 1 < nstage) swrite(buf ^ 1);
 #pragma unroll
         for (int qi = 0; qi < RQ; ++qi) {
             const bool changed = gl[qi] < tb[qi];
@@ -767,28 +798,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
     for (int qi = 0; qi < RQ; ++qi) {
         int64_t v = best[qi];
-        int p = bp[qi], k = bk[qi];
-        group_min<16>(v, p, k);
+        int p = bp[qi], kk = bk[qi];
+        group_min<16>(v, p, kk);
         if ((lane & 15) == 0 && rr[qi] >= 0) {
             Partial o;
             o.val = v;
             o.p = p == INT32_MAX ? -1 : p;
-            o.k = k;
+            o.k = kk;
             part[(size_t)rr[qi] * geo.nslot + slot] = o;
         }
+    }
+  };
+    for (;;) {
+        __syncthreads();   // every thread is done with the previous item (LDS, s_item)
+        if (tid == 0) s_item = atomicAdd(bt.queue + xcd, 1);
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(s_item);
+        if (idx >= total) break;   // uniform: every wave leaves
+        const int im = find_img(qpre, bt.n, idx);
+        run_item(im, idx - qpre[im]);
     }
 }
 
 // ---------------------------------------------------------------- launchers
+// Both operand builders in one launch: the range fragments' workgroups
+// first, then the domain tiles'.
+__global__ __launch_bounds__(256) void k_mfma_prep(BatchDev b, int na) {
+    if ((int)blockIdx.x < na) k_mfma_afrag(b, blockIdx.x);
+    else k_mfma_bfrag(b, blockIdx.x - na);
+}
+
 hipError_t launch_mfma_prep_b(const BatchHost &b, hipStream_t st) {
-    if (b.blocks[K_AFRAG] > 0) k_mfma_afrag<<<b.blocks[K_AFRAG], 256, 0, st>>>(b.dev);
-    if (b.blocks[K_BFRAG] > 0) k_mfma_bfrag<<<b.blocks[K_BFRAG], 256, 0, st>>>(b.dev);
+    const int na = b.blocks[K_AFRAG], nt = na + b.blocks[K_BFRAG];
+    if (nt > 0) k_mfma_prep<<<nt, 256, 0, st>>>(b.dev, na);
     return hipGetLastError();
 }
 
 template <int KA, int PL, int RQ, int DT, int WPE>
 static hipError_t launch_search_t(const BatchHost &b, hipStream_t st) {
-    k_mfma_search<KA, PL, RQ, DT, WPE><<<b.blocks[K_SEARCH], 256, 0, st>>>(b.dev, b.ss);
+    const int grid = persistent_grid((const void *)k_mfma_search<KA, PL, RQ, DT, WPE>, b.blocks[K_SEARCH]);
+    k_mfma_search<KA, PL, RQ, DT, WPE><<<grid, 256, 0, st>>>(b.dev, b.ss);
     return hipGetLastError();
 }
 

@@ -38,6 +38,25 @@ __device__ __forceinline__ float2 ldg(gptr<float2> p, size_t i) {
     return make_float2(v.x, v.y);
 }
 
+// Values every lane holds alike, moved to scalar registers: a buffer
+// resource built from them then lives in scalar registers, as the buffer
+// instructions require (else the compiler loops over the lanes' values).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <class T>
+__device__ __forceinline__ const T *uniform(const T *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const T *)(((uint64_t)hi << 32) | lo);
+}
+
+// Raw buffer resource over `bytes` bytes at p (p and bytes alike in every
+// lane): unit stride, the gfx9 data-format word.
+template <class T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const T *p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)uniform(p), 0, bytes, 0x00020000);
+}
+
 __device__ inline bool lex_less_vp(int64_t va, int pa, int64_t vb, int pb) {
     return va < vb || (va == vb && pa < pb);
 }
@@ -47,6 +66,9 @@ __device__ __forceinline__ int max8(int a0, int a1, int a2, int a3, int b0, int 
     const int m1 = max(max(a0, a1), a2), m2 = max(max(a3, b0), b1), m3 = max(b2, b3);
     return max(max(m1, m2), m3);
 }
+
+// NaN-propagating 3-input maximum (one v_maximum3_f32).
+#define FIC_MAX3(x, y, z) __builtin_elementwise_maximum(__builtin_elementwise_maximum(x, y), z)
 
 // Maximum of 8 floats as four v_maximum3_f32.  The NaN-propagating maximum
 // needs no input canonicalisation (fmaxf would add one v_max per input in IEEE
@@ -137,18 +159,23 @@ __device__ inline uint32_t pack_h2(_Float16 lo, _Float16 hi) {
 // (1 - 2^-20) / n, the final factor of the prune threshold below.
 __device__ inline float tn_factor(int n) { return (1.0f - 1.0f / 1048576.0f) / (float)n; }
 
-// Prune threshold tn = sqrt(Cr - best/(16 den^2)) / n, rounded down: the int
-// to float conversion, the two products, the square root and the factor each
-// round by at most 2^-24 relative, and the 1 - 2^-20 in the factor covers
-// them all.  No best yet (or c < 0): every pair passes.  A pair is rejected
+// Prune threshold tn = sqrt(Cr - best/(16 den^2)) / n, rounded down.  The
+// numerator 0 <= num < 2^60 goes to float from its 32-bit halves (two
+// conversions and one fma, each rounding by at most 2^-24 relative, and the
+// high half times 2^32 is at most num since the low half is non-negative);
+// the product with 1/(16 den^2) and that reciprocal round by 2^-24 each, the
+// hardware square root (v_sqrt_f32) is within 1 ulp (2^-23) and halves the
+// relative error of its input, and the final product and the factor round
+// by 2^-24 each: together below 7 * 2^-24, which the 1 - 2^-20 in the factor
+// covers.  No best yet (or c < 0): every pair passes.  A pair is rejected
 // only when it cannot even tie best, so best may come from any pair of the
 // range, found by this workgroup or another.
 __device__ __forceinline__ float tn_shared(int64_t best, int64_t cr, const SConst &sc, float factor) {
     if (best == INT64_MAX) return -1e30f;
     const int64_t num = sc.scale * cr - best;
     if (num < 0) return -1e30f;
-    const float c = (float)num * sc.inv_scale;
-    return sqrtf(c) * factor;
+    const float f = fmaf((float)(int32_t)(num >> 32), 4294967296.0f, (float)(uint32_t)num);
+    return __builtin_amdgcn_sqrtf(f * sc.inv_scale) * factor;
 }
 
 // Threshold from the best of this workgroup's own walk.  A best of 0 cannot

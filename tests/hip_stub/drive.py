@@ -31,12 +31,18 @@ KIND_OF = [("k_level0", K_LEVEL0), ("k_pool_keys", K_KEYS), ("k_sel_hist", K_HIS
            ("k_integ_rows", K_IROW), ("k_integ_colsum", K_ICOL), ("k_integ_coladd", K_ICOL),
            ("k_integ_colscan", K_ICSCAN)]
 PER_IMAGE = ("k_sel_init", "k_sel_pick", "k_bscan", "k_sel_fused")
+ONE_BLOCK = ("k_search_plan",)
 KIND_ARG = ("k_bcount", "k_bscatter")
 NUM_KINDS = 16
 
 
 class BatchDev(ctypes.Structure):
-    _fields_ = [("d", ctypes.c_void_p), ("pre", ctypes.POINTER(ctypes.c_int32)), ("n", ctypes.c_int32)]
+    _fields_ = [("d", ctypes.c_void_p), ("pre", ctypes.POINTER(ctypes.c_int32)), ("n", ctypes.c_int32),
+                ("queue", ctypes.c_void_p)]
+
+
+# resident workgroups of a persistent search under the stub: 2 per CU x 256 CUs
+PERSISTENT_CAP = 512
 
 
 HOOK = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_uint, ctypes.c_uint, ctypes.POINTER(ctypes.c_void_p))
@@ -45,10 +51,23 @@ log = {"launches": [], "errors": [], "forms": [], "shapes": []}
 
 def on_launch(name, grid, block, args):
     name = name.decode()
+    if "k_f16_prep" in name or "k_mfma_prep" in name:   # both operand builders in one launch
+        bd = ctypes.cast(args[0], ctypes.POINTER(BatchDev)).contents
+        n = bd.n
+        pre = np.ctypeslib.as_array(bd.pre, shape=(NUM_KINDS * (n + 1),)).reshape(NUM_KINDS, n + 1).copy()
+        na = ctypes.cast(args[1], ctypes.POINTER(ctypes.c_int32)).contents.value
+        if na != pre[K_AFRAG, n] or grid != pre[K_AFRAG, n] + pre[K_BFRAG, n]:
+            log["errors"].append("%s: grid %d (%d range blocks), planned %d + %d" % (name, grid, na, pre[K_AFRAG, n],
+                                                                                   pre[K_BFRAG, n]))
+        log["launches"].append(("k_prep", grid, None))
+        return
     short = next((k for k, _ in KIND_OF if k in name), None) or next(
-        (k for k in PER_IMAGE + KIND_ARG if k in name), None)
+        (k for k in PER_IMAGE + KIND_ARG + ONE_BLOCK if k in name), None)
     if short is None:
-        log["launches"].append((name, grid, None))
+        # kernels with no planned grid: logged by their short name
+        m = re.match(r"_ZN3fic(\d+)", name)
+        short = name[m.end():m.end() + int(m.group(1))] if m else name
+        log["launches"].append((short, grid, None))
         return
     bd = ctypes.cast(args[0], ctypes.POINTER(BatchDev)).contents
     n = bd.n
@@ -57,6 +76,8 @@ def on_launch(name, grid, block, args):
         log["errors"].append("%s: prefix table not a prefix sum" % short)
     if short in PER_IMAGE:
         want, kind = n, None
+    elif short in ONE_BLOCK:
+        want, kind = 1, None
     elif short in KIND_ARG:
         kind = ctypes.cast(args[1], ctypes.POINTER(ctypes.c_int32)).contents.value
         want = pre[kind, n]
@@ -73,8 +94,13 @@ def on_launch(name, grid, block, args):
             # the tile shape: (pl, rq, dt, wpe), pl = 0 for the 32x32 kernel
             a = [int(v) for v in re.findall(r"Li(\d+)E", name.split(short, 1)[1].split("EEv", 1)[0])]
             log["shapes"].append(a[1:] if short == "k_mfma_search" else [0] + a[1:])
-        if short in ("k_mfma_search", "k_f16_search") and (pre[kind] % 8 != 0).any():
-            log["errors"].append("%s: an image's workgroups do not start on a multiple of 8" % short)
+        if short in ("k_mfma_search", "k_f16_search"):
+            if (pre[kind] % 8 != 0).any():
+                log["errors"].append("%s: an image's workgroups do not start on a multiple of 8" % short)
+            # persistent: the resident workgroups, at most the static count
+            want = min(want, PERSISTENT_CAP)
+            if bd.queue is None:
+                log["errors"].append("%s: no work queue" % short)
     if grid != want:
         log["errors"].append("%s: grid %d, planned %d" % (short, grid, want))
     log["launches"].append((short, grid, kind))

@@ -125,6 +125,11 @@ CASES = [
     # B = 32 over ~200 domain tiles with a ragged last tile, 3 range groups
     ("b32_multi_tile", 13, 256, 192, 12, [(32, 2), (16, 2)], (1, 2), 0, K16, 16, (8, 1)),
     ("pool_max_ties", 11, 96, 64, 30, [(8, 2), (4, 2)], (1, 10), 100, K16, 16, (6, 1)),
+    # many flat rectangles and no entropy filter: constant domains (A = 0) in
+    # the pool at B = 4 and 2, searched with and without s = 0 in S (without
+    # it, flat ranges are searched too; with it, pairs tie at s = 0)
+    ("flat_domains_s_without_0", 14, 96, 64, 40, [(4, 2), (2, 2)], (0, 1), 0, (1, 2, 3), 4, (4, 1)),
+    ("flat_domains_k16", 15, 96, 64, 40, [(4, 1)], (0, 1), 0, K16, 16, (8, 1)),
 ]
 
 

@@ -133,7 +133,7 @@ def test_shape_candidates_listed(runs):
     assert [len(c["0,%d" % B]) for B in (2, 4, 8, 16, 32)][1:] == [3, 6, 6, 3]
     assert len(c["0,2"]) == 0 and len(c["1,32"]) == 0 and len(c["2,32"]) == 0
     assert c["0,16"][0] == [2, 2, 1, 3] and c["0,32"][0] == [2, 1, 1, 2] and c["1,8"][0] == [3, 2, 8, 3]
-    assert c["2,4"][0] == [0, 1, 8, 4] and all(s[0] == 4 for s in c["1,4"])
+    assert c["2,4"][0] == [0, 1, 8, 3] and all(s[0] == 4 for s in c["1,4"])
     for k, v in c.items():
         assert len({tuple(s) for s in v}) == len(v), k   # no duplicates
 
@@ -173,3 +173,25 @@ def test_decode_noalloc_allocates_nothing(runs):
     assert n["over_launches"] == 0 and n["over_allocs"] == 0
     # the ordinary decoder grows its scratch and records timing events
     assert n["decode_allocs"] > 0
+
+
+def test_launches_per_level(runs):
+    # one 512 x 512 image, one level at B = 4, L = 1 (multi-pass selection):
+    # selection state, keys, 6 digit passes of histogram and pick, pool
+    # count, scan and scatter, moments, search-list reset, range moments,
+    # operands (one launch for both sides), search queue, persistent search,
+    # codes (25 launches; the last level has no child compaction)
+    level = (["k_sel_init", "k_pool_keys"] + ["k_sel_hist", "k_sel_pick"] * 6 +
+             ["k_bcount", "k_bscan", "k_bscatter", "k_pool_moments", "k_search_list_reset", "k_range_info", "k_prep",
+              "k_search_plan", "k_f16_search", "k_finalize"])
+    setup = ["k_level0", "k_integ_rows", "k_integ_colsum", "k_integ_colscan", "k_integ_coladd"]
+    assert kinds(runs["large_uncapped"]) == setup + level
+    # small images (one-workgroup selection), two levels: 13 launches per
+    # level, plus the child compaction of the first
+    small = ["k_sel_init", "k_pool_keys", "k_sel_fused", "k_bcount", "k_bscan", "k_bscatter", "k_pool_moments",
+             "k_search_list_reset", "k_range_info", "k_prep", "k_search_plan", None, "k_finalize"]
+    k = kinds(runs["single_mfma"])
+    per_rep = len(k) // 2
+    assert per_rep == len(setup) + 2 * len(small) + 3, k
+    first = k[len(setup):len(setup) + len(small) + 3]
+    assert [a for a, b in zip(first, small + ["k_bcount", "k_bscan", "k_bscatter"]) if b is not None and a != b] == [], first
