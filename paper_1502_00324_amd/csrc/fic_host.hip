@@ -408,7 +408,8 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
                 d.afrag = (uint4 *)take(S_AFRAG, (size_t)afr * 1024);
                 // the f16 form at B <= 4 keeps a second, exact copy of the tiles
                 d.bfrag = (uint4 *)take(S_BFRAG, (size_t)ntiles * d.geo.kt * 1024 * (f16 && d.B <= 4 ? 2 : 1));
-                d.dinfo = (float2 *)take(S_DINFO, (size_t)ntiles * tile * sizeof(float2));
+                // f16: Sd4 and sqrt(A), then the exact (A, Sd4); int8: the first two
+                d.dinfo = (float2 *)take(S_DINFO, (size_t)ntiles * tile * sizeof(float2) * (f16 ? 2 : 1));
             } else {
                 fp32_geometry(d.B, d.range_cap, d.pool_cap, &d.fnchunk, &d.ftpc);
                 d.rpad = fp32_rpad(d.range_cap);

@@ -50,7 +50,7 @@ bool f16_supported(int B) { return B == 2 || B == 4 || B == 8 || B == 16; }
 // Mean-centred operands (the header describes them): every size up to 8.
 __host__ __device__ inline bool f16_centred(int B) { return B <= 8; }
 // Normalised domain operands with the threshold in the accumulator input
-// (one K-step: B = 2 and 4).
+// (one K-step: B = 2 and 4); the exact tiles are kept beside them.
 __host__ __device__ inline bool f16_normalised(int B) { return B <= 4; }
 
 // Range quads per wave (RQ), domain tiles per LDS stage (DT) and the
@@ -60,7 +60,7 @@ __host__ __device__ inline bool f16_normalised(int B) { return B <= 4; }
 struct F16Shape { int B, rq, dt, wpe; };
 static const F16Shape kF16Shapes[] = {
     {2, 1, 8, 3},
-    {4, 1, 8, 3}, {4, 1, 16, 3}, {4, 2, 8, 2}, {4, 1, 4, 3},
+    {4, 1, 16, 3}, {4, 1, 8, 3}, {4, 2, 8, 2}, {4, 1, 4, 3},
     {8, 2, 4, 2}, {8, 1, 4, 3}, {8, 1, 8, 2}, {8, 2, 2, 2},
     {16, 1, 1, 3}, {16, 1, 2, 2},
 };
@@ -147,8 +147,9 @@ __device__ __forceinline__ void k_f16_afrag(const BatchDev &b, const int bid) {
 // Domain operands: f16_tiles(pool_cap) tiles, the last kF16PadTiles of them
 // zero, so that a stage may read past a chunk's end without a bound check.
 // Per domain, structure of arrays in dinfo: Sd4 for all the tiles' domains,
-// then sqrt(A) rounded down; NaN past the pool (no pair on them passes the
-// test).
+// then sqrt(A) rounded down (NaN past the pool: no pair on them passes the
+// test), then with centring the pair (A, Sd4) as 32-bit integers, which the
+// exact evaluation reads from LDS (A <= n^2 1020^2 / 4 < 2^32 for B <= 8).
 __device__ __forceinline__ void k_f16_bfrag(const BatchDev &b, const int bid) {
     const int *pre = b.pre + K_BFRAG * (b.n + 1);
     const int im = find_img(pre, b.n, bid);
@@ -184,9 +185,9 @@ __device__ __forceinline__ void k_f16_bfrag(const BatchDev &b, const int bid) {
         for (int e = 0; e < 8; ++e) w[e] = (_Float16)0;
     }
     if (f16_normalised(B)) {
-        // the exact tile goes to the second array (the confirm reads it); the
-        // searched one holds 2^16 (D4 - Sd4/n) / sqrt(A): 0 when A = 0, NaN
-        // past the pool (a NaN column fails every test)
+        // the exact tile goes to the second array (the exact evaluation reads
+        // it); the searched one holds 2^16 (D4 - Sd4/n) / sqrt(A): 0 when
+        // A = 0, NaN past the pool (a NaN column fails every test)
         ((h8 *)d.bfrag)[(size_t)ntiles * KS * 64 + slot] = w;
         h8 z;
         if (valid) {
@@ -218,17 +219,25 @@ __device__ __forceinline__ void k_f16_bfrag(const BatchDev &b, const int bid) {
         float *dsd = (float *)d.dinfo, *dsa = dsd + (size_t)ntiles * kDomTile32;
         dsd[p] = valid ? (float)d.psum4[p] : __builtin_nanf("");
         dsa[p] = valid ? sqrt_down((double)d.pa[p]) : __builtin_nanf("");
+        if (f16_centred(B)) {
+            uint2 *dsx = (uint2 *)(dsa + (size_t)ntiles * kDomTile32);
+            dsx[p] = valid ? make_uint2((uint32_t)d.pa[p], (uint32_t)d.psum4[p]) : make_uint2(0u, 0u);
+        }
     }
 }
 
 // ---------------------------------------------------------------- search
 // A workgroup of 4 waves owns 16 RQ ranges (each wave RQ quads) and the
-// domain tiles of its chunks.  Domain fragments and the per-domain sqrt(A)
-// (Sd4 as well without centring) go straight from global memory into LDS in
-// stages of DT tiles, double-buffered (the loads of stage s+1 are issued
-// before the MFMAs of stage s), through buffer resources based at the
-// chunk's first tile: a stage's loads differ only by a scalar offset, so
-// they take no vector instructions.  A chunk's last stage may read up to
+// domain tiles of its chunks.  Domain fragments and the per-domain values
+// go straight from global memory into LDS in stages of DT tiles,
+// double-buffered (the loads of stage s+1 are issued before the MFMAs of
+// stage s), through buffer resources based at the chunk's first tile: a
+// stage's loads differ only by a scalar offset, so they take no vector
+// instructions.  Per domain a stage holds sqrt(A) for the prune test and,
+// with centring, the exact (A, Sd4) of the exact evaluation (without it, Sd4
+// for the test), so a passing pair is evaluated from LDS and registers: a
+// global load there would also wait for the stage prefetch, the vector
+// memory counter being in order.  A chunk's last stage may read up to
 // DT - 1 tiles past its end: the next chunk's domains (evaluated twice,
 // harmless: the partials merge by (val, domain)) or the zero padding tiles,
 // whose NaN sqrt(A) never passes.  The MFMAs of tile t+1 are issued before
@@ -237,13 +246,18 @@ template <int KS, int RQ, int DT, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_f16_search(BatchDev bt, SSet ss) {
     constexpr bool CEN = KS <= 4;                // mean-centred operands (B <= 8)
     constexpr bool NORM = KS == 1;               // normalised domains, threshold in the accumulator (B <= 4)
+    constexpr int G = NORM ? 4 : 1;              // tiles per pass test (normalised form)
     constexpr int STAGE = DT * KS * 64;          // uint4 per stage
-    constexpr int ND = NORM ? 1 : DT * kDomTile32;   // per-domain values staged per stage (none when NORM)
+    // domains per stage whose values are staged: none for the normalised
+    // form (only its exact evaluation reads them, from global memory)
+    constexpr int ND = NORM ? 1 : DT * kDomTile32;
     // share range bests across workgroups only when a stage is long enough
     // (>= 4 tiles) to hide the coherent load of the shared values
     constexpr bool SHARE = DT >= 4;
     constexpr int PER_T = STAGE / 256;
     constexpr int PER_D = (ND + 255) / 256;
+    constexpr int NX = NORM ? 1 : ND / 2;        // 16-byte (A, Sd4) records of two domains
+    constexpr int PER_X = (NX + 255) / 256;
     static_assert(STAGE % 256 == 0, "stage must split evenly over 256 threads");
     static_assert(DT <= kF16PadTiles, "a stage reads at most DT - 1 tiles past a chunk");
     // the two stage buffers, separate arrays: a stage's direct-to-LDS loads
@@ -252,6 +266,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     __shared__ uint4 bl1[STAGE];
     __shared__ float sa0[ND], sa1[ND];                          // sqrt(A) rounded down
     __shared__ float sd0[CEN ? 1 : ND], sd1[CEN ? 1 : ND];      // Sd4 (the uncentred test only)
+    __shared__ uint4 sx0[CEN ? NX : 1], sx1[CEN ? NX : 1];      // exact (A, Sd4) (centred only)
     __shared__ SLds sl;
     __shared__ int s_item;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -274,7 +289,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
     const int nalloc = f16_tiles(pool_cap);
     const float *dsd = (const float *)dsc.dinfo, *dsa = dsd + (size_t)nalloc * kDomTile32;
-    const gptr<float> dsd_g = as_global(dsd), dsa_g = as_global(dsa);
+    const uint2 *dsx = (const uint2 *)(dsa + (size_t)nalloc * kDomTile32);
+    const gptr<float> dsa_g = as_global(dsa);
+    const gptr<uint64_t> dsx_g = as_global((const uint64_t *)dsx);   // (A, Sd4): low, high word
     // the exact copy of the tiles (normalised form), after the searched ones
     const gptr<h8> bfx = as_global((const h8 *)(dsc.bfrag + (size_t)nalloc * KS * 64));
     const float tfac = tn_factor(n);
@@ -297,7 +314,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     f16x cth[NORM ? RQ : 1];
     float marg[RQ][2];
     int64_t best[RQ][2], cr[RQ][2], tb[RQ][2];  // tb: the best value tn reflects
-    int bp[RQ][2], bk[RQ][2], rr[RQ][2], sr[RQ][2];
+    int bp[RQ][2], bk[RQ][2], rr[RQ][2], sr[RQ][2], er[RQ][2];
+    const int lgn = __builtin_ctz(n);   // n = B^2, B a power of two
     // The normalised test: acc' = sum (r - m_r) 2^16 (D4 - Sd4/n)/sqrt(A) + c is
     // 2^16 Bx/(n sqrt A) + c up to the range's margin, and a pair can reach
     // the best only if Bx/(n sqrt A) > tn, so with c = margin - 2^16 tn (1 -
@@ -328,6 +346,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             bn[qi][u] = x.bn;
             an[qi][u] = x.an;
             sr[qi][u] = (int)x.sr;
+            // e_r = Sr - n round(Sr / n): the centring error of the range
+            er[qi][u] = (int)x.sr - (((int)x.sr + n / 2) >> lgn << lgn);
             cr[qi][u] = x.cr;
             tn[qi][u] = r >= 0 ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
             tb[qi][u] = INT64_MAX;
@@ -357,10 +377,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // per-wave base in M0
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     int t0 = 0;
-    __amdgpu_buffer_rsrc_t rfrag, rsa, rsd;
+    __amdgpu_buffer_rsrc_t rfrag, rsa, rsd, rsx;
     // one stage of the current chunk into the LDS buffers given: fragments,
     // then per-domain values; wave w fills its own 64-slot blocks
-    auto gload = [&](uint4 *fdst, float *adst, float *ddst, int stg) {
+    auto gload = [&](uint4 *fdst, float *adst, float *ddst, uint4 *xdst, int stg) {
 #pragma unroll
         for (int i = 0; i < PER_T; ++i)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rfrag, (lds_t)(fdst + 64 * wv + 256 * i), 16,
@@ -378,13 +398,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                                              0, 0);
             }
         }
+        if constexpr (CEN && !NORM) {
+#pragma unroll
+            for (int i = 0; i < PER_X; ++i)
+                if (NX % 256 == 0 || tid + 256 * i < NX)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsx, (lds_t)(xdst + 64 * wv + 256 * i), 16,
+                                                             (unsigned)(tid + 256 * i) * 16u,
+                                                             (unsigned)stg * ND * 8u, 0, 0);
+        }
     };
-    // With up to 4 K-steps a tile's fragments are read into registers one
-    // tile ahead of its MFMAs (two sets alternate), so the LDS latency is
-    // covered by the previous tile; longer tiles read them in groups of 8, so
-    // one LDS wait covers a group rather than every MFMA.
+    // With up to 4 K-steps a tile's fragments are read into registers ahead
+    // of its MFMAs, NSET sets in rotation: the read of tile t + NSET is issued
+    // right after the MFMAs of tile t + 1, so it has NSET - 1 prune tests to
+    // land before its own MFMAs (three sets where the registers allow).
+    // Longer tiles read them in groups of 8, so one LDS wait covers a group
+    // rather than every MFMA.
     constexpr bool PREF = KS <= 4;
     constexpr int KG = PREF ? KS : 8;
+    constexpr int NSET = PREF && (KS == 1 || WPE <= 2) ? 3 : 2;
     auto read_tile = [&](h8 (&bf)[KG], const uint4 *Bs, int dt, int s0) {
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
@@ -415,12 +446,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         const int nstage = t1 > t0 ? (t1 - t0 + DT - 1) / DT : 0;
         if (nstage == 0) continue;   // uniform over the workgroup
         // resources over [t0, nalloc): a chunk's offsets stay below 2^31 (the plan checks)
-        const int left = uniform((int)min((long)(nalloc - t0) * kDomTile32 * 4, (long)INT32_MAX));
-        rfrag = buffer_rsrc(dsc.bfrag + (size_t)t0 * KS * 64, uniform((int)min((long)(nalloc - t0) * KS * 1024,
-                                                                               (long)INT32_MAX)));
-        rsa = buffer_rsrc(dsa + (size_t)t0 * kDomTile32, left);
-        rsd = buffer_rsrc(dsd + (size_t)t0 * kDomTile32, left);
-        gload(bl0, sa0, sd0, 0);
+        const long dl = (long)(nalloc - t0) * kDomTile32;
+        rfrag = buffer_rsrc(dsc.bfrag + (size_t)t0 * KS * 64, uniform((int)min(dl / kDomTile32 * KS * 1024, (long)INT32_MAX)));
+        rsa = buffer_rsrc(dsa + (size_t)t0 * kDomTile32, uniform((int)min(dl * 4, (long)INT32_MAX)));
+        rsd = buffer_rsrc(dsd + (size_t)t0 * kDomTile32, uniform((int)min(dl * 4, (long)INT32_MAX)));
+        rsx = buffer_rsrc(dsx + (size_t)t0 * kDomTile32, uniform((int)min(dl * 8, (long)INT32_MAX)));
+        gload(bl0, sa0, sd0, sx0, 0);
         // the direct-to-LDS loads count on vmcnt only: every wave drains its
         // own before the barrier that publishes the stage
         __builtin_amdgcn_s_waitcnt(0);
@@ -431,9 +462,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             uint4 *const Bs = buf ? bl1 : bl0;
             const float *const As = buf ? sa1 : sa0;
             const float *const Ds = buf ? sd1 : sd0;
+            const uint2 *const Xs = (const uint2 *)(buf ? sx1 : sx0);
             if (stg + 1 < nstage) {
-                if constexpr (buf) gload(bl0, sa0, sd0, stg + 1);
-                else gload(bl1, sa1, sd1, stg + 1);
+                if constexpr (buf) gload(bl0, sa0, sd0, sx0, stg + 1);
+                else gload(bl1, sa1, sd1, sx1, stg + 1);
             }
             // the range bests of other workgroups: issued after the stage
             // prefetch (so its wait does not include them), applied at the end
@@ -446,65 +478,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             if (wave_on) {
                 const int tbase = t0 + stg * DT;
                 f16x acc[2][RQ];
-                h8 bq[2][KG];
-                // the per-domain values are read one tile ahead of their test,
-                // so the test never waits for LDS
-                float sq_n = NORM ? 0.f : As[lane & 31], sd_n = CEN ? 0.f : Ds[lane & 31];
-                if constexpr (PREF) read_tile(bq[0], Bs, 0, 0);
+                h8 bq[NSET][KG];
+                float mt[G][RQ];   // normalised form: the tile maxima of the current group
+                // the per-domain values are read two tiles ahead of their test
+                // (a ring of two), so the test never waits for LDS
+                float sqv[2] = {0.f, 0.f}, sdv[2];
+                sqv[0] = NORM ? 0.f : As[lane & 31];
+                sdv[0] = CEN ? 0.f : Ds[lane & 31];
+                if (!NORM && DT > 1) {
+                    sqv[1] = As[kDomTile32 + (lane & 31)];
+                    sdv[1] = CEN ? 0.f : Ds[kDomTile32 + (lane & 31)];
+                }
+                if constexpr (PREF) {
+#pragma unroll
+                    for (int j = 0; j < NSET - 1; ++j)
+                        if (j < DT) read_tile(bq[j], Bs, j, 0);
+                }
                 mfma_tile(acc[0], Bs, 0, bq[0]);
-                if (PREF && DT > 1) read_tile(bq[1], Bs, 1, 0);
+                if (PREF && NSET - 1 < DT) read_tile(bq[NSET - 1], Bs, NSET - 1, 0);
 #pragma unroll
                 for (int dt = 0; dt < DT; ++dt) {
                     const int cur = dt & 1;
                     const int col = dt * kDomTile32 + (lane & 31);
-                    const float sqa = sq_n, sd4f = sd_n;
+                    const float sqa = sqv[cur], sd4f = sdv[cur];
                     if (dt + 1 < DT) {
-                        if constexpr (!NORM) sq_n = As[col + kDomTile32];
-                        if constexpr (!CEN) sd_n = Ds[col + kDomTile32];
-                        mfma_tile(acc[cur ^ 1], Bs, dt + 1, bq[(dt + 1) & 1]);
+                        mfma_tile(acc[cur ^ 1], Bs, dt + 1, bq[(dt + 1) % NSET]);
                         // the set of tile dt is free once tile dt's MFMAs were issued
-                        if (PREF && dt + 2 < DT) read_tile(bq[dt & 1], Bs, dt + 2, 0);
+                        if (PREF && dt + NSET < DT) read_tile(bq[dt % NSET], Bs, dt + NSET, 0);
+                        // keep the read here: the scheduler would otherwise sink it
+                        // towards its use and expose the LDS latency
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    bool pass[RQ][2];
-                    float mx[RQ][2];
-                    bool any = false;
-                    if constexpr (NORM) {
-                        // the threshold is in the accumulators: the largest of the
-                        // lane's 16 values (both ranges, 8 isometries) against 0;
-                        // false on NaN (a column past the pool)
-#pragma unroll
-                        for (int qi = 0; qi < RQ; ++qi) {
-                            const f16x &a = acc[cur][qi];
-                            const float m = FIC_MAX3(FIC_MAX3(max8f(a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7]),
-                                                              a[8], a[9]),
-                                                     FIC_MAX3(a[10], a[11], a[12]), FIC_MAX3(a[13], a[14], a[15]));
-                            pass[qi][0] = pass[qi][1] = m > 0.f;
-                            any |= pass[qi][0];
-                        }
-                    } else {
-#pragma unroll
-                        for (int qi = 0; qi < RQ; ++qi)
-#pragma unroll
-                            for (int u = 0; u < 2; ++u) {
-                                const f16x &a = acc[cur][qi];
-                                const int o = 8 * u;
-                                mx[qi][u] = max8f(a[o], a[o + 1], a[o + 2], a[o + 3], a[o + 4], a[o + 5], a[o + 6], a[o + 7]);
-                                const float rhs = CEN ? fmaf(tn[qi][u], sqa, -cmargin)
-                                                      : fmaf(tn[qi][u], sqa, fmaf(-bn[qi][u], sd4f, -an[qi][u]));
-                                // false on NaN: rows past the ranges, domains past the
-                                // pool, and ranges already at val 0
-                                pass[qi][u] = mx[qi][u] > rhs;
-                                any |= pass[qi][u];
-                            }
+                    if (!NORM && dt + 2 < DT) {
+                        sqv[cur] = As[col + 2 * kDomTile32];
+                        if constexpr (!CEN) sdv[cur] = Ds[col + 2 * kDomTile32];
                     }
-                    if (__builtin_amdgcn_ballot_w64(any)) {  // rare: exact evaluation, then share the best
-                        const int p = tbase * kDomTile32 + col;
+                    // the exact evaluation of tile dtj for the lanes in ps (mx: the
+                    // isometry maxima of the exact cross terms, the centred form only),
+                    // then the range bests shared with the other lanes and walks
+                    auto exact_tile = [&](const int dtj, bool (&ps)[RQ][2], float (&mx)[RQ][2], float sd4f) {
+                        const int colj = dtj * kDomTile32 + (lane & 31);
+                        const int p = tbase * kDomTile32 + colj;
                         // a passing pair has a finite sqrt(A): p is a pool domain
-                        const int64_t sd4 = (int64_t)(CEN ? dsd_g[p] : sd4f);   // Sd4 < 2^24: exact in float
+                        int64_t Ad = 0, sd4 = (int64_t)sd4f;   // Sd4 < 2^24: exact in float
                         if constexpr (NORM) {
+                            const uint64_t xv = dsx_g[p];
+                            Ad = (uint32_t)xv;
+                            sd4 = (int64_t)(xv >> 32);
+                        } else if constexpr (CEN) {
+                            const uint2 xi = Xs[colj];
+                            Ad = xi.x;
+                            sd4 = xi.y;
+                        }
+                        if constexpr (NORM) {
+                            const float sqx = dsa_g[p];
                             // the exact cross terms of the tile (every lane: the MFMA is
                             // wave-wide), from the exact copy of its fragment
-                            const h8 bx = bfx[(size_t)(tbase + dt) * 64 + lane];
+                            const h8 bx = bfx[(size_t)(tbase + dtj) * 64 + lane];
 #pragma unroll
                             for (int qi = 0; qi < RQ; ++qi) {
                                 const f16x ex = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[qi][0], bx, f16x{0.f}, 0, 0, 0);
@@ -513,7 +543,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                     const int o = 8 * u;
                                     mx[qi][u] = max8f(ex[o], ex[o + 1], ex[o + 2], ex[o + 3], ex[o + 4], ex[o + 5],
                                                       ex[o + 6], ex[o + 7]);
-                                    pass[qi][u] = pass[qi][u] && rr[qi][u] >= 0;
+                                    // the centred test on the exact cross term: the normalised
+                                    // one passes a few more pairs
+                                    ps[qi][u] = ps[qi][u] && rr[qi][u] >= 0 && mx[qi][u] > fmaf(tn[qi][u], sqx, -cmargin);
                                 }
                             }
                         }
@@ -522,21 +554,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 #pragma unroll
                             for (int u = 0; u < 2; ++u) {
                                 bool imp = false;
-                                if (NORM && pass[qi][u]) {
-                                    // the centred test on the exact cross term first: the
-                                    // normalised one passes a few more pairs
-                                    pass[qi][u] = mx[qi][u] > fmaf(tn[qi][u], dsa_g[p], -cmargin);
-                                }
-                                if (pass[qi][u]) {
-                                    const int64_t A = pa[p];
-                                    if (CEN) {
-                                        const int64_t er = (int64_t)sr[qi][u] - (int64_t)n * round_mean(sr[qi][u], n);
-                                        const int64_t ed = sd4 - (int64_t)n * round_mean(sd4, n);
-                                        imp = confirm_bx((int64_t)n * (int64_t)mx[qi][u] - er * ed, p, A, cr[qi][u], sl,
-                                                         sc, best[qi][u], bp[qi][u], bk[qi][u]);
+                                if (ps[qi][u]) {
+                                    if constexpr (CEN) {
+                                        // e_d = Sd4 - n round(Sd4 / n), n a power of two
+                                        const int ed = (int)sd4 - (((int)sd4 + n / 2) >> lgn << lgn);
+                                        imp = confirm_bx((int64_t)n * (int64_t)mx[qi][u] - (int64_t)er[qi][u] * ed, p, Ad,
+                                                         cr[qi][u], sl, sc, best[qi][u], bp[qi][u], bk[qi][u]);
                                     } else {
-                                        imp = confirm_pair((int)mx[qi][u], p, sd4, A, sr[qi][u], cr[qi][u], n, sl, sc,
-                                                           best[qi][u], bp[qi][u], bk[qi][u]);
+                                        imp = confirm_pair((int)mx[qi][u], p, sd4, pa[p], sr[qi][u], cr[qi][u], n, sl,
+                                                           sc, best[qi][u], bp[qi][u], bk[qi][u]);
                                     }
                                 }
                                 // only a lane best that tightens the shared one is worth sharing
@@ -554,6 +580,79 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                     if constexpr (NORM) build_cth(qi);   // uniform: inside a ballot
                                 }
                             }
+                    };
+                    if constexpr (NORM) {
+                        // the threshold is in the accumulators: the largest of the
+                        // lane's 16 values (both ranges, 8 isometries) against 0, one
+                        // branch per group of G tiles (false on NaN: a column past the
+                        // pool)
+#pragma unroll
+                        for (int qi = 0; qi < RQ; ++qi) {
+                            const f16x &a = acc[cur][qi];
+                            mt[dt % G][qi] = FIC_MAX3(FIC_MAX3(max8f(a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7]),
+                                                               a[8], a[9]),
+                                                      FIC_MAX3(a[10], a[11], a[12]), FIC_MAX3(a[13], a[14], a[15]));
+                        }
+                        if (dt % G == G - 1 || dt == DT - 1) {
+                            const int g0 = dt - dt % G;
+                            bool any = false;
+#pragma unroll
+                            for (int qi = 0; qi < RQ; ++qi) {
+                                // fmaxf drops NaN: a tile past the pool must not hide the others
+                                float gm = mt[0][qi];
+#pragma unroll
+                                for (int j = 1; j <= dt - g0; ++j) gm = fmaxf(gm, mt[j][qi]);
+                                any |= gm > 0.f;
+                            }
+                            if (__builtin_expect(__builtin_amdgcn_ballot_w64(any) != 0, 0)) {  // rare
+                                // the passing tiles of the group in order, one at a time
+                                // (a loop, not unrolled: one copy of the evaluation)
+                                uint32_t pl[RQ], gmask = 0;
+#pragma unroll
+                                for (int qi = 0; qi < RQ; ++qi) pl[qi] = 0;
+#pragma unroll
+                                for (int j = 0; j <= dt - g0; ++j) {
+                                    bool anyj = false;
+#pragma unroll
+                                    for (int qi = 0; qi < RQ; ++qi) {
+                                        const bool b = mt[j][qi] > 0.f;
+                                        pl[qi] |= b ? 1u << j : 0u;
+                                        anyj |= b;
+                                    }
+                                    gmask |= __builtin_amdgcn_ballot_w64(anyj) ? 1u << j : 0u;
+                                }
+                                gmask = __builtin_amdgcn_readfirstlane(gmask);
+                                while (gmask) {
+                                    const int j = __builtin_ctz(gmask);
+                                    gmask &= gmask - 1;
+                                    bool ps[RQ][2];
+                                    float mx[RQ][2];
+#pragma unroll
+                                    for (int qi = 0; qi < RQ; ++qi) ps[qi][0] = ps[qi][1] = (pl[qi] >> j) & 1u;
+                                    exact_tile(g0 + j, ps, mx, 0.f);
+                                }
+                            }
+                        }
+                    } else {
+                        bool ps[RQ][2];
+                        float mx[RQ][2];
+                        bool any = false;
+#pragma unroll
+                        for (int qi = 0; qi < RQ; ++qi)
+#pragma unroll
+                            for (int u = 0; u < 2; ++u) {
+                                const f16x &a = acc[cur][qi];
+                                const int o = 8 * u;
+                                mx[qi][u] = max8f(a[o], a[o + 1], a[o + 2], a[o + 3], a[o + 4], a[o + 5], a[o + 6], a[o + 7]);
+                                const float rhs = CEN ? fmaf(tn[qi][u], sqa, -cmargin)
+                                                      : fmaf(tn[qi][u], sqa, fmaf(-bn[qi][u], sd4f, -an[qi][u]));
+                                // false on NaN: rows past the ranges, domains past the
+                                // pool, and ranges already at val 0
+                                ps[qi][u] = mx[qi][u] > rhs;
+                                any |= ps[qi][u];
+                            }
+                        if (__builtin_expect(__builtin_amdgcn_ballot_w64(any) != 0, 0))   // rare
+                            exact_tile(dt, ps, mx, sd4f);
                     }
                 }
             }
@@ -636,8 +735,8 @@ hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st) {
     if (B == 2) {
         FIC_F16(1, 1, 8, 3);
     } else if (B == 4) {
-        FIC_F16(1, 1, 8, 3);
         FIC_F16(1, 1, 16, 3);
+        FIC_F16(1, 1, 8, 3);
         FIC_F16(1, 2, 8, 2);
         FIC_F16(1, 1, 4, 3);
     } else if (B == 8) {
