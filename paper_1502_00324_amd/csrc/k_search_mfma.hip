@@ -131,8 +131,9 @@ TileShape mfma_pick(int B, bool f16, int choice) {
 // its XCD with one running best over them (about a quarter of the XCD's
 // chunks, and enough to keep the partial results, one per range and slot,
 // under 256 MB).  tile_kib is the fragment size of one domain tile in KiB.
-// Partial-result slots per XCD and range group: measured best at 16 for
-// B = 32, 4 otherwise (FIC_SLOTS_PER_XCD overrides both).
+// Partial-result slots per XCD and range group: measured best at 64 for
+// B = 32 (a walk of two or three chunks, which the concurrent workgroups of
+// an XCD share in its L2), 4 otherwise (FIC_SLOTS_PER_XCD overrides both).
 static int slots_per_xcd(int dflt) {
     const char *e = getenv("FIC_SLOTS_PER_XCD");
     const int v = e ? atoi(e) : 0;
@@ -182,7 +183,7 @@ MfmaGeom mfma_geometry(int B, int range_cap, int pool_cap, const TileShape &sh) 
     g.kt = sh.pl == 2 ? 2 * g.ka : g.ka;
     g.rpw = 16 * sh.rq;
     const int ntiles = (pool_cap + kDomTile - 1) / kDomTile;
-    split_chunks(g, range_cap, ntiles, g.kt, sh.dt, true, B == 32 ? 16 : 4);
+    split_chunks(g, range_cap, ntiles, g.kt, sh.dt, true, B == 32 ? 64 : 4);
     return g;
 }
 
@@ -427,6 +428,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     __shared__ float sa0[NDL], sa1[NDL], sd0[NDL], sd1[NDL];   // sqrt(A) rounded down, Sd4
     __shared__ SLds sl;
     __shared__ int s_item;
+    __shared__ float warm[256];   // the L2 warm-up's destination, never read
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
     const SConst sc = make_sconst(ss);
@@ -645,6 +647,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                         uniform((int)min((long)(nalloc - t0) * KB * 1024, (long)INT32_MAX)));
     rsa = buffer_rsrc(dsa + (size_t)t0 * kDomTile, left);
     rsd = buffer_rsrc(dsd + (size_t)t0 * kDomTile, left);
+    l2_warm(rfrag, (t1 - t0) * KB * 1024, rg % (int)(gridDim.x / 8), (int)(gridDim.x / 8), warm, wv, tid);
     gload(bl0, sa0, sd0, 0);
     // the direct-to-LDS loads count on vmcnt only: every wave drains its own
     // before the barrier that publishes the stage
