@@ -269,7 +269,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     __shared__ uint4 sx0[CEN ? NX : 1], sx1[CEN ? NX : 1];      // exact (A, Sd4) (centred only)
     __shared__ SLds sl;
     __shared__ int s_item;
-    __shared__ float warm[256];   // the L2 warm-up's destination, never read
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
     const SConst sc = make_sconst(ss);
@@ -452,7 +451,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         rsa = buffer_rsrc(dsa + (size_t)t0 * kDomTile32, uniform((int)min(dl * 4, (long)INT32_MAX)));
         rsd = buffer_rsrc(dsd + (size_t)t0 * kDomTile32, uniform((int)min(dl * 4, (long)INT32_MAX)));
         rsx = buffer_rsrc(dsx + (size_t)t0 * kDomTile32, uniform((int)min(dl * 8, (long)INT32_MAX)));
-        l2_warm(rfrag, (t1 - t0) * KS * 1024, rg % (int)(gridDim.x / 8), (int)(gridDim.x / 8), warm, wv, tid);
         gload(bl0, sa0, sd0, sx0, 0);
         // the direct-to-LDS loads count on vmcnt only: every wave drains its
         // own before the barrier that publishes the stage

@@ -428,7 +428,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     __shared__ float sa0[NDL], sa1[NDL], sd0[NDL], sd1[NDL];   // sqrt(A) rounded down, Sd4
     __shared__ SLds sl;
     __shared__ int s_item;
-    __shared__ float warm[256];   // the L2 warm-up's destination, never read
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
     const SConst sc = make_sconst(ss);
@@ -647,7 +646,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                         uniform((int)min((long)(nalloc - t0) * KB * 1024, (long)INT32_MAX)));
     rsa = buffer_rsrc(dsa + (size_t)t0 * kDomTile, left);
     rsd = buffer_rsrc(dsd + (size_t)t0 * kDomTile, left);
-    l2_warm(rfrag, (t1 - t0) * KB * 1024, rg % (int)(gridDim.x / 8), (int)(gridDim.x / 8), warm, wv, tid);
     gload(bl0, sa0, sd0, 0);
     // the direct-to-LDS loads count on vmcnt only: every wave drains its own
     // before the barrier that publishes the stage

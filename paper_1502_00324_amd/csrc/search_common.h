@@ -57,25 +57,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const T *p, int by
     return __builtin_amdgcn_make_buffer_rsrc((void *)uniform(p), 0, bytes, 0x00020000);
 }
 
-// L2 warm-up of a chunk of domain fragments: the workgroups of one XCD walk
-// the same chunk at about the same time, so without it each new stage would
-// miss in L2 for all of them at once.  Workgroup `share` of `nshare` touches
-// one dword per 128-byte line of its part of [0, bytes) through a direct-to-
-// LDS load into `dummy` (64 dwords per wave, never read): the loads count on
-// vmcnt like the stage loads, so the first stage wait also covers them, and
-// the later stages find the chunk in L2.
-__device__ __forceinline__ void l2_warm(__amdgpu_buffer_rsrc_t r, int bytes, int share, int nshare, float *dummy,
-                                        int wv, int tid) {
-    typedef __attribute__((address_space(3))) void *lds_t;
-    const int lines = (bytes + 127) >> 7;
-    const int per = (lines + nshare - 1) / nshare;
-    const int lo = uniform(share * per), hi = uniform(min(lines, lo + per));
-    for (int l0 = lo; l0 < hi; l0 += 256)   // uniform bounds: every wave runs the same trips
-        if (l0 + tid < hi)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_t)(dummy + 64 * wv), 4, (unsigned)(l0 + tid) << 7, 0, 0,
-                                                     0);
-}
-
 __device__ inline bool lex_less_vp(int64_t va, int pa, int64_t vb, int pb) {
     return va < vb || (va == vb && pa < pb);
 }
