@@ -260,6 +260,7 @@ struct ImgIn {
     fic_level_codes *codes;     // NULL for a pool-only plan
     uint32_t *children;
     int32_t *nchildren;
+    int pool_expect;            // > 0: the pool size to plan chunks for (else from the candidates)
 };
 
 struct LevelPlan {
@@ -387,7 +388,7 @@ bool plan_level(LevelPlan &pl, const std::vector<ImgIn> &in, bool do_search, int
                 // chunks are counted for the pool size the percentile and the cap
                 // leave (the capacity may hold every candidate); the kernels split
                 // the actual pool evenly over them
-                long long pexp = d.nd - d.c;
+                long long pexp = x.pool_expect > 0 ? x.pool_expect : d.nd - d.c;
                 if (d.pool_max > 0) pexp = min(pexp, (long long)d.pool_max);
                 pexp = max(1LL, min(pexp, (long long)d.pool_cap));
                 d.geo = f16 ? f16_geometry(d.B, d.range_cap, (int)pexp, pl.bh.shape)
@@ -1132,10 +1133,11 @@ int fic_encode_level(fic_ctx *ctx, const fic_image *img, const fic_pool *pool, c
     if (out->capacity < range_capacity) return FIC_E_CAPACITY;
     int st = enter(ctx);
     if (st != FIC_OK) return st;
-    // the search needs no pool scratch: the coarsest step keeps the unused key buffer small
+    // the search needs no pool scratch: the coarsest step keeps the unused key
+    // buffer small, and the chunks are planned for the caller's pool capacity
     std::vector<ImgIn> in(1);
     in[0] = ImgIn{img, B, B, 0, 1, 0, const_cast<fic_pool *>(pool), ranges_xy, n_ranges, range_capacity, out,
-                  children_xy, n_children};
+                  children_xy, n_children, pool->capacity};
     std::vector<LevelPlan> plans(1);
     if (!plan_level(plans[0], in, true, engine, 0, true, FIC_POOL_ENTROPY, ctx->tune)) return FIC_E_NOMEM;
     plans[0].bh.ss = make_sset(s_num, s_count, s_den);
