@@ -237,7 +237,10 @@ __device__ __forceinline__ void k_f16_bfrag(const BatchDev &b, const int bid) {
 // with centring, the exact (A, Sd4) of the exact evaluation (without it, Sd4
 // for the test), so a passing pair is evaluated from LDS and registers: a
 // global load there would also wait for the stage prefetch, the vector
-// memory counter being in order.  A chunk's last stage may read up to
+// memory counter being in order.  The normalised form (B <= 4) stages
+// fragments only: its test needs no per-domain value, and its rare exact
+// evaluation reads the exact tile and the domain's values from global
+// memory (staging them measured slower).  A chunk's last stage may read up to
 // DT - 1 tiles past its end: the next chunk's domains (evaluated twice,
 // harmless: the partials merge by (val, domain)) or the zero padding tiles,
 // whose NaN sqrt(A) never passes.  The MFMAs of tile t+1 are issued before
