@@ -574,7 +574,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                 if (__builtin_amdgcn_ballot_w64(imp)) {
                                     // the 32 lanes holding this range share their best: a
                                     // pair is only rejected when it cannot even tie it
-                                    const int64_t gb = group_min_val<32>(best[qi][u]);
+                                    const int64_t gb = group_min_val_wave<32>(best[qi][u]);
                                     if (rr[qi][u] >= 0 && gb <= tb[qi][u]) {
                                         tb[qi][u] = gb;
                                         tn[qi][u] = tn_from(gb, cr[qi][u], sc, tfac);

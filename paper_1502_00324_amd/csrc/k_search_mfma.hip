@@ -765,7 +765,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                             // the 16 lanes holding this range share their best: the
                             // threshold may use it because a pair is only rejected
                             // when it cannot even tie it
-                            const int64_t gb = group_min_val<16>(best[qi]);
+                            const int64_t gb = group_min_val_wave<16>(best[qi]);
                             if (rr[qi] >= 0 && gb <= tb[qi]) {
                                 tb[qi] = gb;
                                 tn[qi] = tn_from(gb, cr[qi], sc, tfac);

@@ -88,13 +88,22 @@ __device__ inline float sqrt_down(double v) {
     return f;
 }
 
-// Contrast numerators in LDS, so lanes may index them independently.
+// Contrast numerators in LDS, so lanes may index them independently, and
+// the line through the first and last of them (num_j ~ num_0 + j d), from
+// which the exact search below takes its starting index.
 struct SLds {
     int32_t num[kMaxS];
+    float g_c0, g_inv;   // 2 num_0 + d and 1 / (2 d) (0 for a single value)
 };
 
 __device__ inline void load_sset(SLds &dst, const SSet &ss) {
     if (threadIdx.x < kMaxS) dst.num[threadIdx.x] = ss.num[threadIdx.x];
+    if (threadIdx.x == 0) {
+        const int c = ss.count;   // numerators strictly ascending: d > 0 when c > 1
+        const float d = c > 1 ? (float)(ss.num[c - 1] - ss.num[0]) / (float)(c - 1) : 0.f;
+        dst.g_c0 = 2.f * (float)ss.num[0] + d;
+        dst.g_inv = c > 1 ? 0.5f / d : 0.f;
+    }
 }
 
 // Uniform constants of the contrast set, built once per workgroup from the
@@ -124,19 +133,35 @@ __device__ __forceinline__ bool confirm_bx(int64_t bx, int p, int64_t A, int64_t
     const int64_t den = sc.den;
     const int64_t lhs = 8 * den * bx;
     // midpoint rule: s_{j+1} beats s_j iff 8 den Bx > A (num_j + num_{j+1}); the
-    // predicate is monotone (true, then false) in j, so k* = the first false j
-    int lo = 0, hi = sc.count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (lhs > A * (int64_t)(ss.num[mid] + ss.num[mid + 1])) lo = mid + 1;
-        else hi = mid;
+    // predicate is monotone (true, then false) in j, so k* = the first false j.
+    // Start where the line through the end numerators puts q = 8 den Bx / A
+    // (num_j + num_{j+1} ~ 2 num_0 + (2j + 1) d), then step to k* with the
+    // exact predicate: the walk ends at k* from any start, and for an evenly
+    // spaced set the start is k* or next to it, so the three table reads
+    // below are usually all there is (no dependent chain of reads).  A = 0
+    // gives an infinite or NaN q, which the clamp turns into an end index.
+    const int last = sc.count - 1;
+    const float lf = fmaf((float)(int32_t)(lhs >> 32), 4294967296.0f, (float)(uint32_t)lhs);
+    const float af = fmaf((float)(int32_t)(A >> 32), 4294967296.0f, (float)(uint32_t)A);
+    const float t = (lf * __builtin_amdgcn_rcpf(af) - ss.g_c0) * ss.g_inv;
+    int k = (int)ceilf(fminf(fmaxf(t, 0.f), (float)last));   // fmaxf drops NaN
+    int64_t nb = ss.num[max(k - 1, 0)], nk = ss.num[k], na = ss.num[min(k + 1, last)];
+    while (k > 0 && !(lhs > A * (nb + nk))) {   // s_{k-1} is not beaten by s_k
+        --k;
+        na = nk;
+        nk = nb;
+        nb = ss.num[max(k - 1, 0)];
     }
-    const int64_t nk = ss.num[lo];
+    while (k < last && lhs > A * (nk + na)) {   // s_{k+1} beats s_k
+        ++k;
+        nk = na;
+        na = ss.num[min(k + 1, last)];
+    }
     const int64_t val = nk * nk * A - 8 * nk * den * bx + sc.scale * cr;
     if (val < best) {
         best = val;
         bp = p;
-        bk = lo;
+        bk = k;
         return true;
     }
     return false;
@@ -202,6 +227,37 @@ template <int WIDTH>
 __device__ inline int64_t group_min_val(int64_t v) {
 #pragma unroll
     for (int off = WIDTH / 2; off > 0; off >>= 1) v = min(v, (int64_t)__shfl_xor(v, off, 64));
+    return v;
+}
+
+// v of another lane of the same 16-lane row by a DPP row permutation (a lane
+// whose source is inactive keeps its own value)
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp64(int64_t v) {
+    const int lo = (int)(uint32_t)v, hi = (int)(v >> 32);
+    const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    return (int64_t)(((uint64_t)h << 32) | l);
+}
+
+// The minimum over aligned groups of 16 or 32 lanes, in every lane of the
+// group, without the LDS crossbar: quad swaps, the mirrors within 8 and 16
+// lanes, and for 32 the exchange of rows 0 and 1 (2 and 3).  For a wave whose
+// lanes are all active.
+template <int WIDTH>
+__device__ inline int64_t group_min_val_wave(int64_t v) {
+    static_assert(WIDTH == 16 || WIDTH == 32, "16- or 32-lane groups");
+    v = min(v, dpp64<0xB1>(v));    // quad_perm [1, 0, 3, 2]: lane ^ 1
+    v = min(v, dpp64<0x4E>(v));    // quad_perm [2, 3, 0, 1]: lane ^ 2
+    v = min(v, dpp64<0x141>(v));   // row_half_mirror: 7 - i within 8
+    v = min(v, dpp64<0x140>(v));   // row_mirror: 15 - i within 16
+    if constexpr (WIDTH == 32) {
+        // both results of the swap: row r and row r ^ 1 at the same lane
+        const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        v = min((int64_t)(((uint64_t)h[0] << 32) | l[0]), (int64_t)(((uint64_t)h[1] << 32) | l[1]));
+    }
     return v;
 }
 
