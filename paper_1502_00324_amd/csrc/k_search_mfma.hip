@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     const float tfac = tn_factor(n);
     const int32_t *np = dsc.pcount;
     // R: the length of the search list (constant ranges are coded already)
-    const int R = min(*dsc.ns, range_cap), P = min(*np, pool_cap);
+    const int R = uniform(min(*dsc.ns, range_cap)), P = uniform(min(*np, pool_cap));
     int rg, cfirst, cstep, ncs, slot;
     item_walk(geo, R, xcd, k, rg, cfirst, cstep, ncs, slot);
     const gptr<int32_t> sidx = as_global(dsc.sidx);
@@ -816,8 +816,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         __syncthreads();
         const int idx = __builtin_amdgcn_readfirstlane(s_item);
         if (idx >= total) break;   // uniform: every wave leaves
-        const int im = find_img(qpre, bt.n, idx);
-        run_item(im, idx - qpre[im]);
+        const int im = uniform(find_img(qpre, bt.n, idx));
+        run_item(im, uniform(idx - qpre[im]));
     }
 }
 
