@@ -60,7 +60,7 @@ __host__ __device__ inline bool f16_normalised(int B) { return B <= 4; }
 struct F16Shape { int B, rq, dt, wpe; };
 static const F16Shape kF16Shapes[] = {
     {2, 1, 8, 3},
-    {4, 1, 16, 3}, {4, 1, 8, 3}, {4, 2, 8, 2}, {4, 1, 4, 3},
+    {4, 1, 16, 4}, {4, 1, 16, 3}, {4, 1, 8, 3}, {4, 2, 8, 2}, {4, 1, 4, 3}, {4, 1, 8, 4},
     {8, 2, 4, 2}, {8, 1, 4, 3}, {8, 1, 8, 2}, {8, 2, 2, 2},
     {16, 1, 1, 3}, {16, 1, 2, 2},
 };
@@ -285,25 +285,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   auto run_item = [&](const int im, const int k) {
     const ImgLvl &dsc = bt.d[im];
     const MfmaGeom geo = dsc.geo;
-    const gptr<h8> afrag = as_global((const h8 *)dsc.afrag);
-    RInfo *__restrict__ ri = dsc.ri;
-    const gptr<int64_t> pa = as_global(dsc.pa);
-    Partial *__restrict__ part = dsc.part;
-    const int range_cap = dsc.range_cap, pool_cap = dsc.pool_cap, n = dsc.B * dsc.B;
+    // the level's pointers and sizes in scalar registers (alike in every lane)
+    const gptr<h8> afrag = as_global((const h8 *)uniform(dsc.afrag));
+    RInfo *__restrict__ ri = uniform(dsc.ri);
+    const gptr<int64_t> pa = as_global((const int64_t *)uniform(dsc.pa));
+    Partial *__restrict__ part = uniform(dsc.part);
+    const int range_cap = uniform(dsc.range_cap), pool_cap = uniform(dsc.pool_cap), n = uniform(dsc.B * dsc.B);
     const int nalloc = f16_tiles(pool_cap);
-    const float *dsd = (const float *)dsc.dinfo, *dsa = dsd + (size_t)nalloc * kDomTile32;
+    const float *dsd = (const float *)uniform(dsc.dinfo), *dsa = dsd + (size_t)nalloc * kDomTile32;
     const uint2 *dsx = (const uint2 *)(dsa + (size_t)nalloc * kDomTile32);
     const gptr<float> dsa_g = as_global(dsa);
     const gptr<uint64_t> dsx_g = as_global((const uint64_t *)dsx);   // (A, Sd4): low, high word
     // the exact copy of the tiles (normalised form), after the searched ones
-    const gptr<h8> bfx = as_global((const h8 *)(dsc.bfrag + (size_t)nalloc * KS * 64));
+    const gptr<h8> bfx = as_global((const h8 *)(uniform(dsc.bfrag) + (size_t)nalloc * KS * 64));
     const float tfac = tn_factor(n);
     const float cmargin = (float)(n / 2 + 4);   // centred test: n/4 centring + n/4 + 4 float margin
     // R: the length of the search list (constant ranges are coded already)
     const int R = uniform(min(*dsc.ns, range_cap)), P = uniform(min(*dsc.pcount, pool_cap));
     int rg, cfirst, cstep, ncs, slot;
     item_walk(geo, R, xcd, k, rg, cfirst, cstep, ncs, slot);
-    const gptr<int32_t> sidx = as_global(dsc.sidx);
+    const gptr<int32_t> sidx = as_global((const int32_t *)uniform(dsc.sidx));
     const int ntiles = (P + kDomTile32 - 1) / kDomTile32;
     const int q0 = (rg * 4 + wave) * RQ;
     const bool wave_on = q0 * 4 < R;
@@ -413,12 +414,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // With up to 4 K-steps a tile's fragments are read into registers ahead
     // of its MFMAs, NSET sets in rotation: the read of tile t + NSET is issued
     // right after the MFMAs of tile t + 1, so it has NSET - 1 prune tests to
-    // land before its own MFMAs (three sets where the registers allow).
+    // land before its own MFMAs (three sets where the registers allow; at
+    // four waves per SIMD two, the other waves covering the wait).
     // Longer tiles read them in groups of 8, so one LDS wait covers a group
     // rather than every MFMA.
     constexpr bool PREF = KS <= 4;
     constexpr int KG = PREF ? KS : 8;
-    constexpr int NSET = PREF && (KS == 1 || WPE <= 2) ? 3 : 2;
+    constexpr int NSET = PREF && ((KS == 1 && WPE <= 3) || WPE <= 2) ? 3 : 2;
     auto read_tile = [&](h8 (&bf)[KG], const uint4 *Bs, int dt, int s0) {
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
@@ -742,6 +744,8 @@ hipError_t launch_f16_search_b(const BatchHost &b, hipStream_t st) {
         FIC_F16(1, 1, 8, 3);
         FIC_F16(1, 2, 8, 2);
         FIC_F16(1, 1, 4, 3);
+        FIC_F16(1, 1, 16, 4);
+        FIC_F16(1, 1, 8, 4);
     } else if (B == 8) {
         FIC_F16(4, 2, 4, 2);
         FIC_F16(4, 1, 4, 3);

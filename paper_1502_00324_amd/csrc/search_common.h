@@ -43,11 +43,11 @@ __device__ __forceinline__ float2 ldg(gptr<float2> p, size_t i) {
 // instructions require (else the compiler loops over the lanes' values).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 template <class T>
-__device__ __forceinline__ const T *uniform(const T *p) {
+__device__ __forceinline__ T *uniform(T *p) {
     const uint64_t v = (uint64_t)p;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (const T *)(((uint64_t)hi << 32) | lo);
+    return (T *)(((uint64_t)hi << 32) | lo);
 }
 
 // Raw buffer resource over `bytes` bytes at p (p and bytes alike in every
