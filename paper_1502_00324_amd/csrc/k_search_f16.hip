@@ -272,6 +272,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     __shared__ uint4 sx0[CEN ? NX : 1], sx1[CEN ? NX : 1];      // exact (A, Sd4) (centred only)
     __shared__ SLds sl;
     __shared__ int s_item;
+    // per range (4 waves x RQ quads x 4 ranges): values only the rare paths
+    // read (Cr, the best value the threshold reflects, the centring error e_r,
+    // the normalised margin), kept in LDS rather than in registers the tile
+    // loop needs
+    struct RangeLds { int64_t cr, tb; int er; float marg; };
+    __shared__ RangeLds s_rng[4 * RQ * 4];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
     const SConst sc = make_sconst(ss);
@@ -316,9 +322,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // normalised form: the accumulator input of every tile, -(threshold) of
     // the lane's two ranges (values 0..7 and 8..15), and its error margin
     f16x cth[NORM ? RQ : 1];
-    float marg[RQ][2];
-    int64_t best[RQ][2], cr[RQ][2], tb[RQ][2];  // tb: the best value tn reflects
-    int bp[RQ][2], bk[RQ][2], rr[RQ][2], sr[RQ][2], er[RQ][2];
+    int64_t best[RQ][2];
+    int bp[RQ][2], bk[RQ][2], rr[RQ][2], sr[RQ][2];
+    const auto rng = [&](int qi, int u) -> RangeLds & { return s_rng[((wave * RQ + qi) * 2 + hh) * 2 + u]; };
     const int lgn = __builtin_ctz(n);   // n = B^2, B a power of two
     // The normalised test: acc' = sum (r - m_r) 2^16 (D4 - Sd4/n)/sqrt(A) + c is
     // 2^16 Bx/(n sqrt A) + c up to the range's margin, and a pair can reach
@@ -332,7 +338,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             const float t = tn[qi][u];
             const float c = (rr[qi][u] < 0 || __builtin_isnan(t)) ? -__builtin_inff()
                           : t < -1e29f ? 1e30f
-                                       : marg[qi][u] - 65536.0f * t * (1.0f - 1.0f / 1048576.0f);
+                                       : rng(qi, u).marg - 65536.0f * t * (1.0f - 1.0f / 1048576.0f);
 #pragma unroll
             for (int e = 0; e < 8; ++e) cth[NORM ? qi : 0][8 * u + e] = c;
         }
@@ -350,15 +356,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             bn[qi][u] = x.bn;
             an[qi][u] = x.an;
             sr[qi][u] = (int)x.sr;
+            // every lane of the range writes the same values (no other wave reads them)
+            RangeLds &rl = rng(qi, u);
             // e_r = Sr - n round(Sr / n): the centring error of the range
-            er[qi][u] = (int)x.sr - (((int)x.sr + n / 2) >> lgn << lgn);
-            cr[qi][u] = x.cr;
+            rl.er = (int)x.sr - (((int)x.sr + n / 2) >> lgn << lgn);
+            rl.cr = x.cr;
             tn[qi][u] = r >= 0 ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
-            tb[qi][u] = INT64_MAX;
+            rl.tb = INT64_MAX;
             // start from the best other walks of this range have shared (a
             // stale copy only loosens the test)
             if (r >= 0 && x.gbest < INT64_MAX) {
-                tb[qi][u] = x.gbest;
+                rl.tb = x.gbest;
                 tn[qi][u] = tn_shared(x.gbest, x.cr, sc, tfac);
             }
             best[qi][u] = INT64_MAX;
@@ -366,7 +374,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
             bk[qi][u] = 0;
             // |sum a_i (w~_i - w_i)| <= 2^-10 |a| |w| with a = r - m_r and |w| = 2^16/sqrt(n):
             // |a|^2 = Cr/n + n (mean - m_r)^2 <= Cr/n + n/4 (rounded up here)
-            marg[qi][u] = NORM ? 64.0f * sqrtf((float)x.cr / (float)n + 0.25f * (float)n + 1.0f) * (1.0f + 1.0f / 1024.0f) /
+            rl.marg = NORM ? 64.0f * sqrtf((float)x.cr / (float)n + 0.25f * (float)n + 1.0f) * (1.0f + 1.0f / 1024.0f) /
                                      sqrtf((float)n)
                                : 0.f;
         }
@@ -563,23 +571,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                     if constexpr (CEN) {
                                         // e_d = Sd4 - n round(Sd4 / n), n a power of two
                                         const int ed = (int)sd4 - (((int)sd4 + n / 2) >> lgn << lgn);
-                                        imp = confirm_bx((int64_t)n * (int64_t)mx[qi][u] - (int64_t)er[qi][u] * ed, p, Ad,
-                                                         cr[qi][u], sl, sc, best[qi][u], bp[qi][u], bk[qi][u]);
+                                        imp = confirm_bx((int64_t)n * (int64_t)mx[qi][u] - (int64_t)rng(qi, u).er * ed, p, Ad,
+                                                         rng(qi, u).cr, sl, sc, best[qi][u], bp[qi][u], bk[qi][u]);
                                     } else {
-                                        imp = confirm_pair((int)mx[qi][u], p, sd4, pa[p], sr[qi][u], cr[qi][u], n, sl,
+                                        imp = confirm_pair((int)mx[qi][u], p, sd4, pa[p], sr[qi][u], rng(qi, u).cr, n, sl,
                                                            sc, best[qi][u], bp[qi][u], bk[qi][u]);
                                     }
                                 }
                                 // only a lane best that tightens the shared one is worth sharing
                                 // (or a walk's own 0, which ends the walk for the range)
-                                imp = imp && (best[qi][u] < tb[qi][u] || best[qi][u] == 0);
+                                imp = imp && (best[qi][u] < rng(qi, u).tb || best[qi][u] == 0);
                                 if (__builtin_amdgcn_ballot_w64(imp)) {
                                     // the 32 lanes holding this range share their best: a
                                     // pair is only rejected when it cannot even tie it
                                     const int64_t gb = group_min_val_wave<32>(best[qi][u]);
-                                    if (rr[qi][u] >= 0 && gb <= tb[qi][u]) {
-                                        tb[qi][u] = gb;
-                                        tn[qi][u] = tn_from(gb, cr[qi][u], sc, tfac);
+                                    if (rr[qi][u] >= 0 && gb <= rng(qi, u).tb) {
+                                        rng(qi, u).tb = gb;
+                                        tn[qi][u] = tn_from(gb, rng(qi, u).cr, sc, tfac);
                                         if (SHARE && (lane & 31) == 0) gbest_push(&ri[rr[qi][u]].gbest, gb);
                                     }
                                     if constexpr (NORM) build_cth(qi);   // uniform: inside a ballot
@@ -666,9 +674,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 bool changed = false;
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
-                    if (gl[qi][u] < tb[qi][u]) {
-                        tb[qi][u] = gl[qi][u];
-                        tn[qi][u] = tn_shared(gl[qi][u], cr[qi][u], sc, tfac);
+                    if (gl[qi][u] < rng(qi, u).tb) {
+                        rng(qi, u).tb = gl[qi][u];
+                        tn[qi][u] = tn_shared(gl[qi][u], rng(qi, u).cr, sc, tfac);
                         changed = true;
                     }
                 if (NORM && __builtin_amdgcn_ballot_w64(changed)) build_cth(qi);
