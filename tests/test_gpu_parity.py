@@ -121,6 +121,9 @@ CASES = [
     ("b16_single_level", 7, 96, 96, 5, [(16, 2)], (3, 10), 0, K16, 16, (8, 1)),
     ("pct0_full_pool", 8, 64, 64, 5, [(8, 2), (4, 2)], (0, 1), 0, K16, 16, (5, 1)),
     ("odd_s_set", 9, 64, 64, 5, [(8, 4), (4, 4)], (3, 10), 0, (0, 3, 7, 10), 10, (7, 2)),
+    # clustered contrasts: the search's start, taken from the line through the
+    # end values, lands several steps from the chosen index
+    ("clustered_s_set", 16, 96, 64, 8, [(8, 2), (4, 2)], (1, 10), 0, (0, 1, 2, 3, 4, 12, 14, 15, 16), 16, (6, 1)),
     ("b32_to_b16", 10, 128, 128, 10, [(32, 4), (16, 4)], (1, 2), 0, K16, 16, (8, 1)),
     # B = 32 over ~200 domain tiles with a ragged last tile, 3 range groups
     ("b32_multi_tile", 13, 256, 192, 12, [(32, 2), (16, 2)], (1, 2), 0, K16, 16, (8, 1)),
