@@ -87,7 +87,7 @@ static const Shape kShapes[] = {
     {4, 1, 2, 16, 3}, {4, 1, 1, 16, 3}, {4, 1, 4, 16, 2},
     {8, 2, 2, 8, 3}, {8, 2, 2, 16, 2}, {8, 2, 1, 8, 4}, {8, 2, 3, 8, 2}, {8, 2, 4, 8, 2}, {8, 1, 2, 8, 2},
     {16, 2, 2, 1, 3}, {16, 2, 2, 1, 2}, {16, 2, 1, 2, 3}, {16, 2, 2, 2, 2}, {16, 2, 1, 1, 4}, {16, 1, 1, 1, 2},
-    {8, 3, 2, 8, 3}, {8, 3, 1, 8, 4}, {8, 3, 2, 16, 2}, {8, 3, 3, 8, 2}, {8, 3, 4, 8, 2},
+    {8, 3, 2, 12, 3}, {8, 3, 2, 8, 3}, {8, 3, 1, 8, 4}, {8, 3, 2, 16, 2}, {8, 3, 3, 8, 2}, {8, 3, 4, 8, 2},
     {16, 3, 1, 2, 3}, {16, 3, 2, 1, 2}, {16, 3, 1, 1, 4}, {16, 3, 2, 2, 2},
     {32, 2, 1, 1, 2}, {32, 2, 2, 1, 1}, {32, 2, 1, 2, 1},
     {4, 4, 2, 8, 3}, {4, 4, 2, 16, 3}, {4, 4, 1, 8, 4}, {4, 4, 2, 8, 4}, {4, 4, 3, 8, 3}, {4, 4, 4, 8, 2},
@@ -428,6 +428,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     __shared__ float sa0[NDL], sa1[NDL], sd0[NDL], sd1[NDL];   // sqrt(A) rounded down, Sd4
     __shared__ SLds sl;
     __shared__ int s_item;
+    // per range (4 waves x RQ quads x 4 ranges): values only the rare paths
+    // and the stage ends read (Cr, the best value the threshold reflects,
+    // Sr).  The f16 form keeps them in LDS, which frees the registers its
+    // 12-tile stages need; the int8 forms, whose stages are one or two tiles
+    // (a stage end per tile or two), keep them in registers.
+    struct RangeLds { int64_t cr, tb; int sr; };
+    __shared__ RangeLds s_rng[4 * RQ * 4];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_sset(sl, ss);
     const SConst sc = make_sconst(ss);
@@ -463,8 +470,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 
     v4i A[RQ][2][KA];
     float tn[RQ], bn[RQ], an[RQ];
-    int64_t best[RQ], cr[RQ], tb[RQ];  // tb: the best value tn reflects
-    int bp[RQ], bk[RQ], rr[RQ], sr[RQ];
+    int64_t best[RQ];
+    int bp[RQ], bk[RQ], rr[RQ];
+    RangeLds rreg[RQ];
+    const auto rng = [&](int qi) -> RangeLds & {
+        if constexpr (PL == 3) return s_rng[(wave * RQ + qi) * 4 + g];
+        else return rreg[qi];
+    };
 #pragma unroll
     for (int qi = 0; qi < RQ; ++qi) {
 #pragma unroll
@@ -477,14 +489,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         const RInfo x = ri[r >= 0 ? r : 0];
         bn[qi] = x.bn;
         an[qi] = x.an;
-        sr[qi] = (int)x.sr;
-        cr[qi] = x.cr;
+        // every lane of the range writes the same values (no other wave reads them)
+        RangeLds &rl = rng(qi);
+        rl.sr = (int)x.sr;
+        rl.cr = x.cr;
         tn[qi] = r >= 0 ? -1e30f : __builtin_nanf("");  // NaN: the row never passes
-        tb[qi] = INT64_MAX;
+        rl.tb = INT64_MAX;
         // start from the best other walks of this range have shared (a stale
         // copy only loosens the test)
         if (r >= 0 && x.gbest < INT64_MAX) {
-            tb[qi] = x.gbest;
+            rl.tb = x.gbest;
             tn[qi] = tn_shared(x.gbest, x.cr, sc, tfac);
         }
         best[qi] = INT64_MAX;
@@ -751,24 +765,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                             const v4f x1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(a1), as_h8(bt1), v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
                             if (pass[qi]) {
                                 const float c1 = max8f(x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w);
-                                const int64_t er = (int64_t)sr[qi] - (int64_t)n * round_mean(sr[qi], n);
-                                imp = confirm_bx((int64_t)n * (int64_t)c1 - er * ed, p, Ad, cr[qi], sl, sc, best[qi],
+                                const int64_t er = (int64_t)rng(qi).sr - (int64_t)n * round_mean(rng(qi).sr, n);
+                                imp = confirm_bx((int64_t)n * (int64_t)c1 - er * ed, p, Ad, rng(qi).cr, sl, sc, best[qi],
                                                  bp[qi], bk[qi]);
                             }
                         } else if (pass[qi]) {
-                            imp = confirm_pair((int)mx[qi], p, sd4, Ad, sr[qi], cr[qi], n, sl, sc, best[qi], bp[qi], bk[qi]);
+                            imp = confirm_pair((int)mx[qi], p, sd4, Ad, rng(qi).sr, rng(qi).cr, n, sl, sc, best[qi], bp[qi], bk[qi]);
                         }
                         // only a lane best that tightens the shared one is worth sharing
                         // (or a walk's own 0, which ends the walk for the range)
-                        imp = imp && (best[qi] < tb[qi] || best[qi] == 0);
+                        imp = imp && (best[qi] < rng(qi).tb || best[qi] == 0);
                         if (__builtin_amdgcn_ballot_w64(imp)) {
                             // the 16 lanes holding this range share their best: the
                             // threshold may use it because a pair is only rejected
                             // when it cannot even tie it
                             const int64_t gb = group_min_val_wave<16>(best[qi]);
-                            if (rr[qi] >= 0 && gb <= tb[qi]) {
-                                tb[qi] = gb;
-                                tn[qi] = tn_from(gb, cr[qi], sc, tfac);
+                            if (rr[qi] >= 0 && gb <= rng(qi).tb) {
+                                rng(qi).tb = gb;
+                                tn[qi] = tn_from(gb, rng(qi).cr, sc, tfac);
                                 if (SHARE && (lane & 15) == 0) gbest_push(&ri[rr[qi]].gbest, gb);
                             }
                             if constexpr (FT) build_thr(qi);   // uniform: inside a ballot
@@ -779,10 +793,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         }
 #pragma unroll
         for (int qi = 0; qi < RQ; ++qi) {
-            const bool changed = gl[qi] < tb[qi];
+            const bool changed = gl[qi] < rng(qi).tb;
             if (changed) {
-                tb[qi] = gl[qi];
-                tn[qi] = tn_shared(gl[qi], cr[qi], sc, tfac);
+                rng(qi).tb = gl[qi];
+                tn[qi] = tn_shared(gl[qi], rng(qi).cr, sc, tfac);
             }
             if (FT && __builtin_amdgcn_ballot_w64(changed)) build_thr(qi);
         }
@@ -860,6 +874,7 @@ hipError_t launch_mfma_search_b(const BatchHost &b, hipStream_t st) {
         FIC_SEARCH(1, 2, 4, 8, 2);
         FIC_SEARCH(4, 1, 2, 8, 2);
         FIC_SEARCH(2, 3, 2, 8, 3);
+        FIC_SEARCH(2, 3, 2, 12, 3);
         FIC_SEARCH(2, 3, 1, 8, 4);
         FIC_SEARCH(2, 3, 2, 16, 2);
         FIC_SEARCH(2, 3, 3, 8, 2);

@@ -130,7 +130,7 @@ def test_ctx_create_reports_missing_device():
 def test_shape_queries_are_host_only():
     assert fic.shape_count(fic.FORM_I8, 16) == 6 and fic.shape_count(fic.FORM_F16, 32) == 0
     assert fic.shape_count(fic.FORM_I8, 12) == 0 and fic.lib().fic_shape_count(7, 8) == 0
-    assert fic.shape_describe(fic.FORM_F16_16X16, 8, 0) == (3, 2, 8, 3)
+    assert fic.shape_describe(fic.FORM_F16_16X16, 8, 0) == (3, 2, 12, 3)
     with pytest.raises(fic.FicError):
         fic.shape_describe(fic.FORM_I8, 8, 99)
     assert fic.lib().fic_ctx_set_tuning(None, None) == fic.FIC_E_INVALID

@@ -132,7 +132,7 @@ def test_shape_candidates_listed(runs):
     # every matrix form has compiled shapes for its block sizes, the default first
     assert [len(c["0,%d" % B]) for B in (2, 4, 8, 16, 32)][1:] == [3, 6, 6, 3]
     assert len(c["0,2"]) == 0 and len(c["1,32"]) == 0 and len(c["2,32"]) == 0
-    assert c["0,16"][0] == [2, 2, 1, 3] and c["0,32"][0] == [2, 1, 1, 2] and c["1,8"][0] == [3, 2, 8, 3]
+    assert c["0,16"][0] == [2, 2, 1, 3] and c["0,32"][0] == [2, 1, 1, 2] and c["1,8"][0] == [3, 2, 12, 3]
     assert c["2,4"][0] == [0, 1, 16, 4] and all(s[0] == 4 for s in c["1,4"])
     for k, v in c.items():
         assert len({tuple(s) for s in v}) == len(v), k   # no duplicates
