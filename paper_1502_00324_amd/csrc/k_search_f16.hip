@@ -332,16 +332,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // 2^-20) (the 2^-20 covers the float roundings of c and of the sum) it
     // passes only if acc' > 0.  No best yet: c = 1e30, every pair passes; a
     // row without a range, or a range whose walk found val 0: -inf, none.
+    // (one range's half of the accumulator input: values 8u .. 8u + 7)
+    auto build_cth_half = [&](int qi, int u) {
+        const float t = tn[qi][u];
+        const float c = (rr[qi][u] < 0 || __builtin_isnan(t)) ? -__builtin_inff()
+                      : t < -1e29f ? 1e30f
+                                   : rng(qi, u).marg - 65536.0f * t * (1.0f - 1.0f / 1048576.0f);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cth[NORM ? qi : 0][8 * u + e] = c;
+    };
     auto build_cth = [&](int qi) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const float t = tn[qi][u];
-            const float c = (rr[qi][u] < 0 || __builtin_isnan(t)) ? -__builtin_inff()
-                          : t < -1e29f ? 1e30f
-                                       : rng(qi, u).marg - 65536.0f * t * (1.0f - 1.0f / 1048576.0f);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) cth[NORM ? qi : 0][8 * u + e] = c;
-        }
+        build_cth_half(qi, 0);
+        build_cth_half(qi, 1);
     };
 #pragma unroll
     for (int qi = 0; qi < RQ; ++qi) {
@@ -590,7 +592,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                                         tn[qi][u] = tn_from(gb, rng(qi, u).cr, sc, tfac);
                                         if (SHARE && (lane & 31) == 0) gbest_push(&ri[rr[qi][u]].gbest, gb);
                                     }
-                                    if constexpr (NORM) build_cth(qi);   // uniform: inside a ballot
+                                    if constexpr (NORM) build_cth_half(qi, u);   // uniform: inside a ballot
                                 }
                             }
                     };
