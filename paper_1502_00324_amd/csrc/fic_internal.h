@@ -289,11 +289,15 @@ __device__ inline int search_items(const ImgLvl &d, int x) {
 // Range group, chunk walk and partial-result slot of item k of XCD x's queue
 // within image d (R ranges in its search list).
 __device__ inline void item_walk(const MfmaGeom &g, int R, int x, int k, int &rg, int &cfirst, int &cstep, int &ncs,
-                                 int &slot) {
+                                 int &slot, bool rotate = false) {
     const int nrg = (R + g.rpw - 1) / g.rpw;
     if (g.xcd) {   // XCD x owns chunks x, x + 8, ...: groups of G of them
         const int grp = k / nrg;
-        rg = k - grp * nrg;
+        // rotate: each XCD starts its pass over the range groups at a
+        // different eighth, so the first walks of a group do not all start
+        // at once without a shared best (the chunks an XCD reads stay the
+        // same; measured faster at B = 4, slower at B = 8)
+        rg = (k - grp * nrg + (rotate ? (int)((long long)x * nrg / 8) : 0)) % nrg;
         cfirst = x + 8 * grp * g.G;
         cstep = 8;
         ncs = g.G;

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // R: the length of the search list (constant ranges are coded already)
     const int R = uniform(min(*dsc.ns, range_cap)), P = uniform(min(*dsc.pcount, pool_cap));
     int rg, cfirst, cstep, ncs, slot;
-    item_walk(geo, R, xcd, k, rg, cfirst, cstep, ncs, slot);
+    item_walk(geo, R, xcd, k, rg, cfirst, cstep, ncs, slot, true);
     const gptr<int32_t> sidx = as_global((const int32_t *)uniform(dsc.sidx));
     const int ntiles = (P + kDomTile32 - 1) / kDomTile32;
     const int q0 = (rg * 4 + wave) * RQ;
