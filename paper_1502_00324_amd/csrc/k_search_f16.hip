@@ -494,7 +494,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 const int tbase = t0 + stg * DT;
                 f16x acc[2][RQ];
                 h8 bq[NSET][KG];
-                float mt[G][RQ];   // normalised form: the tile maxima of the current group
+                float gmx[RQ];   // normalised form: the running maximum of the current group
                 // the per-domain values are read two tiles ahead of their test
                 // (a ring of two), so the test never waits for LDS
                 float sqv[2] = {0.f, 0.f}, sdv[2];
@@ -599,38 +599,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
                     if constexpr (NORM) {
                         // the threshold is in the accumulators: the largest of the
                         // lane's 16 values (both ranges, 8 isometries) against 0, one
-                        // branch per group of G tiles (false on NaN: a column past the
-                        // pool)
+                        // branch per group of G tiles.  The group's running maximum
+                        // rides in the spare input of the tile's maximum tree (no extra
+                        // instruction); the maximum propagates NaN (a column past the
+                        // pool), so a NaN group maximum is treated as a possible pass
+                        // and the rare path below tests the group's tiles one by one.
 #pragma unroll
                         for (int qi = 0; qi < RQ; ++qi) {
                             const f16x &a = acc[cur][qi];
-                            mt[dt % G][qi] = FIC_MAX3(FIC_MAX3(max8f(a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7]),
-                                                               a[8], a[9]),
-                                                      FIC_MAX3(a[10], a[11], a[12]), FIC_MAX3(a[13], a[14], a[15]));
+                            const float prev = dt % G == 0 ? a[7] : gmx[qi];
+                            gmx[qi] = FIC_MAX3(FIC_MAX3(max9f(a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], prev),
+                                                        a[8], a[9]),
+                                               FIC_MAX3(a[10], a[11], a[12]), FIC_MAX3(a[13], a[14], a[15]));
                         }
                         if (dt % G == G - 1 || dt == DT - 1) {
                             const int g0 = dt - dt % G;
                             bool any = false;
 #pragma unroll
-                            for (int qi = 0; qi < RQ; ++qi) {
-                                // fmaxf drops NaN: a tile past the pool must not hide the others
-                                float gm = mt[0][qi];
-#pragma unroll
-                                for (int j = 1; j <= dt - g0; ++j) gm = fmaxf(gm, mt[j][qi]);
-                                any |= gm > 0.f;
-                            }
+                            for (int qi = 0; qi < RQ; ++qi) any |= !(gmx[qi] <= 0.f);
                             if (__builtin_expect(__builtin_amdgcn_ballot_w64(any) != 0, 0)) {  // rare
-                                // the passing tiles of the group in order, one at a time
-                                // (a loop, not unrolled: one copy of the evaluation)
+                                // which tiles of the group pass, each tested alone (its
+                                // fragment is still in the stage; a tile past the pool gives
+                                // NaN, which fails), with the threshold as it is now (at most
+                                // tighter than when the group ran: a valid test); then the
+                                // passing tiles in order, one at a time (a loop, not
+                                // unrolled: one copy of the evaluation)
                                 uint32_t pl[RQ], gmask = 0;
 #pragma unroll
                                 for (int qi = 0; qi < RQ; ++qi) pl[qi] = 0;
 #pragma unroll
                                 for (int j = 0; j <= dt - g0; ++j) {
+                                    h8 fj;
+                                    {
+                                        const uint4 u = Bs[(g0 + j) * KS * 64 + lane];
+                                        __builtin_memcpy(&fj, &u, sizeof(h8));
+                                    }
                                     bool anyj = false;
 #pragma unroll
                                     for (int qi = 0; qi < RQ; ++qi) {
-                                        const bool b = mt[j][qi] > 0.f;
+                                        const f16x e = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[qi][0], fj, cth[qi], 0, 0, 0);
+                                        const float m = FIC_MAX3(FIC_MAX3(max8f(e[0], e[1], e[2], e[3], e[4], e[5], e[6], e[7]),
+                                                                          e[8], e[9]),
+                                                                 FIC_MAX3(e[10], e[11], e[12]), FIC_MAX3(e[13], e[14], e[15]));
+                                        const bool b = m > 0.f;
                                         pl[qi] |= b ? 1u << j : 0u;
                                         anyj |= b;
                                     }

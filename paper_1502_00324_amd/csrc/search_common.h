@@ -81,6 +81,14 @@ __device__ __forceinline__ float max8f(float a0, float a1, float a2, float a3, f
 #undef FIC_MAX2
 }
 
+// The maximum of 8 floats and a ninth (the spare input of the 2-input step
+// above): still four v_maximum3_f32.
+__device__ __forceinline__ float max9f(float a0, float a1, float a2, float a3, float b0, float b1, float b2,
+                                       float b3, float c) {
+    const float m1 = FIC_MAX3(a0, a1, a2), m2 = FIC_MAX3(a3, b0, b1);
+    return FIC_MAX3(m1, m2, FIC_MAX3(b2, b3, c));
+}
+
 __device__ inline float sqrt_down(double v) {
     const double s = sqrt(v);
     float f = (float)s;
